@@ -1,0 +1,182 @@
+"""Seeded synthetic scenes shaped like the paper's endoscopic workloads.
+
+This module only draws random inputs; it holds none of the rasterizer's
+arithmetic, so both the HIP path and the FP64 oracle can take their inputs
+from it.  The activations that the paper leaves to the optimiser (scales are
+stored in log space, opacities as logits) are applied here, because the
+rasterizer consumes linear scales and opacities in (0, 1).
+
+Five workloads are defined (sizes follow the paper: 640x512 frames (Sec. 4.1,
+EndoVis18), 128 semantic channels (Sec. 3.3), 30k-90k initial points and
+about 1e5 Gaussians in a trained scene (hyper-parameter table)):
+
+* ``small``   128x128, 2,000 Gaussians, SH degree 0, D=8, forward only.
+* ``mid``     640x512, 100k Gaussians, SH degree 3, D=32, forward+backward.
+* ``metric``  640x512, 300k Gaussians drawn like ``small``, SH degree 3,
+              D=128, stored FP32 or BF16.
+* ``batched`` 16 timestamps of one deforming scene (eq. 6 stand-in), pool of
+              200k Gaussians, 50k-200k visible per frame, D=64 BF16.
+* ``large``   1280x1024, 1M Gaussians, SH degree 3, D=128 BF16.
+
+All draws use ``numpy.random.default_rng(seed)`` in float64 in a fixed order
+(means, log-scales, quaternions, opacity logits, SH DC, SH rest, features,
+upstream gradients) and are then cast to float32.  N(a, b) means mean a and
+standard deviation b.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import numpy as np
+
+__all__ = [
+    "Camera", "Scene", "make_scene", "crop_camera", "bf16_round",
+    "WORKLOADS", "batched_frames",
+]
+
+
+@dataclass
+class Camera:
+    """Pinhole camera; pixel (i, j) samples the point (i + 0.5, j + 0.5)."""
+    width: int
+    height: int
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    # row-major 3x4 world-to-camera [R | t]; identity pose for every workload
+    world_to_cam: np.ndarray = field(
+        default_factory=lambda: np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 0]], dtype=np.float32))
+    near: float = 0.2
+
+
+@dataclass
+class Scene:
+    name: str
+    cam: Camera
+    means: np.ndarray      # [N,3] f32
+    scales: np.ndarray     # [N,3] f32, linear
+    quats: np.ndarray      # [N,4] f32, (w,x,y,z), unnormalised
+    opacity: np.ndarray    # [N]   f32 in (0,1)
+    sh: np.ndarray         # [N,(L+1)^2,3] f32
+    feat: np.ndarray       # [N,D] f32
+    sh_degree: int
+    d_rgb: np.ndarray | None = None    # [3,H,W] f32 upstream gradient
+    d_feat: np.ndarray | None = None   # [D,H,W] f32 upstream gradient
+    tile: tuple[int, int] = (16, 16)
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[0])
+
+    @property
+    def feat_dim(self) -> int:
+        return int(self.feat.shape[1])
+
+
+def bf16_round(x: np.ndarray) -> np.ndarray:
+    """Round float32 values to bfloat16 (round to nearest, ties to even) and
+    return them widened back to float32.  NaN stays NaN."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    u = x.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    r = ((u + 0x7FFF + lsb) >> 16) << 16
+    out = (r & 0xFFFFFFFF).astype(np.uint32).view(np.float32)
+    nan = np.isnan(x)
+    if nan.any():
+        out = out.copy()
+        out[nan] = np.nan
+    return out
+
+
+def _sigmoid(x):
+    return 1.0 / (1.0 + np.exp(-x))
+
+
+def _draw(rng, n, xy, zr, logs, sh_degree, feat_dim, dc=(0.5, 0.2), rest_std=0.05):
+    means = np.empty((n, 3))
+    means[:, 0] = rng.uniform(-xy, xy, n)
+    means[:, 1] = rng.uniform(-xy, xy, n)
+    means[:, 2] = rng.uniform(zr[0], zr[1], n)
+    log_s = rng.normal(logs[0], logs[1], (n, 3))
+    q = rng.normal(0.0, 1.0, (n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    op_logit = rng.normal(0.0, 1.0, n)
+    k = (sh_degree + 1) ** 2
+    sh = np.zeros((n, k, 3))
+    sh[:, 0, :] = rng.normal(dc[0], dc[1], (n, 3))
+    if k > 1:
+        sh[:, 1:, :] = rng.normal(0.0, rest_std, (n, k - 1, 3))
+    feat = rng.normal(0.0, 1.0, (n, feat_dim))
+    return dict(means=means.astype(np.float32), scales=np.exp(log_s).astype(np.float32),
+                quats=q.astype(np.float32), opacity=_sigmoid(op_logit).astype(np.float32),
+                sh=sh.astype(np.float32), feat=feat.astype(np.float32))
+
+
+# name -> (width, height, f, n, xy-range, z-range, log-scale N(mu,sd), sh degree, D, backward?)
+WORKLOADS = {
+    "small":   dict(w=128, h=128, f=102.4, n=2000, xy=1.0, z=(2.0, 6.0), logs=(-3.5, 0.4), sh=0, d=8, grads=False),
+    "mid":     dict(w=640, h=512, f=512.0, n=100_000, xy=1.5, z=(1.0, 8.0), logs=(-4.0, 0.5), sh=3, d=32, grads=True),
+    "metric":  dict(w=640, h=512, f=512.0, n=300_000, xy=1.0, z=(2.0, 6.0), logs=(-3.5, 0.4), sh=3, d=128, grads=True),
+    "batched": dict(w=640, h=512, f=512.0, n=200_000, xy=1.5, z=(1.0, 8.0), logs=(-4.0, 0.5), sh=3, d=64, grads=True),
+    "large":   dict(w=1280, h=1024, f=1024.0, n=1_000_000, xy=2.0, z=(0.5, 10.0), logs=(-4.5, 0.6), sh=3, d=128, grads=True),
+}
+_SEEDS = {"small": 1, "mid": 2, "metric": 3, "batched": 4, "large": 5}
+
+
+def make_camera(width, height, f):
+    return Camera(width=width, height=height, fx=float(f), fy=float(f), cx=width / 2.0, cy=height / 2.0)
+
+
+def make_scene(name: str, seed: int | None = None, n: int | None = None, feat_dim: int | None = None,
+               sh_degree: int | None = None, width: int | None = None, height: int | None = None,
+               f: float | None = None, grads: bool | None = None) -> Scene:
+    """Draw one named workload (overrides allow smaller variants of the same
+    distributions for tests)."""
+    w = dict(WORKLOADS[name])
+    seed = _SEEDS[name] if seed is None else seed
+    n = w["n"] if n is None else n
+    d = w["d"] if feat_dim is None else feat_dim
+    L = w["sh"] if sh_degree is None else sh_degree
+    W = w["w"] if width is None else width
+    H = w["h"] if height is None else height
+    fl = w["f"] if f is None else f
+    want_g = w["grads"] if grads is None else grads
+    rng = np.random.default_rng(seed)
+    arrs = _draw(rng, n, w["xy"], w["z"], w["logs"], L, d)
+    cam = make_camera(W, H, fl)
+    sc = Scene(name=name, cam=cam, sh_degree=L, **arrs)
+    if want_g:
+        sc.d_rgb = rng.normal(0.0, 1e-3, (3, H, W)).astype(np.float32)
+        sc.d_feat = rng.normal(0.0, 1e-3, (d, H, W)).astype(np.float32)
+    return sc
+
+
+def crop_camera(cam: Camera, x0: int, y0: int, w: int, h: int) -> Camera:
+    """Sub-window [x0, x0+w) x [y0, y0+h) of ``cam`` as a camera of its own:
+    same focal length and pose, principal point shifted into the window."""
+    return Camera(width=w, height=h, fx=cam.fx, fy=cam.fy, cx=cam.cx - x0, cy=cam.cy - y0,
+                  world_to_cam=cam.world_to_cam.copy(), near=cam.near)
+
+
+def batched_frames(seed: int = 4, n_frames: int = 16, pool: int = 200_000, base: int = 150_000,
+                   n_min: int = 50_000, n_max: int = 200_000, feat_dim: int = 64, amp: float = 0.02):
+    """Timestamps t_k = k / n_frames of one deforming scene.
+
+    Frame k renders the first N_k Gaussians of a pool (the first ``base`` are
+    the canonical scene), with N_k a seeded permutation of
+    round(linspace(n_min, n_max, n_frames)); every mean is offset by
+    amp * sin(2 pi t_k + phi) per axis with phi ~ U[0, 2 pi) per Gaussian and
+    axis (a synthetic stand-in for the deformation network's output).
+    Returns (pool scene, list of per-frame dicts with means and count)."""
+    sc = make_scene("batched", seed=seed, n=pool, feat_dim=feat_dim)
+    rng = np.random.default_rng(seed + 1000)
+    phase = rng.uniform(0.0, 2 * np.pi, (pool, 3))
+    counts = np.round(np.linspace(n_min, n_max, n_frames)).astype(np.int64)
+    counts = counts[rng.permutation(n_frames)]
+    frames = []
+    for k in range(n_frames):
+        t = k / n_frames
+        nk = int(counts[k])
+        m = sc.means[:nk].astype(np.float64) + amp * np.sin(2 * np.pi * t + phase[:nk])
+        frames.append(dict(t=t, n=nk, means=m.astype(np.float32)))
+    return sc, frames
