@@ -213,7 +213,8 @@ def test_view_dependent_colour_uses_camera_centre():
     g["sh"][:, 2, :] = [0.5, -0.7, 0.9]
     g64 = {k: np.asarray(v, np.float64) for k, v in g.items()}
     p = project(**g64, cam=c, cfg=cfg(sh_degree=1))
-    d = mu - C
+    d = g64["means"] - C
     d /= np.linalg.norm(d, axis=1, keepdims=True)
-    expect = np.maximum(0, math.sqrt(3 / (4 * math.pi)) * d[:, 2:3] * np.array([[0.5, -0.7, 0.9]]) + 0.5)
+    k = g64["sh"][:1, 2, :]
+    expect = np.maximum(0, math.sqrt(3 / (4 * math.pi)) * d[:, 2:3] * k + 0.5)
     np.testing.assert_allclose(p["rgb"].numpy(), expect, rtol=1e-12)
