@@ -1,0 +1,239 @@
+/*
+ * fe4dgs_rast.h -- C ABI of the MI355X (gfx950) tile rasterizer for
+ * feature-distilled 4D Gaussian splatting (FeatureEndo-4DGS).
+ *
+ * What the library computes (the paper's Sec. 3.4, "Differentiable Rendering
+ * and Loss Functions", and Sec. 3.1):
+ *   - each deformed Gaussian G_t (eq. 6) is projected: Sigma = R S S^T R^T
+ *     (eq. 2) and Sigma' = J W Sigma W^T J^T (eq. 9), plus a 0.3 px^2
+ *     dilation of the diagonal;
+ *   - it is binned into screen tiles by its 3-sigma pixel box, and every
+ *     tile's list is ordered front to back (by view-space depth, ties by
+ *     Gaussian index);
+ *   - every pixel blends colour and the D semantic channels front to back with
+ *     the same weights alpha_i prod_{j<i}(1 - alpha_j) (eqs. 7 and 8), where
+ *     alpha_i = min(0.99, o_i exp(-q/2)) (eq. 1 in 2-D), q = d^T Sigma'^-1 d,
+ *     Gaussians with q > 9 or outside their box are ignored, alpha < 1/255 is
+ *     skipped, and a pixel stops before the Gaussian that would take its
+ *     transmittance below 1e-4;
+ *   - the backward pass returns the derivative of that forward with respect to
+ *     every Gaussian parameter (the paper trains them all with Adam).
+ *
+ * Conventions
+ *   - pixel (i, j) samples (i + 0.5, j + 0.5); u = fx (tx / tz) + cx.
+ *   - world_to_cam is a row-major 3x4 [R | t]; camera looks along +z.
+ *   - quaternions are (w, x, y, z), any non-zero norm (normalised inside).
+ *   - scales are linear (already exponentiated); opacity is in (0, 1).
+ *   - SH: real orthonormal basis without the Condon-Shortley phase, degree
+ *     0..3, coefficient index l^2 + l + m, layout [n][(L+1)^2][3];
+ *     colour = max(0, sum_k sh_k Y_k(dir) + 0.5), dir = normalise(mu - campos).
+ *   - images are planar float32: rgb [3][H][W], feat [D][H][W],
+ *     final_T [H][W], n_contrib [H][W] (1 + list position of the last
+ *     blended Gaussian in the pixel's tile list).
+ *   - BF16 storage is accepted for sh and feat only (round-to-nearest-even
+ *     bfloat16, passed as uint16 bit patterns); all arithmetic and every
+ *     gradient are float32 (projection geometry in float64).
+ *
+ * Ownership and asynchrony
+ *   - every pointer in the structs below is DEVICE memory owned by the caller;
+ *     the library never allocates device memory in these calls and keeps no
+ *     global mutable state.  Calls only enqueue work on `stream` (a
+ *     hipStream_t, NULL = default stream) and return; results are ready when
+ *     the stream is.  Distinct state buffers may be used concurrently.
+ *   - argument errors are detected on the host before anything is enqueued
+ *     and returned synchronously; conditions only the device can see (sort
+ *     key overflow, non-finite inputs) are recorded in the state's report and
+ *     read with fe_read_report().  No C++ exception crosses the ABI.
+ */
+#ifndef FE4DGS_RAST_H
+#define FE4DGS_RAST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FE4DGS_ABI_VERSION 1
+
+typedef enum fe_status {
+  FE_OK = 0,
+  FE_ERR_INVALID_ARG = 1,        /* NULL pointer, bad size, bad enum value      */
+  FE_ERR_UNSUPPORTED = 2,        /* feat_dim > 256, sh_degree > 3, W/H > 32767  */
+  FE_ERR_WORKSPACE_TOO_SMALL = 3,/* state / scratch / workspace below *_bytes() */
+  FE_ERR_KEY_OVERFLOW = 4,       /* device: more (tile, Gaussian) keys than
+                                    key_capacity; outputs are invalid and
+                                    report.keys_needed holds the count needed  */
+  FE_ERR_HIP = 5                 /* a HIP runtime call failed                  */
+} fe_status;
+
+typedef enum fe_dtype { FE_F32 = 0, FE_BF16 = 1 } fe_dtype;
+
+/* Pinhole camera (identity pose in every workload of the paper's data). */
+typedef struct fe_camera {
+  int32_t width, height;         /* pixels, 1..32767                           */
+  float fx, fy, cx, cy;          /* focal lengths and principal point, pixels  */
+  float world_to_cam[12];        /* row-major 3x4 [R | t]                       */
+  float near_plane;              /* cull when tz <= near_plane (0.2 typical)   */
+} fe_camera;
+
+/* Rasterizer configuration. */
+typedef struct fe_config {
+  int32_t tile_w, tile_h;        /* tile shape in pixels; tile_w * tile_h must
+                                    be 64, 128 or 256 and tile_w one of
+                                    8, 16, 32                                  */
+  int32_t threads_per_tile;      /* 0 = tile_w * tile_h (one pixel per thread) */
+  int32_t sh_degree;             /* 0..3                                        */
+  int32_t feat_dim;              /* D, 1..256                                   */
+  int32_t sh_dtype, feat_dtype;  /* fe_dtype                                    */
+  float bg_rgb[3];               /* colour background (feature background is 0)*/
+  float cov2d_dilation;          /* added to Sigma'_xx and Sigma'_yy (0.3)      */
+  float jacobian_clamp;          /* J evaluated at tx/tz clamped to
+                                    +-k W / (2 fx) (1.3); 0 disables            */
+  int64_t key_capacity;          /* maximum number of (tile, Gaussian) keys    */
+  uint32_t flags;                /* FE_FLAG_*                                   */
+  int32_t variant;               /* compositing kernel variant (FE_VARIANT_*)  */
+} fe_config;
+
+#define FE_FLAG_NO_ZERO_GRADS 0x1u  /* backward accumulates into *out instead of
+                                       overwriting it                           */
+
+#define FE_VARIANT_AUTO 0           /* library default                          */
+#define FE_VARIANT_VALU 1           /* vector-ALU blending in both directions   */
+
+/* Packed Gaussian arrays (device, SoA, contiguous). */
+typedef struct fe_gaussians {
+  int64_t n;
+  const float* means;            /* [n][3]                                      */
+  const float* scales;           /* [n][3] linear                               */
+  const float* quats;            /* [n][4] (w, x, y, z)                          */
+  const float* opacity;          /* [n]                                          */
+  const void* sh;                /* [n][(L+1)^2][3] float or bf16 bits          */
+  const void* feat;              /* [n][D] float or bf16 bits                   */
+} fe_gaussians;
+
+/* Forward outputs (device). */
+typedef struct fe_images {
+  float* rgb;                    /* [3][H][W]                                   */
+  float* feat;                   /* [D][H][W]                                   */
+  float* final_T;                /* [H][W]                                      */
+  int32_t* n_contrib;            /* [H][W]                                      */
+} fe_images;
+
+/* Backward outputs (device, float32; overwritten unless FE_FLAG_NO_ZERO_GRADS). */
+typedef struct fe_grads {
+  float* means;                  /* [n][3]                                      */
+  float* scales;                 /* [n][3]                                      */
+  float* quats;                  /* [n][4]                                      */
+  float* opacity;                /* [n]                                          */
+  float* sh;                     /* [n][(L+1)^2][3]                              */
+  float* feat;                   /* [n][D]                                      */
+  float* means2d;                /* optional [n][2] dL/d(u, v); may be NULL     */
+} fe_grads;
+
+/* Device-side report, read back with fe_read_report(). */
+typedef struct fe_report {
+  int32_t status;                /* FE_OK or FE_ERR_KEY_OVERFLOW                */
+  int32_t reserved;
+  int64_t keys_needed;           /* number of (tile, Gaussian) keys the frame has */
+  int64_t n_visible;             /* Gaussians that emitted at least one key     */
+  int64_t n_culled_nonfinite;    /* Gaussians culled for non-finite parameters  */
+} fe_report;
+
+/* Byte offsets of the regions of a forward state buffer (for tests and
+ * tools; every offset is 256-byte aligned).  Sorted arrays hold
+ * report.keys_needed valid entries (at most key_capacity). */
+typedef struct fe_state_layout {
+  size_t total;
+  size_t xy;                     /* float2 [n]    pixel position (u, v)         */
+  size_t conic_opacity;          /* float4 [n]    conic (A, B, C), opacity      */
+  size_t rgb;                    /* float4 [n]    colour (r, g, b, 0)           */
+  size_t box;                    /* int16x4 [n]   pixel box (i0, j0, i1, j1)    */
+  size_t depth_key;              /* uint32 [n]    float32 depth bits in ascending
+                                                  order (culled: 0xFFFFFFFF)    */
+  size_t depth_order;            /* uint32 [n]    Gaussian indices in that order
+                                                  (stable: ties by index)       */
+  size_t tile_count;             /* uint32 [n]    tiles touched                 */
+  size_t sorted_tile;            /* uint32 [cap]  tile id of each sorted key    */
+  size_t sorted_gauss;           /* uint32 [cap]  Gaussian index of each key    */
+  size_t ranges;                 /* uint32x2 [tiles] [start, end) per tile      */
+  size_t report;                 /* device report words                         */
+} fe_state_layout;
+
+int         fe_abi_version(void);
+const char* fe_status_string(fe_status s);
+
+/* Validate a configuration and camera (host only, no GPU needed). */
+fe_status fe_validate(const fe_config* cfg, const fe_camera* cam, int64_t n);
+
+/* Size and layout of the forward state for n Gaussians (host only).
+ * Returns 0 (and fills nothing) when the arguments are invalid. */
+size_t    fe_state_bytes(const fe_config* cfg, const fe_camera* cam, int64_t n);
+fe_status fe_state_layout_get(const fe_config* cfg, const fe_camera* cam, int64_t n,
+                              fe_state_layout* out);
+
+/* Scratch needed by fe_render_backward (host only). */
+size_t    fe_backward_scratch_bytes(const fe_config* cfg, const fe_camera* cam, int64_t n);
+
+/* Forward render of one camera.  `state` (device, state_bytes >=
+ * fe_state_bytes) receives the projected record, the sorted key lists and the
+ * report, and must be passed unchanged to fe_render_backward. */
+fe_status fe_render_forward(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
+                            const fe_images* out, void* state, size_t state_bytes, void* stream);
+
+/* Backward of fe_render_forward for upstream gradients d_rgb [3][H][W] and
+ * d_feat [D][H][W] (device float32; none flows into final_T / n_contrib).
+ * `fwd` must be the images that forward wrote (final_T and n_contrib are
+ * read).  `scratch` (device, >= fe_backward_scratch_bytes) holds per-Gaussian
+ * screen-space gradients. */
+fe_status fe_render_backward(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
+                             const fe_images* fwd, const void* state, size_t state_bytes,
+                             const float* d_rgb, const float* d_feat, const fe_grads* out,
+                             void* scratch, size_t scratch_bytes, void* stream);
+
+/* Copy the device report of `state` to the host.  Synchronises `stream`.
+ * Returns report->status as the call's status (FE_ERR_KEY_OVERFLOW when the
+ * frame needed more keys than key_capacity). */
+fe_status fe_read_report(const void* state, size_t state_bytes, fe_report* out, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batched frames (many timestamps / views, uneven Gaussian counts) replayed
+ * as one captured HIP graph.  The plan binds every buffer at creation; the
+ * caller rewrites the Gaussian arrays / upstream gradients in place between
+ * launches.  Frames are independent renders that share nothing but the
+ * stream; per-frame results equal fe_render_forward / fe_render_backward on
+ * that frame alone.
+ * ---------------------------------------------------------------------- */
+typedef struct fe_batch_plan fe_batch_plan;
+
+#define FE_MODE_FORWARD 1
+#define FE_MODE_BACKWARD 2
+#define FE_MODE_FORWARD_BACKWARD 3
+
+/* Workspace for `frames` frames with n[f] Gaussians each (host only). */
+size_t fe_batch_workspace_bytes(const fe_config* cfg, const fe_camera* cams, int32_t frames,
+                                const int64_t* n);
+
+/* Create a plan.  Arrays of length `frames`: cams, g, out, d_rgb, d_feat,
+ * grads (d_rgb / d_feat / grads may be NULL for FE_MODE_FORWARD).  The plan
+ * owns host memory and HIP graph handles only; `workspace` stays the
+ * caller's.  The first fe_batch_launch captures the graph. */
+fe_status fe_batch_plan_create(const fe_config* cfg, const fe_camera* cams, int32_t frames,
+                               const fe_gaussians* g, const fe_images* out,
+                               const float* const* d_rgb, const float* const* d_feat,
+                               const fe_grads* grads, int32_t mode, void* workspace,
+                               size_t workspace_bytes, fe_batch_plan** plan);
+
+/* Enqueue one replay of every frame on `stream` (capturing on first use). */
+fe_status fe_batch_launch(fe_batch_plan* plan, void* stream);
+
+/* Report of frame f (synchronises `stream`). */
+fe_status fe_batch_read_report(fe_batch_plan* plan, int32_t f, fe_report* out, void* stream);
+
+void fe_batch_plan_destroy(fe_batch_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FE4DGS_RAST_H */

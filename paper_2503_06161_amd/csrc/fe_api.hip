@@ -1,0 +1,431 @@
+// C ABI of libfe4dgs_rast.so: argument validation, state layout and the
+// order of kernel launches.  See include/fe4dgs_rast.h for the contract.
+#include "fe_common.h"
+
+#include <new>
+#include <vector>
+
+#pragma clang fp contract(off)
+
+namespace fe {
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+bool compute_layout(const fe_config* cfg, const fe_camera* cam, int64_t n, Layout* L) {
+  if (fe_validate(cfg, cam, n) != FE_OK) return false;
+  L->n = n;
+  L->cap = cfg->key_capacity;
+  L->tiles_x = ceil_div(cam->width, cfg->tile_w);
+  L->tiles_y = ceil_div(cam->height, cfg->tile_h);
+  L->tiles = L->tiles_x * L->tiles_y;
+  L->nchunks_n = ceil_div(n, kSortChunk);
+  L->nchunks_k = ceil_div(L->cap, kSortChunk);
+  L->nscan_blocks = ceil_div(n, kScanChunk);
+  int bits = 0;
+  while ((1ll << bits) < (int64_t)L->tiles) ++bits;
+  L->tile_passes = (bits + kRadixBits - 1) / kRadixBits;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  // zeroed at the start of every forward: report, radix totals, ranges
+  L->report = take(sizeof(unsigned long long) * 2 * kRepWords);
+  L->totals = take(sizeof(uint32_t) * kRadixBins * (4 + L->tile_passes));
+  L->ranges = take(sizeof(uint2) * (size_t)L->tiles);
+  L->xy = take(sizeof(float2) * n);
+  L->conic_o = take(sizeof(float4) * n);
+  L->rgb = take(sizeof(float4) * n);
+  L->box = take(sizeof(short4) * n);
+  L->dkey_a = take(4 * n);
+  L->dkey_b = take(4 * n);
+  L->didx_a = take(4 * n);
+  L->didx_b = take(4 * n);
+  L->count = take(4 * n);
+  L->offsets = take(4 * n);
+  L->scan_sums = take(4 * (size_t)(L->nscan_blocks + 1));
+  L->hist_n = take(4 * (size_t)kRadixBins * L->nchunks_n);
+  L->tile_a = take(4 * (size_t)L->cap);
+  L->gauss_a = take(4 * (size_t)L->cap);
+  L->tile_b = take(4 * (size_t)L->cap);
+  L->gauss_b = take(4 * (size_t)L->cap);
+  L->hist_k = take(4 * (size_t)kRadixBins * L->nchunks_k);
+  L->total = o;
+  return true;
+}
+
+StateView make_view(const Layout& L, void* base) {
+  char* b = static_cast<char*>(base);
+  StateView v;
+  v.xy = reinterpret_cast<float2*>(b + L.xy);
+  v.conic_o = reinterpret_cast<float4*>(b + L.conic_o);
+  v.rgb = reinterpret_cast<float4*>(b + L.rgb);
+  v.box = reinterpret_cast<short4*>(b + L.box);
+  v.dkey_a = reinterpret_cast<uint32_t*>(b + L.dkey_a);
+  v.dkey_b = reinterpret_cast<uint32_t*>(b + L.dkey_b);
+  v.didx_a = reinterpret_cast<uint32_t*>(b + L.didx_a);
+  v.didx_b = reinterpret_cast<uint32_t*>(b + L.didx_b);
+  v.count = reinterpret_cast<uint32_t*>(b + L.count);
+  v.offsets = reinterpret_cast<uint32_t*>(b + L.offsets);
+  v.scan_sums = reinterpret_cast<uint32_t*>(b + L.scan_sums);
+  v.hist_n = reinterpret_cast<uint32_t*>(b + L.hist_n);
+  v.tile_a = reinterpret_cast<uint32_t*>(b + L.tile_a);
+  v.gauss_a = reinterpret_cast<uint32_t*>(b + L.gauss_a);
+  v.tile_b = reinterpret_cast<uint32_t*>(b + L.tile_b);
+  v.gauss_b = reinterpret_cast<uint32_t*>(b + L.gauss_b);
+  v.hist_k = reinterpret_cast<uint32_t*>(b + L.hist_k);
+  v.totals = reinterpret_cast<uint32_t*>(b + L.totals);
+  v.ranges = reinterpret_cast<uint2*>(b + L.ranges);
+  v.report = reinterpret_cast<unsigned long long*>(b + L.report);
+  v.n = L.n;
+  v.cap = L.cap;
+  v.tiles_x = L.tiles_x;
+  v.tiles_y = L.tiles_y;
+  v.tiles = L.tiles;
+  v.nchunks_n = L.nchunks_n;
+  v.nchunks_k = L.nchunks_k;
+  v.nscan_blocks = L.nscan_blocks;
+  v.tile_passes = L.tile_passes;
+  return v;
+}
+
+CamConst make_cam_const(const fe_camera* cam, const fe_config* cfg) {
+  CamConst c;
+  for (int r = 0; r < 3; ++r) {
+    for (int k = 0; k < 3; ++k) c.R[r * 3 + k] = cam->world_to_cam[r * 4 + k];
+    c.t[r] = cam->world_to_cam[r * 4 + 3];
+  }
+  for (int k = 0; k < 3; ++k) c.campos[k] = -((c.R[0 * 3 + k] * c.t[0] + c.R[1 * 3 + k] * c.t[1]) + c.R[2 * 3 + k] * c.t[2]);
+  c.fx = cam->fx;
+  c.fy = cam->fy;
+  c.cx = cam->cx;
+  c.cy = cam->cy;
+  const double k = cfg->jacobian_clamp;
+  if (k > 0.0) {
+    c.limx = (k * (double)cam->width) / (2.0 * c.fx);
+    c.limy = (k * (double)cam->height) / (2.0 * c.fy);
+  } else {
+    c.limx = 0.0;
+    c.limy = 0.0;
+  }
+  c.near_plane = cam->near_plane;
+  c.dilation = cfg->cov2d_dilation;
+  c.width = cam->width;
+  c.height = cam->height;
+  return c;
+}
+
+static fe_status hip_status(hipError_t e) { return e == hipSuccess ? FE_OK : FE_ERR_HIP; }
+
+static fe_status check_gaussians(const fe_config* cfg, const fe_gaussians* g) {
+  if (!g || g->n < 0) return FE_ERR_INVALID_ARG;
+  if (g->n == 0) return FE_OK;
+  if (!g->means || !g->scales || !g->quats || !g->opacity || !g->sh || !g->feat) return FE_ERR_INVALID_ARG;
+  (void)cfg;
+  return FE_OK;
+}
+
+static fe_status forward_impl(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
+                              const fe_images* out, void* state, const Layout& L, hipStream_t s) {
+  StateView v = make_view(L, state);
+  hipError_t e;
+  const size_t zero_words = (L.ranges + sizeof(uint2) * (size_t)L.tiles - L.report) / 4;
+  if ((e = launch_zero_u32(reinterpret_cast<uint32_t*>(v.report), zero_words, s)) != hipSuccess) return FE_ERR_HIP;
+  if ((e = launch_project_fwd(make_cam_const(cam, cfg), cfg, g, v, s)) != hipSuccess) return FE_ERR_HIP;
+  if ((e = launch_sort_and_bin(cfg, v, s)) != hipSuccess) return FE_ERR_HIP;
+  return hip_status(launch_composite_fwd(cfg, cam, g, v, out, s));
+}
+
+static fe_status backward_impl(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
+                               const fe_images* fwd, const void* state, const Layout& L, const float* d_rgb,
+                               const float* d_feat, const fe_grads* out, void* scratch, hipStream_t s) {
+  StateView v = make_view(L, const_cast<void*>(state));
+  float* grad2d = static_cast<float*>(scratch);
+  hipError_t e;
+  if ((e = launch_zero_u32(reinterpret_cast<uint32_t*>(grad2d), (size_t)12 * g->n, s)) != hipSuccess) return FE_ERR_HIP;
+  if (!(cfg->flags & FE_FLAG_NO_ZERO_GRADS)) {
+    if ((e = launch_zero_u32(reinterpret_cast<uint32_t*>(out->feat), (size_t)cfg->feat_dim * g->n, s)) != hipSuccess)
+      return FE_ERR_HIP;
+  }
+  if ((e = launch_composite_bwd(cfg, cam, g, v, fwd, d_rgb, d_feat, grad2d, out->feat, s)) != hipSuccess)
+    return FE_ERR_HIP;
+  return hip_status(launch_project_bwd(make_cam_const(cam, cfg), cfg, g, v, grad2d, out, s));
+}
+
+}  // namespace fe
+
+using namespace fe;
+
+extern "C" {
+
+int fe_abi_version(void) { return FE4DGS_ABI_VERSION; }
+
+const char* fe_status_string(fe_status s) {
+  switch (s) {
+    case FE_OK: return "ok";
+    case FE_ERR_INVALID_ARG: return "invalid argument";
+    case FE_ERR_UNSUPPORTED: return "unsupported configuration";
+    case FE_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case FE_ERR_KEY_OVERFLOW: return "sort key capacity exceeded";
+    case FE_ERR_HIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+fe_status fe_validate(const fe_config* cfg, const fe_camera* cam, int64_t n) {
+  if (!cfg || !cam || n < 0) return FE_ERR_INVALID_ARG;
+  if (cam->width < 1 || cam->height < 1) return FE_ERR_INVALID_ARG;
+  if (cam->width > 32767 || cam->height > 32767) return FE_ERR_UNSUPPORTED;
+  if (!(cam->fx > 0.f) || !(cam->fy > 0.f)) return FE_ERR_INVALID_ARG;
+  const int tw = cfg->tile_w, th = cfg->tile_h;
+  if (!(tw == 8 || tw == 16 || tw == 32)) return FE_ERR_UNSUPPORTED;
+  const int nt = tw * th;
+  if (th < 1 || (nt != 64 && nt != 128 && nt != 256)) return FE_ERR_UNSUPPORTED;
+  if (cfg->threads_per_tile != 0 && cfg->threads_per_tile != nt) return FE_ERR_UNSUPPORTED;
+  if (cfg->sh_degree < 0) return FE_ERR_INVALID_ARG;
+  if (cfg->sh_degree > 3) return FE_ERR_UNSUPPORTED;
+  if (cfg->feat_dim < 1) return FE_ERR_INVALID_ARG;
+  if (cfg->feat_dim > 256) return FE_ERR_UNSUPPORTED;
+  if ((cfg->sh_dtype != FE_F32 && cfg->sh_dtype != FE_BF16) ||
+      (cfg->feat_dtype != FE_F32 && cfg->feat_dtype != FE_BF16))
+    return FE_ERR_INVALID_ARG;
+  if (cfg->key_capacity < 0 || cfg->key_capacity > 0x7FFFFFFFll) return FE_ERR_INVALID_ARG;
+  if (n > (int64_t)kScanChunk * kScanTopMax) return FE_ERR_UNSUPPORTED;
+  if (cfg->variant != FE_VARIANT_AUTO && cfg->variant != FE_VARIANT_VALU) return FE_ERR_UNSUPPORTED;
+  return FE_OK;
+}
+
+size_t fe_state_bytes(const fe_config* cfg, const fe_camera* cam, int64_t n) {
+  Layout L;
+  if (!compute_layout(cfg, cam, n, &L)) return 0;
+  return L.total;
+}
+
+fe_status fe_state_layout_get(const fe_config* cfg, const fe_camera* cam, int64_t n, fe_state_layout* out) {
+  if (!out) return FE_ERR_INVALID_ARG;
+  const fe_status st = fe_validate(cfg, cam, n);
+  if (st != FE_OK) return st;
+  Layout L;
+  compute_layout(cfg, cam, n, &L);
+  out->total = L.total;
+  out->xy = L.xy;
+  out->conic_opacity = L.conic_o;
+  out->rgb = L.rgb;
+  out->box = L.box;
+  out->depth_key = L.dkey_a;
+  out->depth_order = L.didx_a;
+  out->tile_count = L.count;
+  out->sorted_tile = L.tile_a;
+  out->sorted_gauss = L.gauss_a;
+  out->ranges = L.ranges;
+  out->report = L.report;
+  return FE_OK;
+}
+
+size_t fe_backward_scratch_bytes(const fe_config* cfg, const fe_camera* cam, int64_t n) {
+  if (fe_validate(cfg, cam, n) != FE_OK) return 0;
+  return (size_t)(n > 0 ? n : 1) * 12 * sizeof(float);
+}
+
+fe_status fe_render_forward(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
+                            const fe_images* out, void* state, size_t state_bytes, void* stream) {
+  fe_status st = fe_validate(cfg, cam, g ? g->n : -1);
+  if (st != FE_OK) return st;
+  if ((st = check_gaussians(cfg, g)) != FE_OK) return st;
+  if (!out || !out->rgb || !out->feat || !out->final_T || !out->n_contrib || !state) return FE_ERR_INVALID_ARG;
+  Layout L;
+  compute_layout(cfg, cam, g->n, &L);
+  if (state_bytes < L.total) return FE_ERR_WORKSPACE_TOO_SMALL;
+  return forward_impl(cfg, cam, g, out, state, L, static_cast<hipStream_t>(stream));
+}
+
+fe_status fe_render_backward(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
+                             const fe_images* fwd, const void* state, size_t state_bytes,
+                             const float* d_rgb, const float* d_feat, const fe_grads* out,
+                             void* scratch, size_t scratch_bytes, void* stream) {
+  fe_status st = fe_validate(cfg, cam, g ? g->n : -1);
+  if (st != FE_OK) return st;
+  if ((st = check_gaussians(cfg, g)) != FE_OK) return st;
+  if (!fwd || !fwd->final_T || !fwd->n_contrib || !state || !d_rgb || !d_feat || !out || !scratch)
+    return FE_ERR_INVALID_ARG;
+  if (!out->means || !out->scales || !out->quats || !out->opacity || !out->sh || !out->feat)
+    return FE_ERR_INVALID_ARG;
+  Layout L;
+  compute_layout(cfg, cam, g->n, &L);
+  if (state_bytes < L.total) return FE_ERR_WORKSPACE_TOO_SMALL;
+  if (scratch_bytes < fe_backward_scratch_bytes(cfg, cam, g->n)) return FE_ERR_WORKSPACE_TOO_SMALL;
+  if (g->n == 0) return FE_OK;
+  return backward_impl(cfg, cam, g, fwd, state, L, d_rgb, d_feat, out, scratch, static_cast<hipStream_t>(stream));
+}
+
+fe_status fe_read_report(const void* state, size_t state_bytes, fe_report* out, void* stream) {
+  if (!state || !out || state_bytes < sizeof(unsigned long long) * kRepWords) return FE_ERR_INVALID_ARG;
+  unsigned long long w[kRepWords];
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (hipMemcpyAsync(w, state, sizeof(w), hipMemcpyDeviceToHost, s) != hipSuccess) return FE_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return FE_ERR_HIP;
+  out->status = (int32_t)w[kRepStatus];
+  out->reserved = 0;
+  out->keys_needed = (int64_t)w[kRepKeys];
+  out->n_visible = (int64_t)w[kRepVisible];
+  out->n_culled_nonfinite = (int64_t)w[kRepNonFinite];
+  return (fe_status)out->status;
+}
+
+// ------------------------------------------------------------------------
+// Batched frames captured into one HIP graph.
+// ------------------------------------------------------------------------
+struct fe_batch_plan {
+  fe_config cfg;
+  int32_t frames;
+  int32_t mode;
+  std::vector<fe_camera> cams;
+  std::vector<fe_gaussians> g;
+  std::vector<fe_images> out;
+  std::vector<const float*> d_rgb, d_feat;
+  std::vector<fe_grads> grads;
+  std::vector<Layout> layouts;
+  std::vector<size_t> state_off, scratch_off;
+  char* ws;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  bool captured;
+};
+
+static size_t batch_layout(const fe_config* cfg, const fe_camera* cams, int32_t frames, const int64_t* n,
+                           std::vector<Layout>* layouts, std::vector<size_t>* st_off,
+                           std::vector<size_t>* sc_off) {
+  size_t o = 0;
+  for (int f = 0; f < frames; ++f) {
+    Layout L;
+    if (!compute_layout(cfg, &cams[f], n[f], &L)) return 0;
+    if (layouts) layouts->push_back(L);
+    if (st_off) st_off->push_back(o);
+    o = align256(o + L.total);
+    if (sc_off) sc_off->push_back(o);
+    o = align256(o + fe_backward_scratch_bytes(cfg, &cams[f], n[f]));
+  }
+  return o;
+}
+
+size_t fe_batch_workspace_bytes(const fe_config* cfg, const fe_camera* cams, int32_t frames, const int64_t* n) {
+  if (!cfg || !cams || !n || frames < 1) return 0;
+  return batch_layout(cfg, cams, frames, n, nullptr, nullptr, nullptr);
+}
+
+fe_status fe_batch_plan_create(const fe_config* cfg, const fe_camera* cams, int32_t frames,
+                               const fe_gaussians* g, const fe_images* out,
+                               const float* const* d_rgb, const float* const* d_feat,
+                               const fe_grads* grads, int32_t mode, void* workspace,
+                               size_t workspace_bytes, fe_batch_plan** plan) {
+  if (!plan) return FE_ERR_INVALID_ARG;
+  *plan = nullptr;
+  if (!cfg || !cams || frames < 1 || !g || !out || !workspace) return FE_ERR_INVALID_ARG;
+  if (mode != FE_MODE_FORWARD && mode != FE_MODE_BACKWARD && mode != FE_MODE_FORWARD_BACKWARD)
+    return FE_ERR_INVALID_ARG;
+  const bool bwd = (mode & FE_MODE_BACKWARD) != 0;
+  if (bwd && (!d_rgb || !d_feat || !grads)) return FE_ERR_INVALID_ARG;
+  std::vector<int64_t> n(frames);
+  for (int f = 0; f < frames; ++f) {
+    fe_status st = fe_validate(cfg, &cams[f], g[f].n);
+    if (st != FE_OK) return st;
+    if ((st = check_gaussians(cfg, &g[f])) != FE_OK) return st;
+    if (!out[f].rgb || !out[f].feat || !out[f].final_T || !out[f].n_contrib) return FE_ERR_INVALID_ARG;
+    if (bwd) {
+      if (!d_rgb[f] || !d_feat[f]) return FE_ERR_INVALID_ARG;
+      const fe_grads& gr = grads[f];
+      if (!gr.means || !gr.scales || !gr.quats || !gr.opacity || !gr.sh || !gr.feat) return FE_ERR_INVALID_ARG;
+    }
+    n[f] = g[f].n;
+  }
+  fe_batch_plan* p = new (std::nothrow) fe_batch_plan();
+  if (!p) return FE_ERR_INVALID_ARG;
+  const size_t need = batch_layout(cfg, cams, frames, n.data(), &p->layouts, &p->state_off, &p->scratch_off);
+  if (workspace_bytes < need) {
+    delete p;
+    return FE_ERR_WORKSPACE_TOO_SMALL;
+  }
+  p->cfg = *cfg;
+  p->frames = frames;
+  p->mode = mode;
+  p->cams.assign(cams, cams + frames);
+  p->g.assign(g, g + frames);
+  p->out.assign(out, out + frames);
+  if (bwd) {
+    p->d_rgb.assign(d_rgb, d_rgb + frames);
+    p->d_feat.assign(d_feat, d_feat + frames);
+    p->grads.assign(grads, grads + frames);
+  }
+  p->ws = static_cast<char*>(workspace);
+  p->graph = nullptr;
+  p->exec = nullptr;
+  p->captured = false;
+  *plan = p;
+  return FE_OK;
+}
+
+static fe_status batch_enqueue(fe_batch_plan* p, hipStream_t s) {
+  fe_status st = FE_OK;
+  if (p->mode & FE_MODE_FORWARD) {
+    for (int f = 0; f < p->frames && st == FE_OK; ++f)
+      st = forward_impl(&p->cfg, &p->cams[f], &p->g[f], &p->out[f], p->ws + p->state_off[f], p->layouts[f], s);
+  }
+  if (p->mode & FE_MODE_BACKWARD) {
+    for (int f = 0; f < p->frames && st == FE_OK; ++f) {
+      if (p->g[f].n == 0) continue;
+      st = backward_impl(&p->cfg, &p->cams[f], &p->g[f], &p->out[f], p->ws + p->state_off[f], p->layouts[f],
+                         p->d_rgb[f], p->d_feat[f], &p->grads[f], p->ws + p->scratch_off[f], s);
+    }
+  }
+  return st;
+}
+
+fe_status fe_batch_launch(fe_batch_plan* p, void* stream) {
+  if (!p) return FE_ERR_INVALID_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!p->captured) {
+    // capture on a private non-default stream so that the caller's stream may be
+    // the legacy default stream
+    hipStream_t cs;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return FE_ERR_HIP;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      hipStreamDestroy(cs);
+      return FE_ERR_HIP;
+    }
+    const fe_status st = batch_enqueue(p, cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &graph);
+    hipStreamDestroy(cs);
+    if (st != FE_OK) {
+      if (graph) hipGraphDestroy(graph);
+      return st;
+    }
+    if (e != hipSuccess || !graph) return FE_ERR_HIP;
+    hipGraphExec_t exec = nullptr;
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+      hipGraphDestroy(graph);
+      return FE_ERR_HIP;
+    }
+    p->graph = graph;
+    p->exec = exec;
+    p->captured = true;
+  }
+  return hip_status(hipGraphLaunch(p->exec, s));
+}
+
+fe_status fe_batch_read_report(fe_batch_plan* p, int32_t f, fe_report* out, void* stream) {
+  if (!p || f < 0 || f >= p->frames) return FE_ERR_INVALID_ARG;
+  return fe_read_report(p->ws + p->state_off[f], p->layouts[f].total, out, stream);
+}
+
+void fe_batch_plan_destroy(fe_batch_plan* p) {
+  if (!p) return;
+  if (p->exec) hipGraphExecDestroy(p->exec);
+  if (p->graph) hipGraphDestroy(p->graph);
+  delete p;
+}
+
+}  // extern "C"

@@ -1,0 +1,122 @@
+// Internal declarations shared by the HIP sources of libfe4dgs_rast.so.
+// Not part of the ABI (the ABI is include/fe4dgs_rast.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/fe4dgs_rast.h"
+
+namespace fe {
+
+// Blending rules (Sec. 3.4 with the thresholds of the hot-path definition).
+constexpr float kAlphaMax = 0.99f;
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kTStop = 1e-4f;
+constexpr float kQMax = 9.0f;
+
+// Radix passes: 8-bit digits, 256 threads x 8 items per chunk.
+constexpr int kRadixBits = 8;
+constexpr int kRadixBins = 256;
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 8;
+constexpr int kSortChunk = kSortThreads * kSortItems;   // 2048
+
+// Exclusive scan: 256 threads x 8 items per block.
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanChunk = kScanThreads * kScanItems;   // 2048
+constexpr int kScanTopMax = kScanThreads * 16;          // block sums scanned by one block
+
+// Report words (unsigned long long) at StateView::report.
+enum ReportWord { kRepStatus = 0, kRepKeys = 1, kRepVisible = 2, kRepNonFinite = 3, kRepWords = 8 };
+
+// Device pointers into one frame's forward state plus its derived sizes.
+struct StateView {
+  float2* xy;
+  float4* conic_o;
+  float4* rgb;
+  short4* box;
+  uint32_t* dkey_a;
+  uint32_t* dkey_b;
+  uint32_t* didx_a;
+  uint32_t* didx_b;
+  uint32_t* count;
+  uint32_t* offsets;
+  uint32_t* scan_sums;
+  uint32_t* hist_n;
+  uint32_t* tile_a;
+  uint32_t* gauss_a;
+  uint32_t* tile_b;
+  uint32_t* gauss_b;
+  uint32_t* hist_k;
+  uint32_t* totals;     // [kRadixBins * (4 + tile_passes)]
+  uint2* ranges;
+  unsigned long long* report;
+  // sizes
+  int64_t n;
+  int64_t cap;
+  int32_t tiles_x, tiles_y, tiles;
+  int32_t nchunks_n, nchunks_k, nscan_blocks;
+  int32_t tile_passes;
+};
+
+struct Layout {
+  size_t total;
+  size_t xy, conic_o, rgb, box, dkey_a, dkey_b, didx_a, didx_b, count, offsets, scan_sums, hist_n;
+  size_t tile_a, gauss_a, tile_b, gauss_b, hist_k, totals, ranges, report;
+  int64_t n, cap;
+  int32_t tiles_x, tiles_y, tiles, nchunks_n, nchunks_k, nscan_blocks, tile_passes;
+};
+
+// Host helpers (fe_api.cpp).
+bool compute_layout(const fe_config* cfg, const fe_camera* cam, int64_t n, Layout* L);
+StateView make_view(const Layout& L, void* base);
+
+// Per-frame projection constants, computed on the host in float64.
+struct CamConst {
+  double R[9];       // world -> camera rotation, row-major
+  double t[3];
+  double campos[3];  // -R^T t
+  double fx, fy, cx, cy;
+  double limx, limy; // Jacobian clamp limits on tx/tz, ty/tz (<= 0: none)
+  double near_plane;
+  double dilation;
+  int32_t width, height;
+};
+CamConst make_cam_const(const fe_camera* cam, const fe_config* cfg);
+
+// ---- launchers (each enqueues on `stream`, returns hipError_t) ----
+hipError_t launch_zero_u32(uint32_t* p, size_t count, hipStream_t s);
+hipError_t launch_project_fwd(const CamConst& cc, const fe_config* cfg, const fe_gaussians* g,
+                              const StateView& v, hipStream_t s);
+hipError_t launch_sort_and_bin(const fe_config* cfg, const StateView& v, hipStream_t s);
+hipError_t launch_composite_fwd(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
+                                const StateView& v, const fe_images* out, hipStream_t s);
+hipError_t launch_composite_bwd(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
+                                const StateView& v, const fe_images* fwd, const float* d_rgb,
+                                const float* d_feat, float* grad2d, float* grad_feat, hipStream_t s);
+hipError_t launch_project_bwd(const CamConst& cc, const fe_config* cfg, const fe_gaussians* g,
+                              const StateView& v, const float* grad2d, const fe_grads* out,
+                              hipStream_t s);
+
+// ---- small device helpers ----
+__device__ __forceinline__ float bf16_bits_to_float(uint16_t b) {
+  return __uint_as_float(static_cast<uint32_t>(b) << 16);
+}
+
+template <typename T>
+__device__ __forceinline__ float load_as_float(const void* p, int64_t i);
+
+template <>
+__device__ __forceinline__ float load_as_float<float>(const void* p, int64_t i) {
+  return static_cast<const float*>(p)[i];
+}
+
+template <>
+__device__ __forceinline__ float load_as_float<uint16_t>(const void* p, int64_t i) {
+  return bf16_bits_to_float(static_cast<const uint16_t*>(p)[i]);
+}
+
+}  // namespace fe

@@ -1,0 +1,532 @@
+// Per-Gaussian projection, forward and backward, for gfx950.
+//
+// Forward (one thread per Gaussian, float64 geometry): camera-space centre,
+// Sigma = R S S^T R^T from the normalised quaternion (eq. 2), the affine
+// approximation J of the perspective map and Sigma' = J W Sigma W^T J^T
+// (eq. 9) plus the dilation, the conic Sigma'^-1, the pixel position, the
+// 3-sigma pixel box and its tile rectangle, and the view-dependent colour from
+// real SH coefficients (Sec. 3.1).  The record is rounded to float32 once.
+//
+// Every expression that decides a sort key or a box (tz, u, v, Sigma'_xx,
+// Sigma'_yy, the box bounds) is evaluated as separate IEEE float64 operations
+// in a fixed order with contraction disabled, so the keys are reproducible
+// bit for bit by any implementation that evaluates the same expressions.
+//
+// Backward (one thread per Gaussian, float64): chain rule from the
+// screen-space gradients (u, v, conic, opacity, colour) through the conic
+// inverse, eq. (9), eq. (2), the quaternion normalisation and the SH basis.
+// The skip/stop decisions and the sort order are piecewise constant; the
+// colour clamp at 0 and a clamped Jacobian coordinate pass zero.
+#include "fe_common.h"
+
+#pragma clang fp contract(off)
+
+namespace fe {
+namespace {
+
+// Real SH basis, orthonormal, no Condon-Shortley phase; each constant is
+// the closed form K_l^m (times sqrt(2) for m != 0) written out.
+constexpr double kC0 = 0.28209479177387814;   // 1 / (2 sqrt(pi))
+constexpr double kC1 = 0.4886025119029199;    // sqrt(3 / (4 pi))
+constexpr double kC2a = 1.0925484305920792;   // sqrt(15 / pi) / 2
+constexpr double kC2b = 0.31539156525252005;  // sqrt(5 / pi) / 4
+constexpr double kC2c = 0.5462742152960396;   // sqrt(15 / pi) / 4
+constexpr double kC3e = 0.5900435899266435;   // sqrt(35 / (2 pi)) / 4
+constexpr double kC3f = 2.890611442640554;    // sqrt(105 / pi) / 2
+constexpr double kC3g = 0.4570457994644658;   // sqrt(21 / (2 pi)) / 4
+constexpr double kC3h = 0.3731763325901154;   // sqrt(7 / pi) / 4
+constexpr double kC3i = 1.445305721320277;    // sqrt(105 / pi) / 4
+
+template <int L>
+__device__ __forceinline__ void sh_basis(double x, double y, double z, double* Y) {
+  Y[0] = kC0;
+  if constexpr (L >= 1) {
+    Y[1] = kC1 * y;
+    Y[2] = kC1 * z;
+    Y[3] = kC1 * x;
+  }
+  if constexpr (L >= 2) {
+    const double xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = kC2a * (x * y);
+    Y[5] = kC2a * (y * z);
+    Y[6] = kC2b * (3.0 * zz - 1.0);
+    Y[7] = kC2a * (x * z);
+    Y[8] = kC2c * (xx - yy);
+    if constexpr (L >= 3) {
+      Y[9] = kC3e * y * (3.0 * xx - yy);
+      Y[10] = kC3f * x * y * z;
+      Y[11] = kC3g * y * (5.0 * zz - 1.0);
+      Y[12] = kC3h * z * (5.0 * zz - 3.0);
+      Y[13] = kC3g * x * (5.0 * zz - 1.0);
+      Y[14] = kC3i * z * (xx - yy);
+      Y[15] = kC3e * x * (xx - 3.0 * yy);
+    }
+  }
+}
+
+// Gradient of sum_k c_k Y_k with respect to the direction components,
+// accumulated into (gx, gy, gz).
+template <int L>
+__device__ __forceinline__ void sh_basis_grad(double x, double y, double z, const double* c,
+                                              double& gx, double& gy, double& gz) {
+  gx = 0.0;
+  gy = 0.0;
+  gz = 0.0;
+  if constexpr (L >= 1) {
+    gy += kC1 * c[1];
+    gz += kC1 * c[2];
+    gx += kC1 * c[3];
+  }
+  if constexpr (L >= 2) {
+    gx += kC2a * y * c[4];
+    gy += kC2a * x * c[4];
+    gy += kC2a * z * c[5];
+    gz += kC2a * y * c[5];
+    gz += 6.0 * kC2b * z * c[6];
+    gx += kC2a * z * c[7];
+    gz += kC2a * x * c[7];
+    gx += 2.0 * kC2c * x * c[8];
+    gy -= 2.0 * kC2c * y * c[8];
+    if constexpr (L >= 3) {
+      const double xx = x * x, yy = y * y, zz = z * z;
+      gx += 6.0 * kC3e * x * y * c[9];
+      gy += kC3e * (3.0 * xx - 3.0 * yy) * c[9];
+      gx += kC3f * y * z * c[10];
+      gy += kC3f * x * z * c[10];
+      gz += kC3f * x * y * c[10];
+      gy += kC3g * (5.0 * zz - 1.0) * c[11];
+      gz += 10.0 * kC3g * y * z * c[11];
+      gz += kC3h * (15.0 * zz - 3.0) * c[12];
+      gx += kC3g * (5.0 * zz - 1.0) * c[13];
+      gz += 10.0 * kC3g * x * z * c[13];
+      gx += 2.0 * kC3i * x * z * c[14];
+      gy -= 2.0 * kC3i * y * z * c[14];
+      gz += kC3i * (xx - yy) * c[14];
+      gx += kC3e * (3.0 * xx - 3.0 * yy) * c[15];
+      gy -= 6.0 * kC3e * x * y * c[15];
+    }
+  }
+}
+
+struct ProjArgs {
+  CamConst cc;
+  int64_t n;
+  int32_t tile_w, tile_h, tiles_x;
+  const float* means;
+  const float* scales;
+  const float* quats;
+  const float* opacity;
+  const void* sh;
+  StateView v;
+};
+
+// Geometry shared by the forward and the backward; everything in float64.
+struct Geo {
+  double tx, ty, tz;
+  double qw, qx, qy, qz, qn;   // normalised quaternion and the input norm
+  double R[9];
+  double s[3];
+  double Sig[6];               // xx xy xz yy yz zz
+  double xr, yr;
+  bool clampx, clampy;
+  double j00, j02, j11, j12;
+  double Tm[6];                // 2x3 row-major
+  double a, b, c;              // Sigma' (dilated)
+  double det;
+  double u, v;
+};
+
+__device__ __forceinline__ void geometry(const CamConst& cc, const float* mp, const float* sp,
+                                         const float* qp, Geo& G) {
+  const double x = mp[0], y = mp[1], z = mp[2];
+  G.tx = ((cc.R[0] * x + cc.R[1] * y) + cc.R[2] * z) + cc.t[0];
+  G.ty = ((cc.R[3] * x + cc.R[4] * y) + cc.R[5] * z) + cc.t[1];
+  G.tz = ((cc.R[6] * x + cc.R[7] * y) + cc.R[8] * z) + cc.t[2];
+  const double w0 = qp[0], x0 = qp[1], y0 = qp[2], z0 = qp[3];
+  G.qn = sqrt(((w0 * w0 + x0 * x0) + y0 * y0) + z0 * z0);
+  const double w = w0 / G.qn, qx = x0 / G.qn, qy = y0 / G.qn, qz = z0 / G.qn;
+  G.qw = w; G.qx = qx; G.qy = qy; G.qz = qz;
+  double* R = G.R;
+  R[0] = 1.0 - 2.0 * (qy * qy + qz * qz);
+  R[1] = 2.0 * (qx * qy - w * qz);
+  R[2] = 2.0 * (qx * qz + w * qy);
+  R[3] = 2.0 * (qx * qy + w * qz);
+  R[4] = 1.0 - 2.0 * (qx * qx + qz * qz);
+  R[5] = 2.0 * (qy * qz - w * qx);
+  R[6] = 2.0 * (qx * qz - w * qy);
+  R[7] = 2.0 * (qy * qz + w * qx);
+  R[8] = 1.0 - 2.0 * (qx * qx + qy * qy);
+  G.s[0] = sp[0]; G.s[1] = sp[1]; G.s[2] = sp[2];
+  double M[9];
+  for (int a = 0; a < 3; ++a)
+    for (int k = 0; k < 3; ++k) M[a * 3 + k] = R[a * 3 + k] * G.s[k];
+  auto sig = [&](int a, int b) {
+    return (M[a * 3 + 0] * M[b * 3 + 0] + M[a * 3 + 1] * M[b * 3 + 1]) + M[a * 3 + 2] * M[b * 3 + 2];
+  };
+  G.Sig[0] = sig(0, 0); G.Sig[1] = sig(0, 1); G.Sig[2] = sig(0, 2);
+  G.Sig[3] = sig(1, 1); G.Sig[4] = sig(1, 2); G.Sig[5] = sig(2, 2);
+  G.xr = G.tx / G.tz;
+  G.yr = G.ty / G.tz;
+  double xc = G.xr, yc = G.yr;
+  G.clampx = false;
+  G.clampy = false;
+  if (cc.limx > 0.0) {
+    G.clampx = (G.xr < -cc.limx) || (G.xr > cc.limx);
+    G.clampy = (G.yr < -cc.limy) || (G.yr > cc.limy);
+    xc = fmin(fmax(G.xr, -cc.limx), cc.limx);
+    yc = fmin(fmax(G.yr, -cc.limy), cc.limy);
+  }
+  G.j00 = cc.fx / G.tz;
+  G.j02 = (-cc.fx * xc) / G.tz;
+  G.j11 = cc.fy / G.tz;
+  G.j12 = (-cc.fy * yc) / G.tz;
+  for (int k = 0; k < 3; ++k) {
+    G.Tm[k] = G.j00 * cc.R[0 * 3 + k] + G.j02 * cc.R[2 * 3 + k];
+    G.Tm[3 + k] = G.j11 * cc.R[1 * 3 + k] + G.j12 * cc.R[2 * 3 + k];
+  }
+  const double S[9] = {G.Sig[0], G.Sig[1], G.Sig[2], G.Sig[1], G.Sig[3], G.Sig[4],
+                       G.Sig[2], G.Sig[4], G.Sig[5]};
+  double U[6];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 3; ++b)
+      U[a * 3 + b] = (G.Tm[a * 3 + 0] * S[0 * 3 + b] + G.Tm[a * 3 + 1] * S[1 * 3 + b]) +
+                     G.Tm[a * 3 + 2] * S[2 * 3 + b];
+  auto c2 = [&](int a, int b) {
+    return (U[a * 3 + 0] * G.Tm[b * 3 + 0] + U[a * 3 + 1] * G.Tm[b * 3 + 1]) + U[a * 3 + 2] * G.Tm[b * 3 + 2];
+  };
+  G.a = c2(0, 0) + cc.dilation;
+  G.b = c2(0, 1);
+  G.c = c2(1, 1) + cc.dilation;
+  G.det = G.a * G.c - G.b * G.b;
+  G.u = cc.fx * G.xr + cc.cx;
+  G.v = cc.fy * G.yr + cc.cy;
+}
+
+__device__ __forceinline__ bool all_finite(const float* p, int k) {
+  bool ok = true;
+  for (int i = 0; i < k; ++i) ok = ok && isfinite(p[i]);
+  return ok;
+}
+
+template <int L, typename ShT>
+__global__ __launch_bounds__(256) void project_fwd_kernel(ProjArgs a) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const bool in = i < a.n;
+  bool nonfinite = false;
+  bool vis = false;
+  if (in) {
+    const CamConst& cc = a.cc;
+    const float* mp = a.means + 3 * i;
+    const float* sp = a.scales + 3 * i;
+    const float* qp = a.quats + 4 * i;
+    const float op = a.opacity[i];
+    const bool fin = all_finite(mp, 3) && all_finite(sp, 3) && all_finite(qp, 4) && isfinite(op);
+    const double q2 = (((double)qp[0] * qp[0] + (double)qp[1] * qp[1]) + (double)qp[2] * qp[2]) +
+                      (double)qp[3] * qp[3];
+    nonfinite = !(fin && q2 > 0.0);
+    uint32_t count = 0;
+    uint32_t dkey = 0xFFFFFFFFu;
+    float2 xy = make_float2(0.f, 0.f);
+    float4 co = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 rgb = make_float4(0.f, 0.f, 0.f, 0.f);
+    short4 box = make_short4(1, 1, 0, 0);
+    if (!nonfinite) {
+      const double tz = ((cc.R[6] * (double)mp[0] + cc.R[7] * (double)mp[1]) + cc.R[8] * (double)mp[2]) + cc.t[2];
+      if (tz > cc.near_plane) {
+        Geo G;
+        geometry(cc, mp, sp, qp, G);
+        if (G.det > 0.0 && isfinite(G.det)) {
+          const double rx = 3.0 * sqrt(G.a);
+          const double ry = 3.0 * sqrt(G.c);
+          double i0 = ceil((G.u - rx) - 0.5);
+          double i1 = floor((G.u + rx) - 0.5);
+          double j0 = ceil((G.v - ry) - 0.5);
+          double j1 = floor((G.v + ry) - 0.5);
+          i0 = fmax(i0, 0.0);
+          j0 = fmax(j0, 0.0);
+          i1 = fmin(i1, (double)(cc.width - 1));
+          j1 = fmin(j1, (double)(cc.height - 1));
+          // conic and the float32 record
+          const double A = G.c / G.det, B = -G.b / G.det, C = G.a / G.det;
+          xy = make_float2((float)G.u, (float)G.v);
+          co = make_float4((float)A, (float)B, (float)C, op);
+          // colour from SH along normalise(mu - campos)
+          const double dx = (double)mp[0] - cc.campos[0];
+          const double dy = (double)mp[1] - cc.campos[1];
+          const double dz = (double)mp[2] - cc.campos[2];
+          const double dn = sqrt(((dx * dx + dy * dy) + dz * dz));
+          double Y[16];
+          sh_basis<L>(dx / dn, dy / dn, dz / dn, Y);
+          constexpr int K = (L + 1) * (L + 1);
+          double col[3] = {0.5, 0.5, 0.5};
+          double acc[3] = {0.0, 0.0, 0.0};
+          for (int k = 0; k < K; ++k)
+            for (int ch = 0; ch < 3; ++ch)
+              acc[ch] += load_as_float<ShT>(a.sh, (i * K + k) * 3 + ch) * Y[k];
+          for (int ch = 0; ch < 3; ++ch) col[ch] = fmax(acc[ch] + 0.5, 0.0);
+          rgb = make_float4((float)col[0], (float)col[1], (float)col[2], 0.f);
+          if (i0 <= i1 && j0 <= j1 && isfinite(G.u) && isfinite(G.v)) {
+            const int ii0 = (int)i0, ii1 = (int)i1, jj0 = (int)j0, jj1 = (int)j1;
+            box = make_short4((short)ii0, (short)jj0, (short)ii1, (short)jj1);
+            const int tx0 = ii0 / a.tile_w, tx1 = ii1 / a.tile_w;
+            const int ty0 = jj0 / a.tile_h, ty1 = jj1 / a.tile_h;
+            count = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+            dkey = __float_as_uint((float)G.tz);
+            vis = true;
+          }
+        }
+      }
+    }
+    a.v.xy[i] = xy;
+    a.v.conic_o[i] = co;
+    a.v.rgb[i] = rgb;
+    a.v.box[i] = box;
+    a.v.dkey_a[i] = dkey;
+    a.v.didx_a[i] = (uint32_t)i;
+    a.v.count[i] = count;
+  }
+  // wave-aggregated report counters
+  const unsigned long long mv = __ballot(vis);
+  const unsigned long long mn = __ballot(nonfinite);
+  if (__lane_id() == 0) {
+    if (mv) atomicAdd(&a.v.report[kRepVisible], (unsigned long long)__popcll(mv));
+    if (mn) atomicAdd(&a.v.report[kRepNonFinite], (unsigned long long)__popcll(mn));
+  }
+}
+
+struct ProjBwdArgs {
+  CamConst cc;
+  int64_t n;
+  const float* means;
+  const float* scales;
+  const float* quats;
+  const void* sh;
+  const float* grad2d;    // [n][12]: u v A B C o r g b - - -
+  const uint32_t* count;
+  float* g_means;
+  float* g_scales;
+  float* g_quats;
+  float* g_opacity;
+  float* g_sh;
+  float* g_means2d;
+  int accumulate;
+};
+
+template <int L, typename ShT>
+__global__ __launch_bounds__(256) void project_bwd_kernel(ProjBwdArgs a) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  constexpr int K = (L + 1) * (L + 1);
+  double gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gop = 0.0;
+  double gsh[K * 3];
+  for (int k = 0; k < K * 3; ++k) gsh[k] = 0.0;
+  double gu = 0.0, gv = 0.0;
+  if (a.count[i] > 0) {
+    const CamConst& cc = a.cc;
+    const float* mp = a.means + 3 * i;
+    const float* sp = a.scales + 3 * i;
+    const float* qp = a.quats + 4 * i;
+    const float* g2 = a.grad2d + 12 * i;
+    gu = g2[0];
+    gv = g2[1];
+    const double gA = g2[2], gB = g2[3], gC = g2[4];
+    gop = g2[5];
+    const double gcol[3] = {g2[6], g2[7], g2[8]};
+    Geo G;
+    geometry(cc, mp, sp, qp, G);
+    // conic -> Sigma':  dL/dSigma' = -M GM M  with M the conic matrix and
+    // GM the symmetric gradient (off-diagonal gB / 2)
+    const double A = G.c / G.det, B = -G.b / G.det, C = G.a / G.det;
+    const double hB = 0.5 * gB;
+    const double P00 = gA * A + hB * B, P01 = gA * B + hB * C;
+    const double P10 = hB * A + gC * B, P11 = hB * B + gC * C;
+    const double S00 = -(A * P00 + B * P10);
+    const double S01 = -(A * P01 + B * P11);
+    const double S11 = -(B * P01 + C * P11);
+    const double GS[4] = {S00, S01, S01, S11};
+    // Sigma' = Tm Sigma Tm^T:  dSigma = Tm^T GS Tm,  dTm = 2 GS Tm Sigma
+    const double* T = G.Tm;
+    const double Sg[9] = {G.Sig[0], G.Sig[1], G.Sig[2], G.Sig[1], G.Sig[3], G.Sig[4],
+                          G.Sig[2], G.Sig[4], G.Sig[5]};
+    double GT[6];   // GS Tm  (2x3)
+    for (int r = 0; r < 2; ++r)
+      for (int k = 0; k < 3; ++k) GT[r * 3 + k] = GS[r * 2 + 0] * T[0 * 3 + k] + GS[r * 2 + 1] * T[1 * 3 + k];
+    double dSig[9];
+    for (int p = 0; p < 3; ++p)
+      for (int q = 0; q < 3; ++q) dSig[p * 3 + q] = T[0 * 3 + p] * GT[0 * 3 + q] + T[1 * 3 + p] * GT[1 * 3 + q];
+    double dT[6];
+    for (int r = 0; r < 2; ++r)
+      for (int k = 0; k < 3; ++k)
+        dT[r * 3 + k] = 2.0 * (GT[r * 3 + 0] * Sg[0 * 3 + k] + GT[r * 3 + 1] * Sg[1 * 3 + k] +
+                               GT[r * 3 + 2] * Sg[2 * 3 + k]);
+    // Tm = J W:  dJ = dT W^T
+    auto dJ = [&](int r, int b) {
+      return dT[r * 3 + 0] * cc.R[b * 3 + 0] + dT[r * 3 + 1] * cc.R[b * 3 + 1] + dT[r * 3 + 2] * cc.R[b * 3 + 2];
+    };
+    const double dj00 = dJ(0, 0), dj02 = dJ(0, 2), dj11 = dJ(1, 1), dj12 = dJ(1, 2);
+    const double tz = G.tz, tz2 = tz * tz, tz3 = tz2 * tz;
+    double gtx = 0.0, gty = 0.0, gtz = 0.0;
+    gtz += -cc.fx / tz2 * dj00 - cc.fy / tz2 * dj11;
+    if (!G.clampx) {
+      gtx += -cc.fx / tz2 * dj02;
+      gtz += 2.0 * cc.fx * G.tx / tz3 * dj02;
+    } else {
+      const double xc = fmin(fmax(G.xr, -cc.limx), cc.limx);
+      gtz += cc.fx * xc / tz2 * dj02;
+    }
+    if (!G.clampy) {
+      gty += -cc.fy / tz2 * dj12;
+      gtz += 2.0 * cc.fy * G.ty / tz3 * dj12;
+    } else {
+      const double yc = fmin(fmax(G.yr, -cc.limy), cc.limy);
+      gtz += cc.fy * yc / tz2 * dj12;
+    }
+    // pixel position
+    gtx += cc.fx / tz * gu;
+    gtz += -cc.fx * G.tx / tz2 * gu;
+    gty += cc.fy / tz * gv;
+    gtz += -cc.fy * G.ty / tz2 * gv;
+    // t = W mu + t_c
+    for (int k = 0; k < 3; ++k) gm[k] = cc.R[0 * 3 + k] * gtx + cc.R[1 * 3 + k] * gty + cc.R[2 * 3 + k] * gtz;
+    // Sigma = M M^T, M = R diag(s):  dM = 2 dSigma M
+    const double* R = G.R;
+    double M[9];
+    for (int p = 0; p < 3; ++p)
+      for (int k = 0; k < 3; ++k) M[p * 3 + k] = R[p * 3 + k] * G.s[k];
+    double dR[9];
+    for (int p = 0; p < 3; ++p)
+      for (int k = 0; k < 3; ++k) {
+        const double dM = 2.0 * (dSig[p * 3 + 0] * M[0 * 3 + k] + dSig[p * 3 + 1] * M[1 * 3 + k] +
+                                 dSig[p * 3 + 2] * M[2 * 3 + k]);
+        dR[p * 3 + k] = dM * G.s[k];
+        gs[k] += dM * R[p * 3 + k];
+      }
+    // rotation of the normalised quaternion
+    const double w = G.qw, x = G.qx, y = G.qy, z = G.qz;
+    const double gw = 2.0 * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+    const double gx = 2.0 * (y * dR[1] + z * dR[2] + y * dR[3] - 2.0 * x * dR[4] - w * dR[5] + z * dR[6] +
+                             w * dR[7] - 2.0 * x * dR[8]);
+    const double gy = 2.0 * (-2.0 * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] +
+                             z * dR[7] - 2.0 * y * dR[8]);
+    const double gz = 2.0 * (-2.0 * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.0 * z * dR[4] +
+                             y * dR[5] + x * dR[6] + y * dR[7]);
+    const double dot = w * gw + x * gx + y * gy + z * gz;
+    gq[0] = (gw - w * dot) / G.qn;
+    gq[1] = (gx - x * dot) / G.qn;
+    gq[2] = (gy - y * dot) / G.qn;
+    gq[3] = (gz - z * dot) / G.qn;
+    // colour
+    const double dx = (double)mp[0] - cc.campos[0];
+    const double dy = (double)mp[1] - cc.campos[1];
+    const double dz = (double)mp[2] - cc.campos[2];
+    const double dn = sqrt(((dx * dx + dy * dy) + dz * dz));
+    const double ux = dx / dn, uy = dy / dn, uz = dz / dn;
+    double Y[16];
+    sh_basis<L>(ux, uy, uz, Y);
+    double gdx = 0.0, gdy = 0.0, gdz = 0.0;
+    for (int ch = 0; ch < 3; ++ch) {
+      double raw = 0.0;
+      double cf[16];
+      for (int k = 0; k < K; ++k) {
+        cf[k] = load_as_float<ShT>(a.sh, (i * K + k) * 3 + ch);
+        raw += cf[k] * Y[k];
+      }
+      raw += 0.5;
+      if (raw >= 0.0 && gcol[ch] != 0.0) {
+        for (int k = 0; k < K; ++k) gsh[k * 3 + ch] = Y[k] * gcol[ch];
+        double ex, ey, ez;
+        sh_basis_grad<L>(ux, uy, uz, cf, ex, ey, ez);
+        gdx += gcol[ch] * ex;
+        gdy += gcol[ch] * ey;
+        gdz += gcol[ch] * ez;
+      }
+    }
+    const double dd = ux * gdx + uy * gdy + uz * gdz;
+    gm[0] += (gdx - ux * dd) / dn;
+    gm[1] += (gdy - uy * dd) / dn;
+    gm[2] += (gdz - uz * dd) / dn;
+  }
+  auto put = [&](float* p, double val) {
+    if (a.accumulate) *p += (float)val; else *p = (float)val;
+  };
+  for (int k = 0; k < 3; ++k) put(a.g_means + 3 * i + k, gm[k]);
+  for (int k = 0; k < 3; ++k) put(a.g_scales + 3 * i + k, gs[k]);
+  for (int k = 0; k < 4; ++k) put(a.g_quats + 4 * i + k, gq[k]);
+  put(a.g_opacity + i, gop);
+  for (int k = 0; k < K * 3; ++k) put(a.g_sh + i * K * 3 + k, gsh[k]);
+  if (a.g_means2d) {
+    put(a.g_means2d + 2 * i, gu);
+    put(a.g_means2d + 2 * i + 1, gv);
+  }
+}
+
+template <typename ShT>
+hipError_t launch_fwd_typed(int L, const ProjArgs& args, int blocks, hipStream_t s) {
+  switch (L) {
+    case 0: hipLaunchKernelGGL((project_fwd_kernel<0, ShT>), dim3(blocks), dim3(256), 0, s, args); break;
+    case 1: hipLaunchKernelGGL((project_fwd_kernel<1, ShT>), dim3(blocks), dim3(256), 0, s, args); break;
+    case 2: hipLaunchKernelGGL((project_fwd_kernel<2, ShT>), dim3(blocks), dim3(256), 0, s, args); break;
+    default: hipLaunchKernelGGL((project_fwd_kernel<3, ShT>), dim3(blocks), dim3(256), 0, s, args); break;
+  }
+  return hipGetLastError();
+}
+
+template <typename ShT>
+hipError_t launch_bwd_typed(int L, const ProjBwdArgs& args, int blocks, hipStream_t s) {
+  switch (L) {
+    case 0: hipLaunchKernelGGL((project_bwd_kernel<0, ShT>), dim3(blocks), dim3(256), 0, s, args); break;
+    case 1: hipLaunchKernelGGL((project_bwd_kernel<1, ShT>), dim3(blocks), dim3(256), 0, s, args); break;
+    case 2: hipLaunchKernelGGL((project_bwd_kernel<2, ShT>), dim3(blocks), dim3(256), 0, s, args); break;
+    default: hipLaunchKernelGGL((project_bwd_kernel<3, ShT>), dim3(blocks), dim3(256), 0, s, args); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_project_fwd(const CamConst& cc, const fe_config* cfg, const fe_gaussians* g,
+                              const StateView& v, hipStream_t s) {
+  if (g->n == 0) return hipSuccess;
+  ProjArgs a;
+  a.cc = cc;
+  a.n = g->n;
+  a.tile_w = cfg->tile_w;
+  a.tile_h = cfg->tile_h;
+  a.tiles_x = v.tiles_x;
+  a.means = g->means;
+  a.scales = g->scales;
+  a.quats = g->quats;
+  a.opacity = g->opacity;
+  a.sh = g->sh;
+  a.v = v;
+  const int blocks = (int)((g->n + 255) / 256);
+  return cfg->sh_dtype == FE_BF16 ? launch_fwd_typed<uint16_t>(cfg->sh_degree, a, blocks, s)
+                                  : launch_fwd_typed<float>(cfg->sh_degree, a, blocks, s);
+}
+
+hipError_t launch_project_bwd(const CamConst& cc, const fe_config* cfg, const fe_gaussians* g,
+                              const StateView& v, const float* grad2d, const fe_grads* out,
+                              hipStream_t s) {
+  if (g->n == 0) return hipSuccess;
+  ProjBwdArgs a;
+  a.cc = cc;
+  a.n = g->n;
+  a.means = g->means;
+  a.scales = g->scales;
+  a.quats = g->quats;
+  a.sh = g->sh;
+  a.grad2d = grad2d;
+  a.count = v.count;
+  a.g_means = out->means;
+  a.g_scales = out->scales;
+  a.g_quats = out->quats;
+  a.g_opacity = out->opacity;
+  a.g_sh = out->sh;
+  a.g_means2d = out->means2d;
+  a.accumulate = (cfg->flags & FE_FLAG_NO_ZERO_GRADS) ? 1 : 0;
+  const int blocks = (int)((g->n + 255) / 256);
+  return cfg->sh_dtype == FE_BF16 ? launch_bwd_typed<uint16_t>(cfg->sh_degree, a, blocks, s)
+                                  : launch_bwd_typed<float>(cfg->sh_degree, a, blocks, s);
+}
+
+}  // namespace fe
