@@ -94,7 +94,20 @@ typedef struct fe_config {
   int64_t key_capacity;          /* maximum number of (tile, Gaussian) keys    */
   uint32_t flags;                /* FE_FLAG_*                                   */
   int32_t variant;               /* compositing kernel variant (FE_VARIANT_*)  */
+  void* const* stage_events;     /* optional timing: NULL, or an array of
+                                    2 * FE_STAGE_COUNT hipEvent_t (entries may be
+                                    NULL); events[2s] / events[2s+1] are recorded
+                                    on the call's stream before / after stage s */
 } fe_config;
+
+/* Stages recorded by fe_config.stage_events. */
+#define FE_STAGE_PROJECT 0          /* projection forward                         */
+#define FE_STAGE_SORT 1             /* depth sort, emit, tile sort, ranges        */
+#define FE_STAGE_COMPOSITE 2        /* per-tile blending forward                  */
+#define FE_STAGE_COMPOSITE_BWD 3    /* per-tile blending backward                 */
+#define FE_STAGE_REDUCE 4           /* per-Gaussian reduction of tile partials    */
+#define FE_STAGE_PROJECT_BWD 5      /* projection backward                        */
+#define FE_STAGE_COUNT 6
 
 #define FE_FLAG_NO_ZERO_GRADS 0x1u  /* backward accumulates into *out instead of
                                        overwriting it                           */

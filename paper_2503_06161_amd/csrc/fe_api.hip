@@ -120,6 +120,13 @@ CamConst make_cam_const(const fe_camera* cam, const fe_config* cfg) {
 
 static fe_status hip_status(hipError_t e) { return e == hipSuccess ? FE_OK : FE_ERR_HIP; }
 
+// optional per-stage events (recorded on the call's stream)
+static void stage_mark(const fe_config* cfg, int stage, int end, hipStream_t s) {
+  if (!cfg->stage_events) return;
+  void* ev = cfg->stage_events[2 * stage + end];
+  if (ev) (void)hipEventRecord(static_cast<hipEvent_t>(ev), s);
+}
+
 static fe_status check_gaussians(const fe_config* cfg, const fe_gaussians* g) {
   if (!g || g->n < 0) return FE_ERR_INVALID_ARG;
   if (g->n == 0) return FE_OK;
@@ -134,9 +141,16 @@ static fe_status forward_impl(const fe_config* cfg, const fe_camera* cam, const 
   hipError_t e;
   const size_t zero_words = (L.ranges + sizeof(uint2) * (size_t)L.tiles - L.report) / 4;
   if ((e = launch_zero_u32(reinterpret_cast<uint32_t*>(v.report), zero_words, s)) != hipSuccess) return FE_ERR_HIP;
+  stage_mark(cfg, FE_STAGE_PROJECT, 0, s);
   if ((e = launch_project_fwd(make_cam_const(cam, cfg), cfg, g, v, s)) != hipSuccess) return FE_ERR_HIP;
+  stage_mark(cfg, FE_STAGE_PROJECT, 1, s);
+  stage_mark(cfg, FE_STAGE_SORT, 0, s);
   if ((e = launch_sort_and_bin(cfg, v, s)) != hipSuccess) return FE_ERR_HIP;
-  return hip_status(launch_composite_fwd(cfg, cam, g, v, out, s));
+  stage_mark(cfg, FE_STAGE_SORT, 1, s);
+  stage_mark(cfg, FE_STAGE_COMPOSITE, 0, s);
+  e = launch_composite_fwd(cfg, cam, g, v, out, s);
+  stage_mark(cfg, FE_STAGE_COMPOSITE, 1, s);
+  return hip_status(e);
 }
 
 static fe_status backward_impl(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
@@ -150,9 +164,14 @@ static fe_status backward_impl(const fe_config* cfg, const fe_camera* cam, const
     if ((e = launch_zero_u32(reinterpret_cast<uint32_t*>(out->feat), (size_t)cfg->feat_dim * g->n, s)) != hipSuccess)
       return FE_ERR_HIP;
   }
+  stage_mark(cfg, FE_STAGE_COMPOSITE_BWD, 0, s);
   if ((e = launch_composite_bwd(cfg, cam, g, v, fwd, d_rgb, d_feat, grad2d, out->feat, s)) != hipSuccess)
     return FE_ERR_HIP;
-  return hip_status(launch_project_bwd(make_cam_const(cam, cfg), cfg, g, v, grad2d, out, s));
+  stage_mark(cfg, FE_STAGE_COMPOSITE_BWD, 1, s);
+  stage_mark(cfg, FE_STAGE_PROJECT_BWD, 0, s);
+  e = launch_project_bwd(make_cam_const(cam, cfg), cfg, g, v, grad2d, out, s);
+  stage_mark(cfg, FE_STAGE_PROJECT_BWD, 1, s);
+  return hip_status(e);
 }
 
 }  // namespace fe

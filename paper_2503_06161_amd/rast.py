@@ -22,6 +22,7 @@ FE_F32, FE_BF16 = 0, 1
 FE_FLAG_NO_ZERO_GRADS = 1
 FE_VARIANT_AUTO, FE_VARIANT_VALU = 0, 1
 FE_MODE_FORWARD, FE_MODE_BACKWARD, FE_MODE_FORWARD_BACKWARD = 1, 2, 3
+STAGES = ("project", "sort", "composite", "composite_bwd", "reduce", "project_bwd")
 
 
 class RasterError(RuntimeError):
@@ -41,7 +42,7 @@ class fe_config(C.Structure):
                 ("sh_degree", C.c_int32), ("feat_dim", C.c_int32), ("sh_dtype", C.c_int32),
                 ("feat_dtype", C.c_int32), ("bg_rgb", C.c_float * 3), ("cov2d_dilation", C.c_float),
                 ("jacobian_clamp", C.c_float), ("key_capacity", C.c_int64), ("flags", C.c_uint32),
-                ("variant", C.c_int32)]
+                ("variant", C.c_int32), ("stage_events", C.c_void_p)]
 
 
 class fe_gaussians(C.Structure):
@@ -138,6 +139,7 @@ class Settings:
     key_capacity: int | None = None
     variant: int = FE_VARIANT_AUTO
     flags: int = 0
+    stage_events: object = None     # optional ctypes array of 2*len(STAGES) hipEvent_t handles
 
     def to_c(self, cap: int) -> fe_config:
         c = fe_config()
@@ -152,6 +154,7 @@ class Settings:
         c.key_capacity = int(cap)
         c.flags = self.flags
         c.variant = self.variant
+        c.stage_events = C.cast(self.stage_events, C.c_void_p) if self.stage_events is not None else None
         return c
 
 
