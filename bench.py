@@ -37,6 +37,8 @@ def _parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-tiles", type=int, default=8)
     ap.add_argument("--forms", default="bf16,f32")
+    ap.add_argument("--variant", default="mfma", choices=["mfma", "valu"],
+                    help="compositing kernels: matrix cores (default) or vector ALU")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for HBM counters)")
     return ap.parse_args()
@@ -80,16 +82,18 @@ def _algorithmic_bytes(stage, n, k, pairs, H, W, D, L, eb):
     return 0
 
 
-def run_form(sc, form, steps, warmup):
+def run_form(sc, form, steps, warmup, variant="mfma"):
     import torch
     from paper_2503_06161_amd import rast
     d, d_rgb, d_feat = _device_inputs(sc, form)
     st = rast.Settings(sh_degree=sc.sh_degree, feat_dim=sc.feat_dim, tile_w=16, tile_h=16,
-                       sh_dtype=form, feat_dtype=form)
+                       sh_dtype=form, feat_dtype=form,
+                       variant=rast.FE_VARIANT_VALU if variant == "valu" else rast.FE_VARIANT_MFMA)
     args = (d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["feat"])
     fwd = rast.render_forward(*args, sc.cam, st, check=True)      # sizes the key buffers
     rep = fwd.report
     st.key_capacity = fwd.cfg.key_capacity
+    st.row_capacity = max(int(rep["rows_needed"]), 1)
     out = dict(rgb=fwd.rgb, feat=fwd.feat, final_T=fwd.final_T, n_contrib=fwd.n_contrib)
     grads = None
     scratch = None
@@ -198,7 +202,7 @@ def main():
     sc = make_scene(WORKLOAD)
     res = {}
     for form in args.forms.split(","):
-        res[form] = run_form(sc, form, args.steps, args.warmup)
+        res[form] = run_form(sc, form, args.steps, args.warmup, args.variant)
     if args.calibrate_copy:
         a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)
@@ -226,7 +230,7 @@ def main():
         "config": {"workload": "640x512 camera (f=512), 300k Gaussians, SH degree 3, D=128 features, "
                                "16x16 tiles, one frame forward+backward", "form": main_form,
                    "gaussians": sc.n, "width": W, "height": H, "feat_dim": D, "sh_degree": L,
-                   "keys": r["keys"], "processed_tile_pairs": r["pairs"]},
+                   "keys": r["keys"], "processed_tile_pairs": r["pairs"], "variant": args.variant},
         "forms": {f: {"frames_per_s": round(v["fps"], 2), "ms_per_step": round(v["ms_per_step"], 4),
                       "stage_ms": {k: round(x, 4) for k, x in v["stage_ms"].items()}} for f, v in res.items()},
         "roofline": {"kernel": stage, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,

@@ -65,7 +65,11 @@ typedef enum fe_status {
   FE_ERR_KEY_OVERFLOW = 4,       /* device: more (tile, Gaussian) keys than
                                     key_capacity; outputs are invalid and
                                     report.keys_needed holds the count needed  */
-  FE_ERR_HIP = 5                 /* a HIP runtime call failed                  */
+  FE_ERR_HIP = 5,                /* a HIP runtime call failed                  */
+  FE_ERR_ROW_OVERFLOW = 6        /* device: the backward needed more partial
+                                    rows than row_capacity; gradients are
+                                    invalid and report.rows_needed holds the
+                                    count needed                               */
 } fe_status;
 
 typedef enum fe_dtype { FE_F32 = 0, FE_BF16 = 1 } fe_dtype;
@@ -92,6 +96,8 @@ typedef struct fe_config {
   float jacobian_clamp;          /* J evaluated at tx/tz clamped to
                                     +-k W / (2 fx) (1.3); 0 disables            */
   int64_t key_capacity;          /* maximum number of (tile, Gaussian) keys    */
+  int64_t row_capacity;          /* backward partial rows (matrix-core variant);
+                                    0 = key_capacity (always sufficient)       */
   uint32_t flags;                /* FE_FLAG_*                                   */
   int32_t variant;               /* compositing kernel variant (FE_VARIANT_*)  */
   void* const* stage_events;     /* optional timing: NULL, or an array of
@@ -114,8 +120,12 @@ typedef struct fe_config {
 
 #define FE_VARIANT_AUTO 0           /* library default                          */
 #define FE_VARIANT_VALU 1           /* vector-ALU blending in both directions   */
+#define FE_VARIANT_MFMA 2           /* D-channel contractions on the matrix cores
+                                       (bf16 parts, exact float32 products)     */
 
-/* Packed Gaussian arrays (device, SoA, contiguous). */
+/* Packed Gaussian arrays (device, SoA, contiguous).  `sh` must be 16-byte
+ * aligned (rows are read with 16-byte loads); the other arrays need their
+ * element alignment.  Misaligned pointers give FE_ERR_INVALID_ARG. */
 typedef struct fe_gaussians {
   int64_t n;
   const float* means;            /* [n][3]                                      */
@@ -152,6 +162,8 @@ typedef struct fe_report {
   int64_t keys_needed;           /* number of (tile, Gaussian) keys the frame has */
   int64_t n_visible;             /* Gaussians that emitted at least one key     */
   int64_t n_culled_nonfinite;    /* Gaussians culled for non-finite parameters  */
+  int64_t rows_needed;           /* sum over tiles of the longest pixel walk
+                                    (matrix-core variant; sizes the backward)   */
 } fe_report;
 
 /* Byte offsets of the regions of a forward state buffer (for tests and
@@ -186,7 +198,11 @@ size_t    fe_state_bytes(const fe_config* cfg, const fe_camera* cam, int64_t n);
 fe_status fe_state_layout_get(const fe_config* cfg, const fe_camera* cam, int64_t n,
                               fe_state_layout* out);
 
-/* Scratch needed by fe_render_backward (host only). */
+/* Scratch needed by fe_render_backward (host only).  With the matrix-core
+ * variant it holds one partial-gradient row of round_up(D + 9, 4) floats for
+ * each (tile, list position) the backward walks; the forward's
+ * report.rows_needed gives the exact count for a frame, and row_capacity
+ * bounds it. */
 size_t    fe_backward_scratch_bytes(const fe_config* cfg, const fe_camera* cam, int64_t n);
 
 /* Forward render of one camera.  `state` (device, state_bytes >=
@@ -207,7 +223,9 @@ fe_status fe_render_backward(const fe_config* cfg, const fe_camera* cam, const f
 
 /* Copy the device report of `state` to the host.  Synchronises `stream`.
  * Returns report->status as the call's status (FE_ERR_KEY_OVERFLOW when the
- * frame needed more keys than key_capacity). */
+ * frame needed more keys than key_capacity, FE_ERR_ROW_OVERFLOW when a
+ * backward of this state needed more rows than row_capacity; a backward may
+ * write this status into the state's report). */
 fe_status fe_read_report(const void* state, size_t state_bytes, fe_report* out, void* stream);
 
 /* ------------------------------------------------------------------------

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfe4dgs_rast.so")
-SOURCES = ["fe_api.hip", "fe_project.hip", "fe_sort.hip", "fe_composite.hip"]
+SOURCES = ["fe_api.hip", "fe_project.hip", "fe_sort.hip", "fe_composite.hip", "fe_composite_mfma.hip", "fe_backward_mfma.hip"]
 ARCH = os.environ.get("FE4DGS_ARCH", "gfx950")
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
@@ -24,6 +24,8 @@ FLAGS = [
     # no packed FP32 instructions in generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
+    # LDS atomics here always have lane-dependent addresses; keep them single instructions
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
 ]
 
 

@@ -25,7 +25,14 @@ bool compute_layout(const fe_config* cfg, const fe_camera* cam, int64_t n, Layou
   L->nscan_blocks = ceil_div(n, kScanChunk);
   int bits = 0;
   while ((1ll << bits) < (int64_t)L->tiles) ++bits;
-  L->tile_passes = (bits + kRadixBits - 1) / kRadixBits;
+  // one 11-bit pass covers up to 2048 tiles; beyond that, 8-bit passes
+  if (bits <= 11) {
+    L->tile_passes = bits > 0 ? 1 : 0;
+    L->tile_bits = bits <= 8 ? 8 : 11;
+  } else {
+    L->tile_passes = (bits + 7) / 8;
+    L->tile_bits = 8;
+  }
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;
@@ -34,7 +41,7 @@ bool compute_layout(const fe_config* cfg, const fe_camera* cam, int64_t n, Layou
   };
   // zeroed at the start of every forward: report, radix totals, ranges
   L->report = take(sizeof(unsigned long long) * 2 * kRepWords);
-  L->totals = take(sizeof(uint32_t) * kRadixBins * (4 + L->tile_passes));
+  L->totals = take(sizeof(uint32_t) * kRadixBinsMax * (3 + L->tile_passes));
   L->ranges = take(sizeof(uint2) * (size_t)L->tiles);
   L->xy = take(sizeof(float2) * n);
   L->conic_o = take(sizeof(float4) * n);
@@ -47,12 +54,17 @@ bool compute_layout(const fe_config* cfg, const fe_camera* cam, int64_t n, Layou
   L->count = take(4 * n);
   L->offsets = take(4 * n);
   L->scan_sums = take(4 * (size_t)(L->nscan_blocks + 1));
-  L->hist_n = take(4 * (size_t)kRadixBins * L->nchunks_n);
+  L->hist_n = take(4 * (size_t)kRadixBinsMax * L->nchunks_n);
   L->tile_a = take(4 * (size_t)L->cap);
   L->gauss_a = take(4 * (size_t)L->cap);
   L->tile_b = take(4 * (size_t)L->cap);
   L->gauss_b = take(4 * (size_t)L->cap);
-  L->hist_k = take(4 * (size_t)kRadixBins * L->nchunks_k);
+  L->hist_k = take(4 * (size_t)(1 << L->tile_bits) * L->nchunks_k);
+  L->tile_maxlast = take(4 * (size_t)L->tiles);
+  L->gofe = take(4 * (size_t)L->cap);
+  L->inv = take(4 * (size_t)L->cap);
+  L->epos = take(4 * (size_t)L->cap);
+  L->eoff = take(4 * n);
   L->total = o;
   return true;
 }
@@ -80,6 +92,11 @@ StateView make_view(const Layout& L, void* base) {
   v.totals = reinterpret_cast<uint32_t*>(b + L.totals);
   v.ranges = reinterpret_cast<uint2*>(b + L.ranges);
   v.report = reinterpret_cast<unsigned long long*>(b + L.report);
+  v.tile_maxlast = reinterpret_cast<uint32_t*>(b + L.tile_maxlast);
+  v.gofe = reinterpret_cast<uint32_t*>(b + L.gofe);
+  v.inv = reinterpret_cast<uint32_t*>(b + L.inv);
+  v.epos = reinterpret_cast<uint32_t*>(b + L.epos);
+  v.eoff = reinterpret_cast<uint32_t*>(b + L.eoff);
   v.n = L.n;
   v.cap = L.cap;
   v.tiles_x = L.tiles_x;
@@ -89,6 +106,7 @@ StateView make_view(const Layout& L, void* base) {
   v.nchunks_k = L.nchunks_k;
   v.nscan_blocks = L.nscan_blocks;
   v.tile_passes = L.tile_passes;
+  v.tile_bits = L.tile_bits;
   return v;
 }
 
@@ -120,6 +138,35 @@ CamConst make_cam_const(const fe_camera* cam, const fe_config* cfg) {
 
 static fe_status hip_status(hipError_t e) { return e == hipSuccess ? FE_OK : FE_ERR_HIP; }
 
+// backward scratch: grad2d [n][12] | row_base [tiles] | scan sums | rows [row_cap][RS]
+struct BwdScratch {
+  size_t grad2d, row_base, sums, rowidx, rows, total;
+  int64_t row_cap;
+};
+
+static bool bwd_scratch_layout(const fe_config* cfg, const fe_camera* cam, int64_t n, BwdScratch* b) {
+  Layout L;
+  if (!compute_layout(cfg, cam, n, &L)) return false;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  b->grad2d = take(sizeof(float) * 12 * (size_t)(n > 0 ? n : 1));
+  b->row_cap = 0;
+  b->row_base = b->sums = b->rowidx = b->rows = o;
+  if (cfg->variant != FE_VARIANT_VALU) {
+    b->row_cap = cfg->row_capacity > 0 ? cfg->row_capacity : cfg->key_capacity;
+    b->row_base = take(sizeof(uint32_t) * ((size_t)L.tiles + 1));
+    b->sums = take(sizeof(uint32_t) * ((size_t)((L.tiles + kScanChunk - 1) / kScanChunk) + 1));
+    b->rowidx = take(sizeof(uint32_t) * (size_t)L.cap);
+    b->rows = take(sizeof(float) * (size_t)backward_row_stride(cfg->feat_dim) * (size_t)b->row_cap);
+  }
+  b->total = o;
+  return true;
+}
+
 // optional per-stage events (recorded on the call's stream)
 static void stage_mark(const fe_config* cfg, int stage, int end, hipStream_t s) {
   if (!cfg->stage_events) return;
@@ -131,7 +178,11 @@ static fe_status check_gaussians(const fe_config* cfg, const fe_gaussians* g) {
   if (!g || g->n < 0) return FE_ERR_INVALID_ARG;
   if (g->n == 0) return FE_OK;
   if (!g->means || !g->scales || !g->quats || !g->opacity || !g->sh || !g->feat) return FE_ERR_INVALID_ARG;
-  (void)cfg;
+  // element alignment everywhere; SH rows are read with 16-byte loads
+  auto misaligned = [](const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) % a) != 0; };
+  if (misaligned(g->means, 4) || misaligned(g->scales, 4) || misaligned(g->quats, 4) || misaligned(g->opacity, 4) ||
+      misaligned(g->sh, 16) || misaligned(g->feat, cfg->feat_dtype == FE_BF16 ? 2 : 4))
+    return FE_ERR_INVALID_ARG;
   return FE_OK;
 }
 
@@ -148,7 +199,8 @@ static fe_status forward_impl(const fe_config* cfg, const fe_camera* cam, const 
   if ((e = launch_sort_and_bin(cfg, v, s)) != hipSuccess) return FE_ERR_HIP;
   stage_mark(cfg, FE_STAGE_SORT, 1, s);
   stage_mark(cfg, FE_STAGE_COMPOSITE, 0, s);
-  e = launch_composite_fwd(cfg, cam, g, v, out, s);
+  e = cfg->variant == FE_VARIANT_VALU ? launch_composite_fwd(cfg, cam, g, v, out, s)
+                                       : launch_composite_fwd_mfma(cfg, cam, g, v, out, s);
   stage_mark(cfg, FE_STAGE_COMPOSITE, 1, s);
   return hip_status(e);
 }
@@ -157,8 +209,33 @@ static fe_status backward_impl(const fe_config* cfg, const fe_camera* cam, const
                                const fe_images* fwd, const void* state, const Layout& L, const float* d_rgb,
                                const float* d_feat, const fe_grads* out, void* scratch, hipStream_t s) {
   StateView v = make_view(L, const_cast<void*>(state));
-  float* grad2d = static_cast<float*>(scratch);
+  BwdScratch bs;
+  bwd_scratch_layout(cfg, cam, g->n, &bs);
+  char* sb = static_cast<char*>(scratch);
+  float* grad2d = reinterpret_cast<float*>(sb + bs.grad2d);
   hipError_t e;
+  if (cfg->variant != FE_VARIANT_VALU) {
+    uint32_t* row_base = reinterpret_cast<uint32_t*>(sb + bs.row_base);
+    float* rows = reinterpret_cast<float*>(sb + bs.rows);
+    if ((e = launch_scan_u32(v.tile_maxlast, row_base, reinterpret_cast<uint32_t*>(sb + bs.sums), v.tiles, s)) !=
+        hipSuccess)
+      return FE_ERR_HIP;
+    stage_mark(cfg, FE_STAGE_COMPOSITE_BWD, 0, s);
+    uint32_t* rowidx = reinterpret_cast<uint32_t*>(sb + bs.rowidx);
+    if ((e = launch_zero_u32(rowidx, (size_t)L.cap, s)) != hipSuccess) return FE_ERR_HIP;
+    if ((e = launch_composite_bwd_mfma(cfg, cam, g, v, fwd, d_rgb, d_feat, row_base, rows, bs.row_cap, rowidx,
+                                       s)) != hipSuccess)
+      return FE_ERR_HIP;
+    stage_mark(cfg, FE_STAGE_COMPOSITE_BWD, 1, s);
+    stage_mark(cfg, FE_STAGE_REDUCE, 0, s);
+    if ((e = launch_reduce_rows(cfg, v, rowidx, rows, grad2d, out->feat, s)) != hipSuccess)
+      return FE_ERR_HIP;
+    stage_mark(cfg, FE_STAGE_REDUCE, 1, s);
+    stage_mark(cfg, FE_STAGE_PROJECT_BWD, 0, s);
+    e = launch_project_bwd(make_cam_const(cam, cfg), cfg, g, v, grad2d, out, s);
+    stage_mark(cfg, FE_STAGE_PROJECT_BWD, 1, s);
+    return hip_status(e);
+  }
   if ((e = launch_zero_u32(reinterpret_cast<uint32_t*>(grad2d), (size_t)12 * g->n, s)) != hipSuccess) return FE_ERR_HIP;
   if (!(cfg->flags & FE_FLAG_NO_ZERO_GRADS)) {
     if ((e = launch_zero_u32(reinterpret_cast<uint32_t*>(out->feat), (size_t)cfg->feat_dim * g->n, s)) != hipSuccess)
@@ -190,6 +267,7 @@ const char* fe_status_string(fe_status s) {
     case FE_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
     case FE_ERR_KEY_OVERFLOW: return "sort key capacity exceeded";
     case FE_ERR_HIP: return "HIP runtime error";
+    case FE_ERR_ROW_OVERFLOW: return "backward row capacity exceeded";
   }
   return "unknown status";
 }
@@ -213,7 +291,8 @@ fe_status fe_validate(const fe_config* cfg, const fe_camera* cam, int64_t n) {
     return FE_ERR_INVALID_ARG;
   if (cfg->key_capacity < 0 || cfg->key_capacity > 0x7FFFFFFFll) return FE_ERR_INVALID_ARG;
   if (n > (int64_t)kScanChunk * kScanTopMax) return FE_ERR_UNSUPPORTED;
-  if (cfg->variant != FE_VARIANT_AUTO && cfg->variant != FE_VARIANT_VALU) return FE_ERR_UNSUPPORTED;
+  if (cfg->variant != FE_VARIANT_AUTO && cfg->variant != FE_VARIANT_VALU && cfg->variant != FE_VARIANT_MFMA)
+    return FE_ERR_UNSUPPORTED;
   return FE_OK;
 }
 
@@ -234,8 +313,8 @@ fe_status fe_state_layout_get(const fe_config* cfg, const fe_camera* cam, int64_
   out->conic_opacity = L.conic_o;
   out->rgb = L.rgb;
   out->box = L.box;
-  out->depth_key = L.dkey_a;
-  out->depth_order = L.didx_a;
+  out->depth_key = L.dkey_b;
+  out->depth_order = L.didx_b;
   out->tile_count = L.count;
   out->sorted_tile = L.tile_a;
   out->sorted_gauss = L.gauss_a;
@@ -245,8 +324,9 @@ fe_status fe_state_layout_get(const fe_config* cfg, const fe_camera* cam, int64_
 }
 
 size_t fe_backward_scratch_bytes(const fe_config* cfg, const fe_camera* cam, int64_t n) {
-  if (fe_validate(cfg, cam, n) != FE_OK) return 0;
-  return (size_t)(n > 0 ? n : 1) * 12 * sizeof(float);
+  BwdScratch b;
+  if (!bwd_scratch_layout(cfg, cam, n, &b)) return 0;
+  return b.total;
 }
 
 fe_status fe_render_forward(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
@@ -291,6 +371,7 @@ fe_status fe_read_report(const void* state, size_t state_bytes, fe_report* out, 
   out->keys_needed = (int64_t)w[kRepKeys];
   out->n_visible = (int64_t)w[kRepVisible];
   out->n_culled_nonfinite = (int64_t)w[kRepNonFinite];
+  out->rows_needed = (int64_t)w[kRepRows];
   return (fe_status)out->status;
 }
 

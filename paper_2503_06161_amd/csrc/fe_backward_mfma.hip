@@ -1,0 +1,537 @@
+// Backward of the per-tile blending with both D-channel contractions on the
+// matrix cores, and the per-Gaussian reduction of the tiles' partial
+// gradients.
+//
+// For a tile and a batch of NB Gaussians (walked back to front), with the
+// upstream feature gradient G [pixels x D] of the tile:
+//   S  = F G^T        s_i(p) = g(p) . f_i           (needed before the walk)
+//   walk per pixel    T_i = T_{i+1} / (1 - alpha_i), w_i = alpha_i T_i,
+//                     dL/dalpha_i = T_i s_i - (sum_{j>i} w_j s_j + T_f s_bg) / (1 - alpha_i)
+//   dF = W^T G        dL/df_i = sum_p w_i(p) g(p)
+// Both contractions run as v_mfma_f32_32x32x16_bf16 with every float32
+// operand split into bf16 parts (G and W into hi + lo, float32 features into
+// hi + mid): the products kept are those of combined order <= 1, so each
+// result carries about 16 significant bits before the float32 accumulation.
+//
+// Partial results are not added into the outputs with device-wide atomics
+// (the eight XCDs keep no common cache, so those run at memory speed).  Each
+// (tile, list position) walked writes one row [dL/df (D), dL/d(u, v, A, B, C,
+// opacity, r, g, b)] into a compact buffer; rows of a tile start at an
+// exclusive scan of the tiles' walk lengths.  A second kernel sums, per
+// Gaussian, the rows of the tiles it was walked in, found through the
+// emit-position -> sorted-position map written by the tile sort.
+#include "fe_common.h"
+
+#include <type_traits>
+
+#pragma clang fp contract(off)
+
+namespace fe {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kNB = 32;
+
+struct BwdArgs {
+  const uint2* ranges;
+  const uint32_t* gauss;
+  const float2* xy;
+  const float4* conic_o;
+  const float4* rgb;
+  const short4* box;
+  const void* feat;
+  const float* final_T;
+  const int32_t* n_contrib;
+  const float* d_rgb;
+  const float* d_feat;
+  const uint32_t* tile_maxlast;
+  const uint32_t* row_base;
+  float* rows;
+  int64_t row_cap;
+  uint32_t* rowidx;          // [cap] 1 + row of each walked pair, by emit position (0: not walked)
+  const uint32_t* epos;      // [cap] emit position of each sorted pair (NULL: identity)
+  unsigned long long* report;
+  float bg[3];
+  int32_t W, H, tile_w, tiles_x, D, RS;
+};
+
+__device__ __forceinline__ bool pair_alpha(float fpx, float fpy, int px, int py, float2 m, float4 co,
+                                           int4 b, float& dx, float& dy, float& G, float& alpha) {
+  dx = fpx - m.x;
+  dy = fpy - m.y;
+  const float q = __builtin_fmaf(co.x * dx, dx, __builtin_fmaf(co.z * dy, dy, 2.0f * co.y * dx * dy));
+  const bool inb = (px >= b.x) & (px <= b.z) & (py >= b.y) & (py <= b.w);
+  if (!(inb && q <= kQMax)) return false;
+  G = __expf(-0.5f * q);
+  alpha = fminf(kAlphaMax, co.w * G);
+  return alpha >= kAlphaMin;
+}
+
+__device__ __forceinline__ void split2(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+// sum of the 16 lanes of each DPP row, complete in lanes 15, 31, 47 and 63
+__device__ __forceinline__ float row_sum16(float v) {
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xF, 0xF, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xF, 0xF, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xF, 0xF, true));
+  return v;
+}
+
+template <typename FT>
+__device__ __forceinline__ float feat_val(const void* p, int64_t i);
+template <>
+__device__ __forceinline__ float feat_val<float>(const void* p, int64_t i) { return static_cast<const float*>(p)[i]; }
+template <>
+__device__ __forceinline__ float feat_val<uint16_t>(const void* p, int64_t i) {
+  return bf16_bits_to_float(static_cast<const uint16_t*>(p)[i]);
+}
+
+template <int DP, typename FT, int NT>
+__global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
+  constexpr bool F32 = std::is_same<FT, float>::value;
+  constexpr int NPF = F32 ? 2 : 1;     // feature planes in GEMM1 (hi, mid)
+  constexpr int CB = DP / 32;
+  constexpr int KS1 = DP / 16;
+  constexpr int NW = NT / 64;
+  constexpr int FROW = DP + 8;         // padded LDS rows (bank spread)
+  constexpr int WROW = 64 + 8;
+  __shared__ float2 s_xy[kNB];
+  __shared__ float4 s_co[kNB];
+  __shared__ float4 s_rgb[kNB];
+  __shared__ int4 s_box[kNB];
+  __shared__ __attribute__((aligned(16))) __bf16 s_f[NPF][kNB][FROW];
+  __shared__ __attribute__((aligned(16))) __bf16 s_w[NW][2][kNB][WROW];
+  __shared__ float s_df[kNB][DP];
+  __shared__ float s_red[12][kNB];
+  __shared__ float s_g[32][NT + 1];    // one 32-channel slice of the tile's upstream gradient
+
+  const int tile = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int tile_h = NT / a.tile_w;
+  const int tx0 = (tile % a.tiles_x) * a.tile_w;
+  const int ty0 = (tile / a.tiles_x) * tile_h;
+  const int px = tx0 + (int)threadIdx.x % a.tile_w;
+  const int py = ty0 + (int)threadIdx.x / a.tile_w;
+  const bool inside = (px < a.W) & (py < a.H);
+  const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+  const int64_t HW = (int64_t)a.W * a.H;
+  const uint2 rg = a.ranges[tile];
+  const uint32_t walk = min(a.tile_maxlast[tile], rg.y - rg.x);
+  const int64_t row0 = a.row_base[tile];
+  if (row0 + walk > (uint64_t)a.row_cap) {
+    if (threadIdx.x == 0) a.report[kRepStatus] = (unsigned long long)FE_ERR_ROW_OVERFLOW;
+    return;   // uniform: nothing of this tile can be stored
+  }
+  if (walk == 0) return;
+
+  // ---- per-pixel state ----
+  float gr0 = 0.f, gr1 = 0.f, gr2 = 0.f;
+  float T = 1.0f;
+  int last = 0;
+  if (inside) {
+    const int64_t p = (int64_t)py * a.W + px;
+    gr0 = a.d_rgb[p];
+    gr1 = a.d_rgb[HW + p];
+    gr2 = a.d_rgb[2 * HW + p];
+    T = a.final_T[p];
+    last = a.n_contrib[p];
+  }
+  float acc = T * ((gr0 * a.bg[0] + gr1 * a.bg[1]) + gr2 * a.bg[2]);
+  int wave_last = last;
+  for (int o = 32; o > 0; o >>= 1) wave_last = max(wave_last, __shfl_xor(wave_last, o, 64));
+
+  // ---- upstream feature gradient of the wave's 64 pixels, in both operand layouts,
+  //      staged through LDS one 32-channel slice at a time (coalesced loads) ----
+  bf16x8 g1[2][KS1][2];   // GEMM1 B: [pixel block][k step][hi, lo]; lane: pixel l%32, channels 8(l/32)+j
+  bf16x8 g2[CB][4][2];    // GEMM2 B: [channel block][k step][hi, lo]; lane: channel l%32, pixels 8(l/32)+j
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < 32 * NT; e += NT) {
+      const int c = e / NT, q = e % NT;
+      const int qx = tx0 + q % a.tile_w, qy = ty0 + q / a.tile_w;
+      const int ch = 32 * cb + c;
+      s_g[c][q] = (ch < a.D && qx < a.W && qy < a.H) ? a.d_feat[ch * HW + (int64_t)qy * a.W + qx] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int pb = 0; pb < 2; ++pb)
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          __bf16 h, l;
+          split2(s_g[16 * s2 + 8 * (lane >> 5) + j][64 * wave + 32 * pb + (lane & 31)], h, l);
+          g1[pb][2 * cb + s2][0][j] = h;
+          g1[pb][2 * cb + s2][1][j] = l;
+        }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        __bf16 h, l;
+        split2(s_g[lane & 31][64 * wave + 16 * s + 8 * (lane >> 5) + j], h, l);
+        g2[cb][s][0][j] = h;
+        g2[cb][s][1][j] = l;
+      }
+  }
+
+  for (int e = threadIdx.x; e < kNB * DP; e += NT) (&s_df[0][0])[e] = 0.f;
+  for (int e = threadIdx.x; e < 12 * kNB; e += NT) (&s_red[0][0])[e] = 0.f;
+
+  const uint32_t end = rg.x + walk;
+  for (uint32_t b1 = end; b1 > rg.x;) {
+    const uint32_t b0 = b1 - rg.x > (uint32_t)kNB ? b1 - kNB : rg.x;
+    const int nb = (int)(b1 - b0);
+    const int pos0 = (int)(b0 - rg.x);
+    __syncthreads();
+    // ---- stage the batch ----
+    for (int t = threadIdx.x; t < kNB; t += NT) {
+      if (t < nb) {
+        const uint32_t g = a.gauss[b0 + t];
+        s_xy[t] = a.xy[g];
+        s_co[t] = a.conic_o[g];
+        s_rgb[t] = a.rgb[g];
+        const short4 b = a.box[g];
+        s_box[t] = make_int4(b.x, b.y, b.z, b.w);
+      }
+    }
+    for (int e = threadIdx.x; e < kNB * (DP / 4); e += NT) {
+      const int i = e / (DP / 4);
+      const int c = (e % (DP / 4)) * 4;
+      const int64_t g = i < nb ? (int64_t)a.gauss[b0 + i] : 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float v = (i < nb && c + j < a.D) ? feat_val<FT>(a.feat, g * a.D + c + j) : 0.f;
+        if constexpr (F32) {
+          __bf16 h, m;
+          split2(v, h, m);
+          s_f[0][i][c + j] = h;
+          s_f[1][i][c + j] = m;
+        } else {
+          s_f[0][i][c + j] = (__bf16)v;   // exact: the value is a bf16
+        }
+      }
+    }
+    __syncthreads();
+    if (wave_last > pos0) {
+      // ---- GEMM1: S^T (Gaussians x pixels) = F (Gaussians x D) . G^T (D x pixels) ----
+      f32x16 s1[2] = {f32x16{}, f32x16{}};
+#pragma unroll
+      for (int s = 0; s < KS1; ++s) {
+        const int kc = 16 * s + 8 * (lane >> 5);
+        bf16x8 fa[NPF];
+#pragma unroll
+        for (int p = 0; p < NPF; ++p) fa[p] = *reinterpret_cast<const bf16x8*>(&s_f[p][lane & 31][kc]);
+#pragma unroll
+        for (int pb = 0; pb < 2; ++pb) {
+          s1[pb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[0], g1[pb][s][0], s1[pb], 0, 0, 0);
+          s1[pb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[0], g1[pb][s][1], s1[pb], 0, 0, 0);
+          if constexpr (F32) s1[pb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[1], g1[pb][s][0], s1[pb], 0, 0, 0);
+        }
+      }
+      // this lane's pixel gets s_i for all 32 Gaussians
+      float S[kNB];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(s1[0][v]), __float_as_uint(s1[1][v]),
+                                                        false, false);
+        S[8 * (v >> 2) + (v & 3)] = __uint_as_float(r[0]);
+        S[8 * (v >> 2) + 4 + (v & 3)] = __uint_as_float(r[1]);
+      }
+      // ---- back-to-front walk of this lane's pixel, in groups of 8 ----
+      // Branch-free so that the independent per-pair work of a group
+      // interleaves; only the transmittance / suffix recurrences are serial.
+      float wv[kNB];
+      constexpr int GR = 8;
+#pragma unroll
+      for (int gi = kNB / GR - 1; gi >= 0; --gi) {
+        float al[GR], Gv[GR], dxv[GR], dyv[GR];
+        bool ct[GR];
+#pragma unroll
+        for (int u = 0; u < GR; ++u) {
+          const int i = gi * GR + u;
+          const float2 m = s_xy[i];
+          const float4 co = s_co[i];
+          const int4 b = s_box[i];
+          const float dx = fpx - m.x, dy = fpy - m.y;
+          const float q = __builtin_fmaf(co.x * dx, dx, __builtin_fmaf(co.z * dy, dy, 2.0f * co.y * dx * dy));
+          const bool inb = (px >= b.x) & (px <= b.z) & (py >= b.y) & (py <= b.w);
+          const float G = __expf(-0.5f * q);
+          const float alpha = fminf(kAlphaMax, co.w * G);
+          ct[u] = (i < nb) & (pos0 + i < last) & inb & (q <= kQMax) & (alpha >= kAlphaMin);
+          al[u] = alpha;
+          Gv[u] = G;
+          dxv[u] = dx;
+          dyv[u] = dy;
+        }
+        float wg[GR], dag[GR];
+#pragma unroll
+        for (int u = GR - 1; u >= 0; --u) {
+          const int i = gi * GR + u;
+          const float4 c = s_rgb[i];
+          const float sv = S[i] + ((gr0 * c.x + gr1 * c.y) + gr2 * c.z);
+          const float inv_om = __builtin_amdgcn_rcpf(1.0f - al[u]);
+          const float Tn = T * inv_om;
+          const float w = al[u] * Tn;
+          const float da = Tn * sv - acc * inv_om;
+          T = ct[u] ? Tn : T;
+          acc = ct[u] ? __builtin_fmaf(w, sv, acc) : acc;
+          wg[u] = ct[u] ? w : 0.f;
+          dag[u] = ct[u] ? da : 0.f;
+        }
+        float red[GR][3];
+#pragma unroll
+        for (int u = 0; u < GR; ++u) {
+          const int i = gi * GR + u;
+          const float4 co = s_co[i];
+          const float opG = co.w * Gv[u];
+          const bool unclamped = opG <= kAlphaMax;
+          const float dq = unclamped ? -0.5f * opG * dag[u] : 0.f;
+          const float dx = dxv[u], dy = dyv[u];
+          float vals[12];
+          vals[0] = -2.0f * dq * (co.x * dx + co.y * dy);
+          vals[1] = -2.0f * dq * (co.y * dx + co.z * dy);
+          vals[2] = dq * dx * dx;
+          vals[3] = dq * 2.0f * dx * dy;
+          vals[4] = dq * dy * dy;
+          vals[5] = unclamped ? Gv[u] * dag[u] : 0.f;
+          vals[6] = wg[u] * gr0;
+          vals[7] = wg[u] * gr1;
+          vals[8] = wg[u] * gr2;
+          vals[9] = 0.f;
+          vals[10] = 0.f;
+          vals[11] = 0.f;
+          wv[i] = wg[u];
+          // sum over the wave's 64 pixels: halve with the 32- and 16-lane
+          // swaps (each lane keeps 3 of the 12 values, summed over 4 lanes),
+          // then a 16-lane row sum; lane 15 of row r holds values 3r..3r+2
+          float h6[6];
+#pragma unroll
+          for (int k = 0; k < 6; ++k) {
+            const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(vals[k]), __float_as_uint(vals[k + 6]),
+                                                            false, false);
+            h6[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+          }
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(h6[k]), __float_as_uint(h6[k + 3]),
+                                                            false, false);
+            red[u][k] = row_sum16(__uint_as_float(r[0]) + __uint_as_float(r[1]));
+          }
+        }
+        if ((lane & 15) == 15) {
+          const int base = 6 * (lane >> 5) + 3 * ((lane >> 4) & 1);
+#pragma unroll
+          for (int u = 0; u < GR; ++u)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) atomicAdd(&s_red[base + k][gi * GR + u], red[u][k]);
+        }
+      }
+      // ---- W^T of the wave into LDS (Gaussian-major, pixels contiguous) ----
+#pragma unroll
+      for (int i = 0; i < kNB; ++i) {
+        __bf16 h, l;
+        split2(wv[i], h, l);
+        s_w[wave][0][i][lane] = h;
+        s_w[wave][1][i][lane] = l;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // ---- GEMM2: dF (Gaussians x D) = W^T (Gaussians x pixels) . G (pixels x D) ----
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        f32x16 d = f32x16{};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int kp = 16 * s + 8 * (lane >> 5);
+          const bf16x8 wh = *reinterpret_cast<const bf16x8*>(&s_w[wave][0][lane & 31][kp]);
+          const bf16x8 wl = *reinterpret_cast<const bf16x8*>(&s_w[wave][1][lane & 31][kp]);
+          d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh, g2[cb][s][0], d, 0, 0, 0);
+          d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh, g2[cb][s][1], d, 0, 0, 0);
+          d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wl, g2[cb][s][0], d, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+          atomicAdd(&s_df[i][32 * cb + (lane & 31)], d[v]);
+        }
+      }
+    }
+    __syncthreads();
+    // ---- rows of this batch: [dL/df (D) | u v A B C o r g b | pad] ----
+    for (int e = threadIdx.x; e < nb * a.RS; e += NT) {
+      const int i = e / a.RS;
+      const int c = e % a.RS;
+      float v = 0.f;
+      if (c < a.D) {
+        v = s_df[i][c];
+        s_df[i][c] = 0.f;
+      } else if (c < a.D + 9) {
+        v = s_red[c - a.D][i];
+        s_red[c - a.D][i] = 0.f;
+      }
+      a.rows[(row0 + pos0 + i) * a.RS + c] = v;
+    }
+    for (int i = threadIdx.x; i < nb; i += NT) {
+      const uint32_t pos = b0 + i;
+      a.rowidx[a.epos ? a.epos[pos] : pos] = (uint32_t)(row0 + pos0 + i + 1);
+    }
+    b1 = b0;
+  }
+}
+
+// ---- per-Gaussian sum of the rows of the tiles it was walked in ----
+struct ReduceArgs {
+  int64_t n;
+  int32_t D, RS;
+  const uint32_t* count;
+  const uint32_t* eoff;
+  const uint32_t* rowidx;       // [cap] 1 + row by emit position, 0 when the pair was not walked
+  const float* rows;
+  const unsigned long long* report;
+  float* grad2d;                // [n][12]
+  float* grad_feat;             // [n][D]
+  int accumulate;
+};
+
+// 16 lanes per Gaussian; each lane owns CPL consecutive channels.  The
+// Gaussian's pairs are contiguous in emit order, so its row indices are one
+// coalesced read.
+template <int CPL>
+__global__ __launch_bounds__(256) void reduce_rows_kernel(ReduceArgs a) {
+  const int sub = threadIdx.x & 15;
+  const int64_t g = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+  const bool live = g < a.n;
+  float accd[CPL];
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) accd[k] = 0.f;
+  float acc9 = 0.f;
+  const bool ok = a.report[kRepStatus] == 0ull;
+  const uint32_t cnt = (live && ok) ? a.count[g] : 0u;
+  const uint32_t e0 = cnt ? a.eoff[g] : 0u;
+  uint32_t cmax = cnt;
+  for (int o = 32; o > 0; o >>= 1) cmax = max(cmax, (uint32_t)__shfl_xor((int)cmax, o, 64));
+  for (uint32_t base = 0; base < cmax; base += 16) {
+    const uint32_t ri = base + sub < cnt ? a.rowidx[e0 + base + sub] : 0u;
+    const unsigned long long m = __ballot(ri != 0u);
+    uint32_t mine = (uint32_t)((m >> (threadIdx.x & 48)) & 0xFFFFull);
+    int most = __popc(mine);
+    for (int o = 32; o > 0; o >>= 1) most = max(most, __shfl_xor(most, o, 64));
+    for (int k = 0; k < most; ++k) {
+      const int b = mine ? __ffs(mine) - 1 : 0;
+      const uint32_t r = (uint32_t)__shfl((int)ri, (int)(threadIdx.x & 48) + b, 64);
+      if (mine != 0u) {
+        const float* src = a.rows + (int64_t)(r - 1) * a.RS;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+          const int ch = sub * CPL + c;
+          if (ch < a.D) accd[c] += src[ch];
+        }
+        if (sub < 9) acc9 += src[a.D + sub];
+        mine &= mine - 1;
+      }
+    }
+  }
+  if (!live) return;
+  float* fo = a.grad_feat + g * a.D;
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) {
+    const int ch = sub * CPL + c;
+    if (ch < a.D) fo[ch] = a.accumulate ? fo[ch] + accd[c] : accd[c];
+  }
+  if (sub < 12) a.grad2d[g * 12 + sub] = sub < 9 ? acc9 : 0.f;
+}
+
+template <int DP, typename FT>
+hipError_t launch_bwd_nt(int nt, const BwdArgs& a, int tiles, hipStream_t s) {
+  switch (nt) {
+    case 64: hipLaunchKernelGGL((composite_bwd_mfma_kernel<DP, FT, 64>), dim3(tiles), dim3(64), 0, s, a); break;
+    case 128: hipLaunchKernelGGL((composite_bwd_mfma_kernel<DP, FT, 128>), dim3(tiles), dim3(128), 0, s, a); break;
+    default: hipLaunchKernelGGL((composite_bwd_mfma_kernel<DP, FT, 256>), dim3(tiles), dim3(256), 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+template <typename FT>
+hipError_t dispatch_bwd(int D, int nt, const BwdArgs& a, int tiles, hipStream_t s) {
+  if (D <= 32) return launch_bwd_nt<32, FT>(nt, a, tiles, s);
+  if (D <= 64) return launch_bwd_nt<64, FT>(nt, a, tiles, s);
+  if (D <= 128) return launch_bwd_nt<128, FT>(nt, a, tiles, s);
+  return launch_bwd_nt<256, FT>(nt, a, tiles, s);
+}
+
+}  // namespace
+
+int backward_row_stride(int D) { return (D + 9 + 3) & ~3; }
+
+hipError_t launch_composite_bwd_mfma(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
+                                     const StateView& v, const fe_images* fwd, const float* d_rgb,
+                                     const float* d_feat, const uint32_t* row_base, float* rows,
+                                     int64_t row_cap, uint32_t* rowidx, hipStream_t s) {
+  if (v.tiles == 0) return hipSuccess;
+  BwdArgs a{};
+  a.ranges = v.ranges;
+  a.gauss = v.gauss_a;
+  a.xy = v.xy;
+  a.conic_o = v.conic_o;
+  a.rgb = v.rgb;
+  a.box = v.box;
+  a.feat = g->feat;
+  a.final_T = fwd->final_T;
+  a.n_contrib = fwd->n_contrib;
+  a.d_rgb = d_rgb;
+  a.d_feat = d_feat;
+  a.tile_maxlast = v.tile_maxlast;
+  a.row_base = row_base;
+  a.rows = rows;
+  a.row_cap = row_cap;
+  a.rowidx = rowidx;
+  a.epos = v.tile_passes > 0 ? v.epos : nullptr;
+  a.report = v.report;
+  for (int k = 0; k < 3; ++k) a.bg[k] = cfg->bg_rgb[k];
+  a.W = cam->width;
+  a.H = cam->height;
+  a.tile_w = cfg->tile_w;
+  a.tiles_x = v.tiles_x;
+  a.D = cfg->feat_dim;
+  a.RS = backward_row_stride(cfg->feat_dim);
+  const int nt = cfg->tile_w * cfg->tile_h;
+  return cfg->feat_dtype == FE_BF16 ? dispatch_bwd<uint16_t>(cfg->feat_dim, nt, a, v.tiles, s)
+                                    : dispatch_bwd<float>(cfg->feat_dim, nt, a, v.tiles, s);
+}
+
+hipError_t launch_reduce_rows(const fe_config* cfg, const StateView& v, const uint32_t* rowidx,
+                              const float* rows, float* grad2d, float* grad_feat, hipStream_t s) {
+  if (v.n == 0) return hipSuccess;
+  ReduceArgs a{};
+  a.n = v.n;
+  a.D = cfg->feat_dim;
+  a.RS = backward_row_stride(cfg->feat_dim);
+  a.count = v.count;
+  a.eoff = v.eoff;
+  a.rowidx = rowidx;
+  a.rows = rows;
+  a.report = v.report;
+  a.grad2d = grad2d;
+  a.grad_feat = grad_feat;
+  a.accumulate = (cfg->flags & FE_FLAG_NO_ZERO_GRADS) ? 1 : 0;
+  const unsigned blocks = (unsigned)((v.n + 15) / 16);
+  const int D = cfg->feat_dim;
+  if (D <= 16) hipLaunchKernelGGL(reduce_rows_kernel<1>, dim3(blocks), dim3(256), 0, s, a);
+  else if (D <= 32) hipLaunchKernelGGL(reduce_rows_kernel<2>, dim3(blocks), dim3(256), 0, s, a);
+  else if (D <= 64) hipLaunchKernelGGL(reduce_rows_kernel<4>, dim3(blocks), dim3(256), 0, s, a);
+  else if (D <= 128) hipLaunchKernelGGL(reduce_rows_kernel<8>, dim3(blocks), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(reduce_rows_kernel<16>, dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace fe

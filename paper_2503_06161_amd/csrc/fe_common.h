@@ -16,9 +16,8 @@ constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kTStop = 1e-4f;
 constexpr float kQMax = 9.0f;
 
-// Radix passes: 8-bit digits, 256 threads x 8 items per chunk.
-constexpr int kRadixBits = 8;
-constexpr int kRadixBins = 256;
+// Radix passes: 8- or 11-bit digits, 256 threads x 8 items per chunk.
+constexpr int kRadixBinsMax = 2048;
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;
 constexpr int kSortChunk = kSortThreads * kSortItems;   // 2048
@@ -30,7 +29,7 @@ constexpr int kScanChunk = kScanThreads * kScanItems;   // 2048
 constexpr int kScanTopMax = kScanThreads * 16;          // block sums scanned by one block
 
 // Report words (unsigned long long) at StateView::report.
-enum ReportWord { kRepStatus = 0, kRepKeys = 1, kRepVisible = 2, kRepNonFinite = 3, kRepWords = 8 };
+enum ReportWord { kRepStatus = 0, kRepKeys = 1, kRepVisible = 2, kRepNonFinite = 3, kRepRows = 4, kRepWords = 8 };
 
 // Device pointers into one frame's forward state plus its derived sizes.
 struct StateView {
@@ -51,8 +50,13 @@ struct StateView {
   uint32_t* tile_b;
   uint32_t* gauss_b;
   uint32_t* hist_k;
-  uint32_t* totals;     // [kRadixBins * (4 + tile_passes)]
+  uint32_t* totals;     // [kRadixBinsMax * (3 + tile_passes)]
   uint2* ranges;
+  uint32_t* tile_maxlast;   // [tiles] largest n_contrib per tile (compositing walk length)
+  uint32_t* gofe;           // [cap] Gaussian of each emitted pair (emit order)
+  uint32_t* inv;            // [cap] sorted position of each emitted pair
+  uint32_t* epos;           // [cap] emit position of each sorted pair
+  uint32_t* eoff;           // [n] first emit position of each Gaussian
   unsigned long long* report;
   // sizes
   int64_t n;
@@ -60,14 +64,15 @@ struct StateView {
   int32_t tiles_x, tiles_y, tiles;
   int32_t nchunks_n, nchunks_k, nscan_blocks;
   int32_t tile_passes;
+  int32_t tile_bits;    // digit width of the tile passes (8 or 11)
 };
 
 struct Layout {
   size_t total;
   size_t xy, conic_o, rgb, box, dkey_a, dkey_b, didx_a, didx_b, count, offsets, scan_sums, hist_n;
-  size_t tile_a, gauss_a, tile_b, gauss_b, hist_k, totals, ranges, report;
+  size_t tile_a, gauss_a, tile_b, gauss_b, hist_k, totals, ranges, report, tile_maxlast, gofe, inv, epos, eoff;
   int64_t n, cap;
-  int32_t tiles_x, tiles_y, tiles, nchunks_n, nchunks_k, nscan_blocks, tile_passes;
+  int32_t tiles_x, tiles_y, tiles, nchunks_n, nchunks_k, nscan_blocks, tile_passes, tile_bits;
 };
 
 // Host helpers (fe_api.cpp).
@@ -94,9 +99,19 @@ hipError_t launch_project_fwd(const CamConst& cc, const fe_config* cfg, const fe
 hipError_t launch_sort_and_bin(const fe_config* cfg, const StateView& v, hipStream_t s);
 hipError_t launch_composite_fwd(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
                                 const StateView& v, const fe_images* out, hipStream_t s);
+hipError_t launch_composite_fwd_mfma(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
+                                     const StateView& v, const fe_images* out, hipStream_t s);
 hipError_t launch_composite_bwd(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
                                 const StateView& v, const fe_images* fwd, const float* d_rgb,
                                 const float* d_feat, float* grad2d, float* grad_feat, hipStream_t s);
+hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, uint32_t* sums, int64_t n, hipStream_t s);
+int backward_row_stride(int D);
+hipError_t launch_composite_bwd_mfma(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
+                                     const StateView& v, const fe_images* fwd, const float* d_rgb,
+                                     const float* d_feat, const uint32_t* row_base, float* rows,
+                                     int64_t row_cap, uint32_t* rowidx, hipStream_t s);
+hipError_t launch_reduce_rows(const fe_config* cfg, const StateView& v, const uint32_t* rowidx,
+                              const float* rows, float* grad2d, float* grad_feat, hipStream_t s);
 hipError_t launch_project_bwd(const CamConst& cc, const fe_config* cfg, const fe_gaussians* g,
                               const StateView& v, const float* grad2d, const fe_grads* out,
                               hipStream_t s);

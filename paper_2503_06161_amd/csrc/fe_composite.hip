@@ -36,6 +36,8 @@ struct CompArgs {
   const float* d_feat;
   float* grad2d;             // [n][12]
   float* grad_feat;          // [n][D]
+  uint32_t* tile_maxlast;    // [tiles]
+  unsigned long long* report;
   float bg[3];
   int32_t W, H, tile_w, tiles_x;
   int32_t D;                 // real feature count
@@ -156,6 +158,16 @@ __global__ __launch_bounds__(NT) void composite_fwd_kernel(CompArgs a) {
       if (k < a.D) a.out_feat[k * HW + p] = Z[k];
     a.out_T[p] = T;
     a.out_n[p] = last;
+  }
+  // per-tile walk length (sizes the matrix-core backward's partial rows)
+  __shared__ int s_maxlast;
+  if (threadIdx.x == 0) s_maxlast = 0;
+  __syncthreads();
+  if (last > 0) atomicMax(&s_maxlast, last);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a.tile_maxlast[tile] = (uint32_t)s_maxlast;
+    if (s_maxlast > 0) atomicAdd(&a.report[kRepRows], (unsigned long long)s_maxlast);
   }
 }
 
@@ -315,6 +327,8 @@ CompArgs make_args(const fe_config* cfg, const fe_camera* cam, const fe_gaussian
   a.rgb = v.rgb;
   a.box = v.box;
   a.feat = g->feat;
+  a.tile_maxlast = v.tile_maxlast;
+  a.report = v.report;
   for (int k = 0; k < 3; ++k) a.bg[k] = cfg->bg_rgb[k];
   a.W = cam->width;
   a.H = cam->height;

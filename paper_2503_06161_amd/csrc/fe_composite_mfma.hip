@@ -1,0 +1,383 @@
+// Per-tile blending with the D-channel contraction on the matrix cores.
+//
+// For one tile and one batch of NB Gaussians in depth order, eq. (8) is a
+// dense contraction: Z[p][c] += sum_i w_i(p) f_i[c], with w_i(p) =
+// alpha_i(p) T_i(p) (zero for skipped or stopped pairs).  The weights are
+// computed per pixel on the vector ALUs, sequentially over the batch (the
+// transmittance recurrence), then the contraction runs as
+// v_mfma_f32_32x32x16_bf16 with the feature matrix as A (channels x
+// Gaussians) and the weights as B (Gaussians x pixels).
+//
+// Exactness: a float32 weight is split without error into three bf16 parts
+// (w = hi + mid + lo; each part carries the next 8 significant bits, so the
+// 24-bit significand is covered exactly).  BF16-stored features are exact
+// bf16; float32 features are split the same way and the six products of
+// combined order <= 2 are accumulated.  Every product of two bf16 values is
+// exact in float32, so the result differs from a float32 dot product only in
+// the order of the float32 additions.
+//
+// Layout: wave w of the workgroup owns tile pixels [64 w, 64 w + 64) in
+// row-major tile order, lane l pixel 64 w + l during the weight pass.  The
+// MFMA B operand wants, per lane l, pixel l % 32 of a 32-pixel block and
+// Gaussians 8 (l / 32) + j; v_permlane32_swap of the weight registers for
+// Gaussians j and 8 + j produces that layout for both pixel blocks at once.
+#include "fe_common.h"
+
+#include <type_traits>
+
+#pragma clang fp contract(off)
+
+namespace fe {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kNB = 32;            // Gaussians per batch
+constexpr int kRowPad = 8;         // bf16 padding per LDS feature row (bank spread)
+constexpr int kRow = kNB + kRowPad;
+
+struct MfmaArgs {
+  const uint2* ranges;
+  const uint32_t* gauss;
+  const float2* xy;
+  const float4* conic_o;
+  const float4* rgb;
+  const short4* box;
+  const void* feat;
+  float* out_rgb;
+  float* out_feat;
+  float* out_T;
+  int32_t* out_n;
+  uint32_t* tile_maxlast;        // [tiles] largest n_contrib of the tile
+  unsigned long long* report;
+  float bg[3];
+  int32_t W, H, tile_w, tiles_x;
+  int32_t D;
+};
+
+__device__ __forceinline__ bool pair_alpha(float fpx, float fpy, int px, int py, float2 m, float4 co,
+                                           int4 b, float& G, float& alpha) {
+  const float dx = fpx - m.x;
+  const float dy = fpy - m.y;
+  const float q = __builtin_fmaf(co.x * dx, dx, __builtin_fmaf(co.z * dy, dy, 2.0f * co.y * dx * dy));
+  const bool inb = (px >= b.x) & (px <= b.z) & (py >= b.y) & (py <= b.w);
+  if (!(inb && q <= kQMax)) return false;
+  G = __expf(-0.5f * q);
+  alpha = fminf(kAlphaMax, co.w * G);
+  return alpha >= kAlphaMin;
+}
+
+__device__ __forceinline__ float bf16_to_f32(__bf16 h) { return (float)h; }
+
+// float32 -> three bf16 parts, hi + mid + lo == x exactly
+__device__ __forceinline__ void split3(float x, __bf16& hi, __bf16& mid, __bf16& lo) {
+  hi = (__bf16)x;
+  const float r1 = x - bf16_to_f32(hi);
+  mid = (__bf16)r1;
+  const float r2 = r1 - bf16_to_f32(mid);
+  lo = (__bf16)r2;
+}
+
+template <typename FT>
+__device__ __forceinline__ void load4(const void* feat, int64_t base, int c, int D, float v[4]);
+
+template <>
+__device__ __forceinline__ void load4<float>(const void* feat, int64_t base, int c, int D, float v[4]) {
+  const float* p = static_cast<const float*>(feat) + base;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) v[j] = c + j < D ? p[c + j] : 0.f;
+}
+
+template <>
+__device__ __forceinline__ void load4<uint16_t>(const void* feat, int64_t base, int c, int D, float v[4]) {
+  const uint16_t* p = static_cast<const uint16_t*>(feat) + base;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) v[j] = c + j < D ? bf16_bits_to_float(p[c + j]) : 0.f;
+}
+
+// occupancy target: two waves per SIMD where everything fits without spills
+// (D <= 32); wider feature rows need the whole register file
+template <int DP>
+constexpr int fwd_waves_per_eu() { return DP <= 32 ? 2 : 1; }
+
+template <int DP, typename FT, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(fwd_waves_per_eu<DP>())))
+void composite_fwd_mfma_kernel(MfmaArgs a) {
+  constexpr int NPL = std::is_same<FT, float>::value ? 3 : 1;   // feature planes (hi, mid, lo)
+  constexpr int CB = DP / 32;                                    // channel blocks
+  __shared__ float2 s_xy[kNB];
+  __shared__ float4 s_co[kNB];
+  __shared__ float4 s_rgb[kNB];
+  __shared__ int4 s_box[kNB];
+  __shared__ __attribute__((aligned(16))) __bf16 s_ft[NPL][DP][kRow];
+  __shared__ int s_maxlast;
+
+  const int tile = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int tile_h = NT / a.tile_w;
+  const int lp = threadIdx.x;                       // pixel of this lane in the weight pass
+  const int px = (tile % a.tiles_x) * a.tile_w + lp % a.tile_w;
+  const int py = (tile / a.tiles_x) * tile_h + lp / a.tile_w;
+  const bool inside = (px < a.W) & (py < a.H);
+  const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+  const uint2 rg = a.ranges[tile];
+
+  float T = 1.0f;
+  float C0 = 0.f, C1 = 0.f, C2 = 0.f;
+  int last = 0;
+  bool done = !inside;
+  f32x16 acc[2][CB];
+#pragma unroll
+  for (int pb = 0; pb < 2; ++pb)
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) acc[pb][cb] = f32x16{};
+  if (threadIdx.x == 0) s_maxlast = 0;
+
+  // Staging is software-pipelined: the Gaussian ids of batch b+2 and the
+  // records / feature rows of batch b+1 are loaded into registers while batch
+  // b is blended, so the global-memory latency overlaps the compute.
+  constexpr int FQ = DP / 4;                               // 4-channel groups per row
+  constexpr int FI = (kNB * FQ + NT - 1) / NT;             // feature groups per thread
+  uint32_t id_n[FI + 1];                                   // ids of the next batch to load
+  float fv[FI][4];                                         // prefetched feature groups
+  float2 p_xy = make_float2(0.f, 0.f);
+  float4 p_co = make_float4(0.f, 0.f, 0.f, 0.f), p_rgb = p_co;
+  short4 p_box = make_short4(1, 1, 0, 0);
+  auto load_ids = [&](uint32_t b0) {
+#pragma unroll
+    for (int k = 0; k < FI; ++k) {
+      const int i = (threadIdx.x + k * NT) / FQ;
+      id_n[k] = (k * NT + (int)threadIdx.x < kNB * FQ && b0 + i < rg.y) ? a.gauss[b0 + i] : 0xFFFFFFFFu;
+    }
+    id_n[FI] = ((int)threadIdx.x < kNB && b0 + threadIdx.x < rg.y) ? a.gauss[b0 + threadIdx.x] : 0xFFFFFFFFu;
+  };
+  auto load_data = [&]() {
+#pragma unroll
+    for (int k = 0; k < FI; ++k) {
+      const int c = ((threadIdx.x + k * NT) % FQ) * 4;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) fv[k][j] = 0.f;
+      if (id_n[k] != 0xFFFFFFFFu) load4<FT>(a.feat, (int64_t)id_n[k] * a.D, c, a.D, fv[k]);
+    }
+    if (id_n[FI] != 0xFFFFFFFFu) {
+      const uint32_t g = id_n[FI];
+      p_xy = a.xy[g];
+      p_co = a.conic_o[g];
+      p_rgb = a.rgb[g];
+      p_box = a.box[g];
+    }
+  };
+  if (rg.x < rg.y) {
+    load_ids(rg.x);
+    load_data();
+    load_ids(rg.x + kNB);
+  }
+  for (uint32_t b0 = rg.x; b0 < rg.y; b0 += kNB) {
+    const int nb = (int)min((uint32_t)kNB, rg.y - b0);
+    if (__syncthreads_count(!done) == 0) break;
+    // ---- stage the batch from registers ----
+    if ((int)threadIdx.x < kNB) {
+      s_xy[threadIdx.x] = p_xy;
+      s_co[threadIdx.x] = p_co;
+      s_rgb[threadIdx.x] = p_rgb;
+      s_box[threadIdx.x] = make_int4(p_box.x, p_box.y, p_box.z, p_box.w);
+    }
+#pragma unroll
+    for (int k = 0; k < FI; ++k) {
+      const int e = threadIdx.x + k * NT;
+      if (e < kNB * FQ) {
+        const int i = e / FQ;
+        const int c = (e % FQ) * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float v = i < nb ? fv[k][j] : 0.f;
+          if constexpr (NPL == 1) {
+            s_ft[0][c + j][i] = (__bf16)v;   // exact: the value is a bf16
+          } else {
+            __bf16 h, m, l;
+            split3(v, h, m, l);
+            s_ft[0][c + j][i] = h;
+            s_ft[1][c + j][i] = m;
+            s_ft[2][c + j][i] = l;
+          }
+        }
+      }
+    }
+    // ---- issue the next batch's loads ----
+    load_data();
+    load_ids(b0 + 2 * kNB);
+    __syncthreads();
+    // ---- weights of this lane's pixel, front to back ----
+    const bool wave_live = __ballot(!done) != 0ull;
+    if (!wave_live) continue;
+    // Per 16 Gaussians (one MFMA k-step): weights branch-free in groups of 8
+    // (the per-pair alphas are independent, only the transmittance recurrence
+    // is serial), then the contraction on the matrix cores.
+    constexpr int GR = 8;
+#pragma unroll
+    for (int s = 0; s < kNB / 16; ++s) {
+      float wv[16];
+#pragma unroll
+      for (int gi = 0; gi < 16 / GR; ++gi) {
+        float al[GR];
+        bool act[GR];
+#pragma unroll
+        for (int u = 0; u < GR; ++u) {
+          const int i = 16 * s + gi * GR + u;
+          const float2 m = s_xy[i];
+          const float4 co = s_co[i];
+          const int4 b = s_box[i];
+          const float dx = fpx - m.x, dy = fpy - m.y;
+          const float q = __builtin_fmaf(co.x * dx, dx, __builtin_fmaf(co.z * dy, dy, 2.0f * co.y * dx * dy));
+          const bool inb = (px >= b.x) & (px <= b.z) & (py >= b.y) & (py <= b.w);
+          const float alpha = fminf(kAlphaMax, co.w * __expf(-0.5f * q));
+          act[u] = (i < nb) & inb & (q <= kQMax) & (alpha >= kAlphaMin);
+          al[u] = alpha;
+        }
+#pragma unroll
+        for (int u = 0; u < GR; ++u) {
+          const int i = 16 * s + gi * GR + u;
+          const float Tn = T * (1.0f - al[u]);
+          const bool live = act[u] & !done;
+          const bool stop = live & (Tn < kTStop);
+          const bool take = live & !stop;
+          done = done | stop;
+          const float w = take ? al[u] * T : 0.f;
+          const float4 c = s_rgb[i];
+          C0 = __builtin_fmaf(w, c.x, C0);
+          C1 = __builtin_fmaf(w, c.y, C1);
+          C2 = __builtin_fmaf(w, c.z, C2);
+          wv[gi * GR + u] = w;
+          T = take ? Tn : T;
+          last = take ? (int)(b0 - rg.x) + i + 1 : last;
+        }
+      }
+      bool any = false;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) any |= wv[i] != 0.f;
+      if (__ballot(any) == 0ull) continue;
+      bf16x8 bw[2][3];   // [pixel block][hi, mid, lo]
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(wv[j]), __float_as_uint(wv[8 + j]), false,
+                                                        false);
+        __bf16 h, m, l;
+        split3(__uint_as_float(r[0]), h, m, l);
+        bw[0][0][j] = h; bw[0][1][j] = m; bw[0][2][j] = l;
+        split3(__uint_as_float(r[1]), h, m, l);
+        bw[1][0][j] = h; bw[1][1][j] = m; bw[1][2][j] = l;
+      }
+      const int krow = 16 * s + 8 * (lane >> 5);
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        const int c = 32 * cb + (lane & 31);
+        bf16x8 fa[NPL];
+#pragma unroll
+        for (int p = 0; p < NPL; ++p) fa[p] = *reinterpret_cast<const bf16x8*>(&s_ft[p][c][krow]);
+#pragma unroll
+        for (int pb = 0; pb < 2; ++pb) {
+          f32x16 z = acc[pb][cb];
+          if constexpr (NPL == 1) {
+            z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[0], bw[pb][0], z, 0, 0, 0);
+            z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[0], bw[pb][1], z, 0, 0, 0);
+            z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[0], bw[pb][2], z, 0, 0, 0);
+          } else {
+            z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[0], bw[pb][0], z, 0, 0, 0);
+            z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[0], bw[pb][1], z, 0, 0, 0);
+            z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[1], bw[pb][0], z, 0, 0, 0);
+            z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[0], bw[pb][2], z, 0, 0, 0);
+            z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[1], bw[pb][1], z, 0, 0, 0);
+            z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[2], bw[pb][0], z, 0, 0, 0);
+          }
+          acc[pb][cb] = z;
+        }
+      }
+    }
+  }
+  // ---- outputs ----
+  const int64_t HW = (int64_t)a.W * a.H;
+  if (inside) {
+    const int64_t p = (int64_t)py * a.W + px;
+    a.out_rgb[p] = __builtin_fmaf(T, a.bg[0], C0);
+    a.out_rgb[HW + p] = __builtin_fmaf(T, a.bg[1], C1);
+    a.out_rgb[2 * HW + p] = __builtin_fmaf(T, a.bg[2], C2);
+    a.out_T[p] = T;
+    a.out_n[p] = last;
+  }
+  // feature image: accumulator row = channel, column = pixel
+#pragma unroll
+  for (int pb = 0; pb < 2; ++pb) {
+    const int lpo = wave * 64 + 32 * pb + (lane & 31);
+    const int ox = (tile % a.tiles_x) * a.tile_w + lpo % a.tile_w;
+    const int oy = (tile / a.tiles_x) * tile_h + lpo / a.tile_w;
+    if (ox < a.W && oy < a.H) {
+      const int64_t p = (int64_t)oy * a.W + ox;
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int c = 32 * cb + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+          if (c < a.D) a.out_feat[c * HW + p] = acc[pb][cb][v];
+        }
+    }
+  }
+  // per-tile walk length (used by the backward to size its partial rows)
+  if (last > 0) atomicMax(&s_maxlast, last);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a.tile_maxlast[tile] = (uint32_t)s_maxlast;
+    if (s_maxlast > 0) atomicAdd(&a.report[kRepRows], (unsigned long long)s_maxlast);
+  }
+}
+
+template <int DP, typename FT>
+hipError_t launch_nt(int nt, const MfmaArgs& a, int tiles, hipStream_t s) {
+  switch (nt) {
+    case 64: hipLaunchKernelGGL((composite_fwd_mfma_kernel<DP, FT, 64>), dim3(tiles), dim3(64), 0, s, a); break;
+    case 128: hipLaunchKernelGGL((composite_fwd_mfma_kernel<DP, FT, 128>), dim3(tiles), dim3(128), 0, s, a); break;
+    default: hipLaunchKernelGGL((composite_fwd_mfma_kernel<DP, FT, 256>), dim3(tiles), dim3(256), 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+template <typename FT>
+hipError_t dispatch(int D, int nt, const MfmaArgs& a, int tiles, hipStream_t s) {
+  if (D <= 32) return launch_nt<32, FT>(nt, a, tiles, s);
+  if (D <= 64) return launch_nt<64, FT>(nt, a, tiles, s);
+  if (D <= 128) return launch_nt<128, FT>(nt, a, tiles, s);
+  return launch_nt<256, FT>(nt, a, tiles, s);
+}
+
+}  // namespace
+
+hipError_t launch_composite_fwd_mfma(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
+                                     const StateView& v, const fe_images* out, hipStream_t s) {
+  if (v.tiles == 0) return hipSuccess;
+  MfmaArgs a{};
+  a.ranges = v.ranges;
+  a.gauss = v.gauss_a;
+  a.xy = v.xy;
+  a.conic_o = v.conic_o;
+  a.rgb = v.rgb;
+  a.box = v.box;
+  a.feat = g->feat;
+  a.out_rgb = out->rgb;
+  a.out_feat = out->feat;
+  a.out_T = out->final_T;
+  a.out_n = out->n_contrib;
+  a.tile_maxlast = v.tile_maxlast;
+  a.report = v.report;
+  for (int k = 0; k < 3; ++k) a.bg[k] = cfg->bg_rgb[k];
+  a.W = cam->width;
+  a.H = cam->height;
+  a.tile_w = cfg->tile_w;
+  a.tiles_x = v.tiles_x;
+  a.D = cfg->feat_dim;
+  const int nt = cfg->tile_w * cfg->tile_h;
+  return cfg->feat_dtype == FE_BF16 ? dispatch<uint16_t>(cfg->feat_dim, nt, a, v.tiles, s)
+                                    : dispatch<float>(cfg->feat_dim, nt, a, v.tiles, s);
+}
+
+}  // namespace fe

@@ -19,6 +19,8 @@
 // colour clamp at 0 and a clamped Jacobian coordinate pass zero.
 #include "fe_common.h"
 
+#include <type_traits>
+
 #pragma clang fp contract(off)
 
 namespace fe {
@@ -105,6 +107,40 @@ __device__ __forceinline__ void sh_basis_grad(double x, double y, double z, cons
       gx += kC3e * (3.0 * xx - 3.0 * yy) * c[15];
       gy -= 6.0 * kC3e * x * y * c[15];
     }
+  }
+}
+
+// One Gaussian's SH row [(L+1)^2][3] as floats.  Degree 3 rows (96 B in
+// bf16, 192 B in float32) are read with 16-byte loads; smaller rows are not
+// 16-byte aligned in general and are read element by element.
+template <int L, typename ShT>
+__device__ __forceinline__ void load_sh_row(const void* sh, int64_t i, float* out) {
+  constexpr int K3 = 3 * (L + 1) * (L + 1);
+  if constexpr (L == 3 && std::is_same<ShT, uint16_t>::value) {
+    const uint4* p = reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(sh) + i * K3);
+#pragma unroll
+    for (int v = 0; v < K3 / 8; ++v) {
+      const uint4 q = p[v];
+      const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        out[8 * v + 2 * h] = __uint_as_float(w[h] << 16);
+        out[8 * v + 2 * h + 1] = __uint_as_float(w[h] & 0xFFFF0000u);
+      }
+    }
+  } else if constexpr (L == 3) {
+    const float4* p = reinterpret_cast<const float4*>(static_cast<const float*>(sh) + i * K3);
+#pragma unroll
+    for (int v = 0; v < K3 / 4; ++v) {
+      const float4 q = p[v];
+      out[4 * v] = q.x;
+      out[4 * v + 1] = q.y;
+      out[4 * v + 2] = q.z;
+      out[4 * v + 3] = q.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < K3; ++k) out[k] = load_as_float<ShT>(sh, i * K3 + k);
   }
 }
 
@@ -258,11 +294,12 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(ProjArgs a) {
           double Y[16];
           sh_basis<L>(dx / dn, dy / dn, dz / dn, Y);
           constexpr int K = (L + 1) * (L + 1);
+          float shr[3 * K];
+          load_sh_row<L, ShT>(a.sh, i, shr);
           double col[3] = {0.5, 0.5, 0.5};
           double acc[3] = {0.0, 0.0, 0.0};
           for (int k = 0; k < K; ++k)
-            for (int ch = 0; ch < 3; ++ch)
-              acc[ch] += load_as_float<ShT>(a.sh, (i * K + k) * 3 + ch) * Y[k];
+            for (int ch = 0; ch < 3; ++ch) acc[ch] += (double)shr[k * 3 + ch] * Y[k];
           for (int ch = 0; ch < 3; ++ch) col[ch] = fmax(acc[ch] + 0.5, 0.0);
           rgb = make_float4((float)col[0], (float)col[1], (float)col[2], 0.f);
           if (i0 <= i1 && j0 <= j1 && isfinite(G.u) && isfinite(G.v)) {
@@ -282,7 +319,6 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(ProjArgs a) {
     a.v.rgb[i] = rgb;
     a.v.box[i] = box;
     a.v.dkey_a[i] = dkey;
-    a.v.didx_a[i] = (uint32_t)i;
     a.v.count[i] = count;
   }
   // wave-aggregated report counters
@@ -423,12 +459,14 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjBwdArgs a) {
     const double ux = dx / dn, uy = dy / dn, uz = dz / dn;
     double Y[16];
     sh_basis<L>(ux, uy, uz, Y);
+    float shr[3 * K];
+    load_sh_row<L, ShT>(a.sh, i, shr);
     double gdx = 0.0, gdy = 0.0, gdz = 0.0;
     for (int ch = 0; ch < 3; ++ch) {
       double raw = 0.0;
       double cf[16];
       for (int k = 0; k < K; ++k) {
-        cf[k] = load_as_float<ShT>(a.sh, (i * K + k) * 3 + ch);
+        cf[k] = shr[k * 3 + ch];
         raw += cf[k] * Y[k];
       }
       raw += 0.5;
@@ -453,7 +491,20 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjBwdArgs a) {
   for (int k = 0; k < 3; ++k) put(a.g_scales + 3 * i + k, gs[k]);
   for (int k = 0; k < 4; ++k) put(a.g_quats + 4 * i + k, gq[k]);
   put(a.g_opacity + i, gop);
-  for (int k = 0; k < K * 3; ++k) put(a.g_sh + i * K * 3 + k, gsh[k]);
+  if constexpr (L == 3) {
+    float4* q = reinterpret_cast<float4*>(a.g_sh + i * K * 3);
+#pragma unroll
+    for (int v = 0; v < K * 3 / 4; ++v) {
+      float4 o = make_float4((float)gsh[4 * v], (float)gsh[4 * v + 1], (float)gsh[4 * v + 2], (float)gsh[4 * v + 3]);
+      if (a.accumulate) {
+        const float4 p = q[v];
+        o.x += p.x; o.y += p.y; o.z += p.z; o.w += p.w;
+      }
+      q[v] = o;
+    }
+  } else {
+    for (int k = 0; k < K * 3; ++k) put(a.g_sh + i * K * 3 + k, gsh[k]);
+  }
   if (a.g_means2d) {
     put(a.g_means2d + 2 * i, gu);
     put(a.g_means2d + 2 * i + 1, gv);

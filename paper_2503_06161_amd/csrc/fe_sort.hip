@@ -131,9 +131,12 @@ __global__ __launch_bounds__(kScanThreads) void scan_add_kernel(uint32_t* out, c
 // ---- radix pass ----
 struct RadixArgs {
   const uint32_t* keys_in;
-  const uint32_t* vals_in;
+  const uint32_t* vals_in;           // NULL: the value is the item's input position
   uint32_t* keys_out;
   uint32_t* vals_out;
+  const uint32_t* gather;            // optional: write gather[val] instead of val ...
+  uint32_t* inv;                     // ... and inv[val] = output position
+  uint32_t* epos;                    // ... and epos[output position] = val
   const unsigned long long* n_dev;   // item count on the device (may be NULL)
   int64_t n_const;                   // used when n_dev is NULL
   int64_t cap;                       // upper bound on the item count
@@ -149,59 +152,67 @@ __device__ __forceinline__ int64_t radix_count(const RadixArgs& a) {
   return k > (unsigned long long)a.cap ? 0 : (int64_t)k;   // overflow: nothing is valid
 }
 
+template <int BITS>
 __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(RadixArgs a) {
-  __shared__ uint32_t h[kRadixBins];
+  constexpr int BINS = 1 << BITS;
+  __shared__ uint32_t h[BINS];
   const int64_t n = radix_count(a);
-  h[threadIdx.x] = 0;
-  __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kSortChunk;
-  if (base < n) {
+  if (base >= n) return;   // chunks past the item count are never read
+  for (int b = threadIdx.x; b < BINS; b += kSortThreads) h[b] = 0;
+  __syncthreads();
 #pragma unroll
-    for (int k = 0; k < kSortItems; ++k) {
-      const int64_t i = base + (int64_t)k * kSortThreads + threadIdx.x;
-      if (i < n) atomicAdd(&h[(a.keys_in[i] >> a.shift) & (kRadixBins - 1)], 1u);
-    }
+  for (int k = 0; k < kSortItems; ++k) {
+    const int64_t i = base + (int64_t)k * kSortThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[(a.keys_in[i] >> a.shift) & (BINS - 1)], 1u);
   }
   __syncthreads();
-  const uint32_t c = h[threadIdx.x];
-  a.hist[(size_t)threadIdx.x * a.nchunks + blockIdx.x] = c;
-  if (c) atomicAdd(&a.totals[threadIdx.x], c);
+  for (int b = threadIdx.x; b < BINS; b += kSortThreads) {
+    const uint32_t c = h[b];
+    a.hist[(size_t)b * a.nchunks + blockIdx.x] = c;
+    if (c) atomicAdd(&a.totals[b], c);
+  }
 }
 
-// one block per digit: exclusive scan of its row, offset by the digit's base
-__global__ __launch_bounds__(kScanThreads) void radix_scan_kernel(uint32_t* hist, const uint32_t* totals,
-                                                                 int32_t nchunks) {
+// one block per digit: exclusive scan of its row over the chunks in use,
+// offset by the digit's base (sum of the totals of the smaller digits)
+template <int BITS>
+__global__ __launch_bounds__(kScanThreads) void radix_scan_kernel(RadixArgs a) {
   __shared__ uint32_t s_warp[4];
   __shared__ uint32_t s_carry;
   const int bin = blockIdx.x;
-  // base = sum of the totals of the smaller digits
-  uint32_t t = threadIdx.x < (unsigned)bin ? totals[threadIdx.x] : 0u;
+  const int64_t n = radix_count(a);
+  const int used = (int)((n + kSortChunk - 1) / kSortChunk);
+  uint32_t t = 0;
+  for (int b = threadIdx.x; b < bin; b += kScanThreads) t += a.totals[b];
   uint32_t tot;
   (void)block_exclusive_scan(t, s_warp, tot);
   if (threadIdx.x == 0) s_carry = tot;
   __syncthreads();
-  uint32_t* row = hist + (size_t)bin * nchunks;
-  for (int start = 0; start < nchunks; start += kScanThreads) {
+  uint32_t* row = a.hist + (size_t)bin * a.nchunks;
+  for (int start = 0; start < used; start += kScanThreads) {
     const int i = start + threadIdx.x;
-    const uint32_t x = i < nchunks ? row[i] : 0u;
+    const uint32_t x = i < used ? row[i] : 0u;
     uint32_t total;
     const uint32_t ex = block_exclusive_scan(x, s_warp, total);
     const uint32_t carry = s_carry;
-    if (i < nchunks) row[i] = carry + ex;
+    if (i < used) row[i] = carry + ex;
     __syncthreads();
     if (threadIdx.x == 0) s_carry = carry + total;
     __syncthreads();
   }
 }
 
+template <int BITS>
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(RadixArgs a) {
-  __shared__ uint32_t cnt[4][kRadixBins];
+  constexpr int BINS = 1 << BITS;
+  __shared__ uint32_t cnt[4][BINS];
   const int64_t n = radix_count(a);
   const int64_t base = (int64_t)blockIdx.x * kSortChunk;
   if (base >= n) return;   // uniform per block
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  for (int k = threadIdx.x; k < 4 * kRadixBins; k += kSortThreads) (&cnt[0][0])[k] = 0u;
+  for (int k = threadIdx.x; k < 4 * BINS; k += kSortThreads) (&cnt[0][0])[k] = 0u;
   __syncthreads();
   uint32_t key[kSortItems], val[kSortItems], rank[kSortItems], dig[kSortItems];
   const int64_t wbase = base + (int64_t)wave * (kSortChunk / 4);
@@ -210,12 +221,12 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(RadixArgs a
     const int64_t i = wbase + (int64_t)j * 64 + lane;
     const bool valid = i < n;
     key[j] = valid ? a.keys_in[i] : 0u;
-    val[j] = valid ? a.vals_in[i] : 0u;
-    const uint32_t d = (key[j] >> a.shift) & (kRadixBins - 1);
+    val[j] = valid ? (a.vals_in ? a.vals_in[i] : (uint32_t)i) : 0u;
+    const uint32_t d = (key[j] >> a.shift) & (BINS - 1);
     dig[j] = d;
     unsigned long long m = __ballot(valid);
 #pragma unroll
-    for (int b = 0; b < kRadixBits; ++b) {
+    for (int b = 0; b < BITS; ++b) {
       const bool bit = (d >> b) & 1u;
       const unsigned long long bb = __ballot(bit);
       m &= bit ? bb : ~bb;
@@ -231,8 +242,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(RadixArgs a
   }
   __syncthreads();
   // per-digit offsets of the four wavefronts' sub-chunks
-  {
-    const int d = threadIdx.x;
+  for (int d = threadIdx.x; d < BINS; d += kSortThreads) {
     uint32_t o = a.hist[(size_t)d * a.nchunks + blockIdx.x];
     for (int w = 0; w < 4; ++w) {
       const uint32_t c = cnt[w][d];
@@ -248,7 +258,13 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(RadixArgs a
       const uint32_t pos = cnt[wave][dig[j]] + rank[j];
       if (pos < (uint64_t)n) {   // always true for a consistent histogram; guards the write
         if (a.keys_out) a.keys_out[pos] = key[j];
-        a.vals_out[pos] = val[j];
+        if (a.gather) {
+          a.vals_out[pos] = a.gather[val[j]];
+          a.inv[val[j]] = pos;
+          a.epos[pos] = val[j];
+        } else {
+          a.vals_out[pos] = val[j];
+        }
       }
     }
   }
@@ -264,6 +280,7 @@ struct EmitArgs {
   unsigned long long* report;
   uint32_t* tile_out;
   uint32_t* gauss_out;
+  uint32_t* eoff;            // [n] first emit position of each Gaussian
   int64_t n;
   int64_t cap;
   int32_t tile_w, tile_h, tiles_x;
@@ -282,6 +299,7 @@ __global__ __launch_bounds__(256) void emit_kernel(EmitArgs a) {
   if (c == 0) return;
   uint32_t off = a.offsets[s];
   if ((uint64_t)off + c > (uint64_t)a.cap) return;
+  a.eoff[g] = off;
   const short4 b = a.box[g];
   const int tx0 = b.x / a.tile_w, tx1 = b.z / a.tile_w;
   const int ty0 = b.y / a.tile_h, ty1 = b.w / a.tile_h;
@@ -316,16 +334,20 @@ hipError_t scan_u32(const uint32_t* in, const uint32_t* gather, uint32_t* out, u
   return hipGetLastError();
 }
 
+template <int BITS>
 hipError_t radix_pass(RadixArgs a, hipStream_t s) {
   if (a.nchunks == 0) return hipSuccess;
-  hipLaunchKernelGGL(radix_hist_kernel, dim3(a.nchunks), dim3(kSortThreads), 0, s, a);
-  hipLaunchKernelGGL(radix_scan_kernel, dim3(kRadixBins), dim3(kScanThreads), 0, s, a.hist,
-                     (const uint32_t*)a.totals, a.nchunks);
-  hipLaunchKernelGGL(radix_scatter_kernel, dim3(a.nchunks), dim3(kSortThreads), 0, s, a);
+  hipLaunchKernelGGL(radix_hist_kernel<BITS>, dim3(a.nchunks), dim3(kSortThreads), 0, s, a);
+  hipLaunchKernelGGL(radix_scan_kernel<BITS>, dim3(1 << BITS), dim3(kScanThreads), 0, s, a);
+  hipLaunchKernelGGL(radix_scatter_kernel<BITS>, dim3(a.nchunks), dim3(kSortThreads), 0, s, a);
   return hipGetLastError();
 }
 
 }  // namespace
+
+hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, uint32_t* sums, int64_t n, hipStream_t s) {
+  return scan_u32(in, nullptr, out, sums, nullptr, n, s);
+}
 
 hipError_t launch_zero_u32(uint32_t* p, size_t count, hipStream_t s) {
   if (count == 0) return hipSuccess;
@@ -338,31 +360,36 @@ hipError_t launch_zero_u32(uint32_t* p, size_t count, hipStream_t s) {
 hipError_t launch_sort_and_bin(const fe_config* cfg, const StateView& v, hipStream_t s) {
   hipError_t e;
   if (v.n == 0) return hipSuccess;
-  // 1. depth sort of all n Gaussians (A -> B -> A -> B -> A)
-  uint32_t* ka = v.dkey_a;
-  uint32_t* kb = v.dkey_b;
-  uint32_t* ia = v.didx_a;
-  uint32_t* ib = v.didx_b;
-  for (int p = 0; p < 4; ++p) {
-    RadixArgs a{ka, ia, kb, ib, nullptr, v.n, v.n, v.hist_n, v.totals + p * kRadixBins, v.nchunks_n, p * kRadixBits};
-    if ((e = radix_pass(a, s)) != hipSuccess) return e;
-    uint32_t* t = ka; ka = kb; kb = t;
-    t = ia; ia = ib; ib = t;
+  // 1. depth sort of all n Gaussians: three 11-bit passes (A -> B -> A -> B);
+  //    the first pass takes the implicit index as value
+  {
+    RadixArgs a0{v.dkey_a, nullptr, v.dkey_b, v.didx_b, nullptr, nullptr, nullptr, nullptr, v.n, v.n, v.hist_n,
+                 v.totals, v.nchunks_n, 0};
+    if ((e = radix_pass<11>(a0, s)) != hipSuccess) return e;
+    RadixArgs a1{v.dkey_b, v.didx_b, v.dkey_a, v.didx_a, nullptr, nullptr, nullptr, nullptr, v.n, v.n, v.hist_n,
+                 v.totals + kRadixBinsMax, v.nchunks_n, 11};
+    if ((e = radix_pass<11>(a1, s)) != hipSuccess) return e;
+    RadixArgs a2{v.dkey_a, v.didx_a, v.dkey_b, v.didx_b, nullptr, nullptr, nullptr, nullptr, v.n, v.n, v.hist_n,
+                 v.totals + 2 * kRadixBinsMax, v.nchunks_n, 22};
+    if ((e = radix_pass<11>(a2, s)) != hipSuccess) return e;
   }
   // 2. offsets of each Gaussian's pairs, in depth order; 64-bit total -> report
   unsigned long long* total = v.report + kRepWords;   // scratch word after the report
-  if ((e = scan_u32(v.count, v.didx_a, v.offsets, v.scan_sums, total, v.n, s)) != hipSuccess) return e;
-  // 3. emit; the buffer is chosen so that the last tile pass ends in tile_a / gauss_a
+  if ((e = scan_u32(v.count, v.didx_b, v.offsets, v.scan_sums, total, v.n, s)) != hipSuccess) return e;
+  // 3. emit (tile id, Gaussian) pairs: tile ids into the buffer from which the
+  //    last tile pass ends in tile_a, Gaussian ids into gofe (or straight into
+  //    gauss_a when there is a single tile and no pass)
   const bool odd = (v.tile_passes & 1) != 0;
   EmitArgs ea;
-  ea.didx = v.didx_a;
+  ea.didx = v.didx_b;
   ea.count = v.count;
   ea.offsets = v.offsets;
   ea.box = v.box;
   ea.total = total;
   ea.report = v.report;
   ea.tile_out = odd ? v.tile_b : v.tile_a;
-  ea.gauss_out = odd ? v.gauss_b : v.gauss_a;
+  ea.gauss_out = v.tile_passes == 0 ? v.gauss_a : v.gofe;
+  ea.eoff = v.eoff;
   ea.n = v.n;
   ea.cap = v.cap;
   ea.tile_w = cfg->tile_w;
@@ -370,17 +397,21 @@ hipError_t launch_sort_and_bin(const fe_config* cfg, const StateView& v, hipStre
   ea.tiles_x = v.tiles_x;
   hipLaunchKernelGGL(emit_kernel, dim3((unsigned)((v.n + 255) / 256)), dim3(256), 0, s, ea);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  // 4. stable passes on the tile digits
+  // 4. stable passes on the tile digits.  The value carried is the emit
+  //    position; the last pass writes the Gaussian index it maps to and the
+  //    inverse map emit position -> sorted position.
   uint32_t* tk_in = ea.tile_out;
-  uint32_t* tg_in = ea.gauss_out;
   uint32_t* tk_out = odd ? v.tile_a : v.tile_b;
-  uint32_t* tg_out = odd ? v.gauss_a : v.gauss_b;
+  const uint32_t* tv_in = nullptr;
   for (int p = 0; p < v.tile_passes; ++p) {
-    RadixArgs a{tk_in, tg_in, tk_out, tg_out, total, 0, v.cap, v.hist_k,
-                v.totals + (4 + p) * kRadixBins, v.nchunks_k, p * kRadixBits};
-    if ((e = radix_pass(a, s)) != hipSuccess) return e;
+    const bool final_pass = p == v.tile_passes - 1;
+    uint32_t* tv_out = final_pass ? v.gauss_a : v.gauss_b;
+    RadixArgs a{tk_in, tv_in, tk_out, tv_out, final_pass ? v.gofe : nullptr, final_pass ? v.inv : nullptr,
+                final_pass ? v.epos : nullptr, total, 0, v.cap, v.hist_k, v.totals + (3 + p) * kRadixBinsMax,
+                v.nchunks_k, p * v.tile_bits};
+    if ((e = (v.tile_bits == 11 ? radix_pass<11>(a, s) : radix_pass<8>(a, s))) != hipSuccess) return e;
     uint32_t* t = tk_in; tk_in = tk_out; tk_out = t;
-    t = tg_in; tg_in = tg_out; tg_out = t;
+    tv_in = tv_out;
   }
   // 5. per-tile ranges (ranges were zeroed with the state's counters)
   const unsigned rb = (unsigned)((v.cap + 255) / 256);

@@ -17,10 +17,11 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfe4dgs_rast.so")
 
-FE_OK, FE_ERR_INVALID_ARG, FE_ERR_UNSUPPORTED, FE_ERR_WORKSPACE_TOO_SMALL, FE_ERR_KEY_OVERFLOW, FE_ERR_HIP = range(6)
+(FE_OK, FE_ERR_INVALID_ARG, FE_ERR_UNSUPPORTED, FE_ERR_WORKSPACE_TOO_SMALL, FE_ERR_KEY_OVERFLOW, FE_ERR_HIP,
+ FE_ERR_ROW_OVERFLOW) = range(7)
 FE_F32, FE_BF16 = 0, 1
 FE_FLAG_NO_ZERO_GRADS = 1
-FE_VARIANT_AUTO, FE_VARIANT_VALU = 0, 1
+FE_VARIANT_AUTO, FE_VARIANT_VALU, FE_VARIANT_MFMA = 0, 1, 2
 FE_MODE_FORWARD, FE_MODE_BACKWARD, FE_MODE_FORWARD_BACKWARD = 1, 2, 3
 STAGES = ("project", "sort", "composite", "composite_bwd", "reduce", "project_bwd")
 
@@ -41,7 +42,8 @@ class fe_config(C.Structure):
     _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("threads_per_tile", C.c_int32),
                 ("sh_degree", C.c_int32), ("feat_dim", C.c_int32), ("sh_dtype", C.c_int32),
                 ("feat_dtype", C.c_int32), ("bg_rgb", C.c_float * 3), ("cov2d_dilation", C.c_float),
-                ("jacobian_clamp", C.c_float), ("key_capacity", C.c_int64), ("flags", C.c_uint32),
+                ("jacobian_clamp", C.c_float), ("key_capacity", C.c_int64), ("row_capacity", C.c_int64),
+                ("flags", C.c_uint32),
                 ("variant", C.c_int32), ("stage_events", C.c_void_p)]
 
 
@@ -61,7 +63,7 @@ class fe_grads(C.Structure):
 
 class fe_report(C.Structure):
     _fields_ = [("status", C.c_int32), ("reserved", C.c_int32), ("keys_needed", C.c_int64),
-                ("n_visible", C.c_int64), ("n_culled_nonfinite", C.c_int64)]
+                ("n_visible", C.c_int64), ("n_culled_nonfinite", C.c_int64), ("rows_needed", C.c_int64)]
 
 
 class fe_state_layout(C.Structure):
@@ -137,11 +139,12 @@ class Settings:
     dilation: float = 0.3
     jacobian_clamp: float = 1.3
     key_capacity: int | None = None
+    row_capacity: int | None = None  # None: the forward's reported need (or key_capacity)
     variant: int = FE_VARIANT_AUTO
     flags: int = 0
     stage_events: object = None     # optional ctypes array of 2*len(STAGES) hipEvent_t handles
 
-    def to_c(self, cap: int) -> fe_config:
+    def to_c(self, cap: int, rows: int = 0) -> fe_config:
         c = fe_config()
         c.tile_w, c.tile_h, c.threads_per_tile = self.tile_w, self.tile_h, 0
         c.sh_degree, c.feat_dim = self.sh_degree, self.feat_dim
@@ -152,6 +155,7 @@ class Settings:
         c.cov2d_dilation = self.dilation
         c.jacobian_clamp = self.jacobian_clamp
         c.key_capacity = int(cap)
+        c.row_capacity = int(rows)
         c.flags = self.flags
         c.variant = self.variant
         c.stage_events = C.cast(self.stage_events, C.c_void_p) if self.stage_events is not None else None
@@ -230,7 +234,7 @@ def read_report(state: torch.Tensor, stream=None) -> dict:
     r = fe_report()
     lib.fe_read_report(C.c_void_p(state.data_ptr()), state.numel(), C.byref(r), C.c_void_p(_stream_handle(stream)))
     return dict(status=r.status, keys_needed=r.keys_needed, n_visible=r.n_visible,
-                n_culled_nonfinite=r.n_culled_nonfinite)
+                n_culled_nonfinite=r.n_culled_nonfinite, rows_needed=r.rows_needed)
 
 
 def state_layout(cam, st: Settings, n: int, cap: int) -> dict:
@@ -301,13 +305,19 @@ def render_backward(fwd: ForwardResult, means, scales, quats, opacity, sh, feat,
                      sh=torch.empty(n, K, 3, device=dev), feat=torch.empty(n, D, device=dev))
         if want_means2d:
             grads["means2d"] = torch.empty(n, 2, device=dev)
-    sc_bytes = lib.fe_backward_scratch_bytes(C.byref(fwd.cfg), C.byref(fwd.cam), n)
+    cfg = fe_config.from_buffer_copy(fwd.cfg)
+    cfg.stage_events = C.cast(st.stage_events, C.c_void_p) if st.stage_events is not None else None
+    if st.row_capacity is not None:
+        cfg.row_capacity = int(st.row_capacity)
+    elif fwd.report is not None:
+        cfg.row_capacity = max(int(fwd.report["rows_needed"]), 1)
+    sc_bytes = lib.fe_backward_scratch_bytes(C.byref(cfg), C.byref(fwd.cam), n)
     if scratch is None or scratch.numel() < sc_bytes:
         scratch = torch.empty(max(sc_bytes, 1), dtype=torch.uint8, device=dev)
     gr = fe_grads(_ptr(grads["means"]), _ptr(grads["scales"]), _ptr(grads["quats"]), _ptr(grads["opacity"]),
                   _ptr(grads["sh"]), _ptr(grads["feat"]), _ptr(grads.get("means2d")))
     im = fe_images(_ptr(fwd.rgb), _ptr(fwd.feat), _ptr(fwd.final_T), _ptr(fwd.n_contrib))
-    _check(lib.fe_render_backward(C.byref(fwd.cfg), C.byref(fwd.cam), C.byref(g), C.byref(im),
+    _check(lib.fe_render_backward(C.byref(cfg), C.byref(fwd.cam), C.byref(g), C.byref(im),
                                   C.c_void_p(fwd.state.data_ptr()), fwd.state.numel(),
                                   C.c_void_p(d_rgb.data_ptr()), C.c_void_p(d_feat.data_ptr()), C.byref(gr),
                                   C.c_void_p(scratch.data_ptr()), scratch.numel(),
