@@ -39,6 +39,7 @@ def _parse():
     ap.add_argument("--forms", default="bf16,f32")
     ap.add_argument("--variant", default="mfma", choices=["mfma", "valu"],
                     help="compositing kernels: matrix cores (default) or vector ALU")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 16-timestamp graph form")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for HBM counters)")
     return ap.parse_args()
@@ -137,6 +138,44 @@ def run_form(sc, form, steps, warmup, variant="mfma"):
     rep2 = rast.read_report(fwd.state)
     return dict(ms_per_step=1e3 * (t1 - t0) / steps, fps=steps / (t1 - t0), stage_ms=stage_ms, pairs=pairs,
                 keys=int(rep2["keys_needed"]), report=rep, eb=2 if form == "bf16" else 4)
+
+
+def run_batched(steps, warmup):
+    """16 timestamps of one deforming scene (50k-200k Gaussians per frame,
+    D=64 BF16, 640x512), forward+backward of all frames as one graph replay."""
+    import numpy as np
+    import torch
+    from paper_2503_06161_amd import rast
+    from paper_2503_06161_amd.batch import BatchRenderer
+    from paper_2503_06161_amd.scenes import batched_frames
+    sc, fr = batched_frames()
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    frames, cams = [], []
+    for f in fr:
+        n = f["n"]
+        frames.append(dict(means=t(f["means"]), scales=t(sc.scales[:n]), quats=t(sc.quats[:n]),
+                           opacity=t(sc.opacity[:n]), sh=t(sc.sh[:n]).bfloat16().contiguous(),
+                           feat=t(sc.feat[:n]).bfloat16().contiguous()))
+        cams.append(sc.cam)
+    rng = np.random.default_rng(44)
+    H, W = sc.cam.height, sc.cam.width
+    d_rgb = [t(rng.normal(0, 1e-3, (3, H, W)).astype(np.float32)) for _ in fr]
+    d_feat = [t(rng.normal(0, 1e-3, (64, H, W)).astype(np.float32)) for _ in fr]
+    st = rast.Settings(sh_degree=3, feat_dim=64, sh_dtype="bf16", feat_dtype="bf16")
+    br = BatchRenderer(frames, cams, st, rast.FE_MODE_FORWARD_BACKWARD, d_rgb, d_feat)
+    for _ in range(warmup):
+        br.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        br.launch()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    bad = [k for k in range(len(fr)) if br.report(k)["status"] != 0]
+    br.close()
+    ms = 1e3 * (t1 - t0) / steps
+    return dict(frames=len(fr), gaussians_per_frame=[f["n"] for f in fr], ms_per_replay=round(ms, 4),
+                frames_per_s=round(len(fr) * 1e3 / ms, 2), status_errors=bad)
 
 
 def cpu_baseline(sc, sample_tiles):
@@ -239,6 +278,11 @@ def main():
     }
     if "bf16" in res and "f32" in res:
         line["bf16_speedup_vs_f32"] = round(res["f32"]["ms_per_step"] / res["bf16"]["ms_per_step"], 4)
+    if not args.no_batched:
+        try:
+            line["batched_16_timestamps"] = run_batched(max(3, args.steps // 2), 2)
+        except Exception as e:  # reported, never hides the main measurement
+            line["batched_16_timestamps"] = {"error": repr(e)[:200]}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(sc, args.cpu_sample_tiles)
     print(json.dumps(line), flush=True)

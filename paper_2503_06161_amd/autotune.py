@@ -1,0 +1,100 @@
+"""Tile-shape / kernel-variant selection by timing.
+
+Every candidate renders the same image (the 3-sigma box rule makes the
+result independent of the tile shape), so the choice only changes speed.
+Candidates are timed with HIP events on the current stream (forward, or
+forward + backward), the fastest is kept, and results are cached in a JSON
+file keyed by device, image size, feature width, storage dtypes and a
+Gaussian-count bucket.  ``FE4DGS_AUTOTUNE_CACHE`` overrides the cache path.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import torch
+
+from . import rast
+
+TILE_SHAPES = [(16, 16), (32, 8), (16, 8), (8, 16), (8, 8)]
+VARIANTS = [rast.FE_VARIANT_MFMA, rast.FE_VARIANT_VALU]
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "fe4dgs_autotune.json")
+
+
+def _cache_path():
+    return os.environ.get("FE4DGS_AUTOTUNE_CACHE", DEFAULT_CACHE)
+
+
+def cache_key(cam, st: rast.Settings, n: int, backward: bool) -> str:
+    dev = torch.cuda.get_device_name() if torch.cuda.is_available() else "cpu"
+    bucket = 2 ** int(math.log2(max(n, 1)))
+    return (f"{dev}|{int(cam.width)}x{int(cam.height)}|D{st.feat_dim}|L{st.sh_degree}|{st.sh_dtype}/{st.feat_dtype}"
+            f"|n~{bucket}|{'fwdbwd' if backward else 'fwd'}")
+
+
+def _load_cache():
+    try:
+        with open(_cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store_cache(c):
+    path = _cache_path()
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(c, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def time_candidate(g: dict, cam, st: rast.Settings, d_rgb=None, d_feat=None, reps: int = 5) -> float:
+    """Median milliseconds of one forward (+ backward when upstream gradients
+    are given) for the settings ``st``."""
+    args = (g["means"], g["scales"], g["quats"], g["opacity"], g["sh"], g["feat"])
+    fwd = rast.render_forward(*args, cam, st, check=True)
+    st2 = rast.Settings(**{**st.__dict__, "key_capacity": fwd.cfg.key_capacity,
+                           "row_capacity": max(int(fwd.report["rows_needed"]), 1)})
+    out = dict(rgb=fwd.rgb, feat=fwd.feat, final_T=fwd.final_T, n_contrib=fwd.n_contrib)
+    grads, scratch = None, None
+    times = []
+    for r in range(reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        f = rast.render_forward(*args, cam, st2, check=False, state=fwd.state, out=out)
+        if d_rgb is not None:
+            grads = rast.render_backward(f, *args, d_rgb, d_feat, st2, grads=grads, scratch=scratch)
+            scratch = grads["_scratch"]
+        e1.record()
+        torch.cuda.synchronize()
+        if r > 0:
+            times.append(e0.elapsed_time(e1))
+    times.sort()
+    return times[len(times) // 2]
+
+
+def autotune(g: dict, cam, st: rast.Settings, d_rgb=None, d_feat=None, candidates=None, use_cache=True,
+             verbose=False) -> rast.Settings:
+    """Return a copy of ``st`` with the fastest tile shape and variant."""
+    n = int(g["means"].shape[0])
+    key = cache_key(cam, st, n, d_rgb is not None)
+    cache = _load_cache() if use_cache else {}
+    if key in cache:
+        c = cache[key]
+        return rast.Settings(**{**st.__dict__, "tile_w": c["tile_w"], "tile_h": c["tile_h"], "variant": c["variant"]})
+    cands = candidates or [(tw, th, v) for (tw, th) in TILE_SHAPES for v in VARIANTS]
+    results = []
+    for tw, th, v in cands:
+        s2 = rast.Settings(**{**st.__dict__, "tile_w": tw, "tile_h": th, "variant": v})
+        ms = time_candidate(g, cam, s2, d_rgb, d_feat)
+        results.append((ms, tw, th, v))
+        if verbose:
+            print(f"autotune {tw}x{th} variant {v}: {ms:.3f} ms", flush=True)
+    ms, tw, th, v = min(results)
+    if use_cache:
+        cache[key] = dict(tile_w=tw, tile_h=th, variant=v, ms=ms,
+                          all=[dict(tile_w=a, tile_h=b, variant=c, ms=m) for m, a, b, c in results])
+        _store_cache(cache)
+    return rast.Settings(**{**st.__dict__, "tile_w": tw, "tile_h": th, "variant": v})

@@ -467,19 +467,51 @@ fe_status fe_batch_plan_create(const fe_config* cfg, const fe_camera* cams, int3
   return FE_OK;
 }
 
-static fe_status batch_enqueue(fe_batch_plan* p, hipStream_t s) {
+// Frames are independent: frame f's forward (and backward) is enqueued on
+// branch stream f % kBranches, forked from and joined back into the capture
+// stream, so the captured graph has parallel chains the GPU may overlap.
+constexpr int kBranches = 4;
+
+static fe_status frame_enqueue(fe_batch_plan* p, int f, hipStream_t s) {
   fe_status st = FE_OK;
-  if (p->mode & FE_MODE_FORWARD) {
-    for (int f = 0; f < p->frames && st == FE_OK; ++f)
-      st = forward_impl(&p->cfg, &p->cams[f], &p->g[f], &p->out[f], p->ws + p->state_off[f], p->layouts[f], s);
+  if (p->mode & FE_MODE_FORWARD)
+    st = forward_impl(&p->cfg, &p->cams[f], &p->g[f], &p->out[f], p->ws + p->state_off[f], p->layouts[f], s);
+  if (st == FE_OK && (p->mode & FE_MODE_BACKWARD) && p->g[f].n > 0)
+    st = backward_impl(&p->cfg, &p->cams[f], &p->g[f], &p->out[f], p->ws + p->state_off[f], p->layouts[f],
+                       p->d_rgb[f], p->d_feat[f], &p->grads[f], p->ws + p->scratch_off[f], s);
+  return st;
+}
+
+struct Branches {
+  int n = 0;
+  hipStream_t s[kBranches] = {};
+  hipEvent_t fork = nullptr, join[kBranches] = {};
+  bool create(int frames) {
+    n = frames < kBranches ? frames : kBranches;
+    if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) return false;
+    for (int b = 0; b < n; ++b)
+      if (hipStreamCreateWithFlags(&s[b], hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&join[b], hipEventDisableTiming) != hipSuccess)
+        return false;
+    return true;
   }
-  if (p->mode & FE_MODE_BACKWARD) {
-    for (int f = 0; f < p->frames && st == FE_OK; ++f) {
-      if (p->g[f].n == 0) continue;
-      st = backward_impl(&p->cfg, &p->cams[f], &p->g[f], &p->out[f], p->ws + p->state_off[f], p->layouts[f],
-                         p->d_rgb[f], p->d_feat[f], &p->grads[f], p->ws + p->scratch_off[f], s);
+  ~Branches() {
+    for (int b = 0; b < kBranches; ++b) {
+      if (join[b]) (void)hipEventDestroy(join[b]);
+      if (s[b]) (void)hipStreamDestroy(s[b]);
     }
+    if (fork) (void)hipEventDestroy(fork);
   }
+};
+
+static fe_status batch_enqueue(fe_batch_plan* p, hipStream_t cs, Branches& br) {
+  fe_status st = hipEventRecord(br.fork, cs) == hipSuccess ? FE_OK : FE_ERR_HIP;
+  for (int b = 0; st == FE_OK && b < br.n; ++b)
+    if (hipStreamWaitEvent(br.s[b], br.fork, 0) != hipSuccess) st = FE_ERR_HIP;
+  for (int f = 0; st == FE_OK && f < p->frames; ++f) st = frame_enqueue(p, f, br.s[f % br.n]);
+  // always join the branches so that the capture ends cleanly
+  for (int b = 0; b < br.n; ++b)
+    if (hipEventRecord(br.join[b], br.s[b]) == hipSuccess) (void)hipStreamWaitEvent(cs, br.join[b], 0);
   return st;
 }
 
@@ -489,13 +521,15 @@ fe_status fe_batch_launch(fe_batch_plan* p, void* stream) {
   if (!p->captured) {
     // capture on a private non-default stream so that the caller's stream may be
     // the legacy default stream
+    Branches br;
+    if (!br.create(p->frames)) return FE_ERR_HIP;
     hipStream_t cs;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return FE_ERR_HIP;
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
       hipStreamDestroy(cs);
       return FE_ERR_HIP;
     }
-    const fe_status st = batch_enqueue(p, cs);
+    const fe_status st = batch_enqueue(p, cs, br);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(cs, &graph);
     hipStreamDestroy(cs);

@@ -1,0 +1,42 @@
+"""Autotuner: every candidate renders the same image, and the choice is
+cached and reused."""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+from paper_2503_06161_amd import rast, autotune
+from paper_2503_06161_amd.scenes import make_scene, crop_camera
+from tests import gpu_util as U
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rast.load_library()
+
+
+def test_candidates_agree_and_choice_is_cached(tmp_path, monkeypatch):
+    print("[case] autotune window of mid", flush=True)
+    monkeypatch.setenv("FE4DGS_AUTOTUNE_CACHE", str(tmp_path / "cache.json"))
+    sc = make_scene("mid")
+    cam = crop_camera(sc.cam, 250, 200, 96, 64)
+    d = U.to_device(sc, "bf16")
+    st = rast.Settings(sh_degree=3, feat_dim=32, sh_dtype="bf16", feat_dtype="bf16")
+    ref = None
+    for tw, th in autotune.TILE_SHAPES:
+        for v in autotune.VARIANTS:
+            s2 = rast.Settings(**{**st.__dict__, "tile_w": tw, "tile_h": th, "variant": v})
+            f = rast.render_forward(d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["feat"], cam, s2)
+            if ref is None:
+                ref = f
+            assert torch.equal(f.rgb, ref.rgb) and torch.equal(f.final_T, ref.final_T)
+            torch.testing.assert_close(f.feat, ref.feat, rtol=0, atol=2e-6)
+    g_rgb = torch.zeros(3, 64, 96, device="cuda")
+    g_feat = torch.full((32, 64, 96), 1e-3, device="cuda")
+    best = autotune.autotune(d, cam, st, g_rgb, g_feat, verbose=True)
+    assert (best.tile_w, best.tile_h) in autotune.TILE_SHAPES
+    again = autotune.autotune(d, cam, st, g_rgb, g_feat, candidates=[(8, 8, rast.FE_VARIANT_VALU)])
+    assert (again.tile_w, again.tile_h, again.variant) == (best.tile_w, best.tile_h, best.variant)
