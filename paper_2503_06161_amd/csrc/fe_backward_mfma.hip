@@ -55,6 +55,7 @@ struct BwdArgs {
   unsigned long long* report;
   float bg[3];
   int32_t W, H, tile_w, tiles_x, D, RS;
+  bool vec;                  // feature rows allow aligned 4-channel vector loads
 };
 
 __device__ __forceinline__ bool pair_alpha(float fpx, float fpy, int px, int py, float2 m, float4 co,
@@ -83,14 +84,47 @@ __device__ __forceinline__ float row_sum16(float v) {
   return v;
 }
 
+// Four consecutive channels of a feature row, kept in their storage form
+// while in flight (two registers for bf16).  `vec` (uniform) says the row
+// start and the channel group are aligned for one vector load.
 template <typename FT>
-__device__ __forceinline__ float feat_val(const void* p, int64_t i);
+struct FeatGroup;
 template <>
-__device__ __forceinline__ float feat_val<float>(const void* p, int64_t i) { return static_cast<const float*>(p)[i]; }
+struct FeatGroup<float> {
+  float4 v;
+  __device__ __forceinline__ void clear() { v = make_float4(0.f, 0.f, 0.f, 0.f); }
+  __device__ __forceinline__ void load(const void* p, int64_t base, int c, int D, bool vec) {
+    const float* f = static_cast<const float*>(p) + base + c;
+    if (vec) {
+      v = *reinterpret_cast<const float4*>(f);
+    } else {
+      v.x = c < D ? f[0] : 0.f;
+      v.y = c + 1 < D ? f[1] : 0.f;
+      v.z = c + 2 < D ? f[2] : 0.f;
+      v.w = c + 3 < D ? f[3] : 0.f;
+    }
+  }
+  __device__ __forceinline__ float get(int j) const { return j == 0 ? v.x : j == 1 ? v.y : j == 2 ? v.z : v.w; }
+};
 template <>
-__device__ __forceinline__ float feat_val<uint16_t>(const void* p, int64_t i) {
-  return bf16_bits_to_float(static_cast<const uint16_t*>(p)[i]);
-}
+struct FeatGroup<uint16_t> {
+  uint2 v;
+  __device__ __forceinline__ void clear() { v = make_uint2(0u, 0u); }
+  __device__ __forceinline__ void load(const void* p, int64_t base, int c, int D, bool vec) {
+    const uint16_t* f = static_cast<const uint16_t*>(p) + base + c;
+    if (vec) {
+      v = *reinterpret_cast<const uint2*>(f);
+    } else {
+      const uint32_t e0 = c < D ? f[0] : 0u, e1 = c + 1 < D ? f[1] : 0u;
+      const uint32_t e2 = c + 2 < D ? f[2] : 0u, e3 = c + 3 < D ? f[3] : 0u;
+      v = make_uint2(e0 | (e1 << 16), e2 | (e3 << 16));
+    }
+  }
+  __device__ __forceinline__ float get(int j) const {
+    const uint32_t w = j < 2 ? v.x : v.y;
+    return __uint_as_float((j & 1) ? (w & 0xFFFF0000u) : (w << 16));
+  }
+};
 
 template <int DP, typename FT, int NT>
 __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
@@ -101,15 +135,25 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
   constexpr int NW = NT / 64;
   constexpr int FROW = DP + 8;         // padded LDS rows (bank spread)
   constexpr int WROW = 64 + 8;
+  constexpr int DFROW = DP + 8;        // rows 4 apart land 32 banks apart
+  constexpr int GROW = NT + 1;
+  // The upstream-gradient slice is needed only before the first batch; the
+  // weight transposes and the per-batch dF sums only after it: they share
+  // one LDS region.
+  constexpr size_t kGBytes = sizeof(float) * 32 * GROW;
+  constexpr size_t kWBytes = sizeof(__bf16) * NW * 2 * kNB * WROW;
+  constexpr size_t kDFBytes = sizeof(float) * kNB * DFROW;
+  constexpr size_t kShared = kGBytes > kWBytes + kDFBytes ? kGBytes : kWBytes + kDFBytes;
   __shared__ float2 s_xy[kNB];
   __shared__ float4 s_co[kNB];
   __shared__ float4 s_rgb[kNB];
   __shared__ int4 s_box[kNB];
   __shared__ __attribute__((aligned(16))) __bf16 s_f[NPF][kNB][FROW];
-  __shared__ __attribute__((aligned(16))) __bf16 s_w[NW][2][kNB][WROW];
-  __shared__ float s_df[kNB][DP];
   __shared__ float s_red[12][kNB];
-  __shared__ float s_g[32][NT + 1];    // one 32-channel slice of the tile's upstream gradient
+  __shared__ __attribute__((aligned(16))) unsigned char s_raw[kShared];
+  float (*s_g)[GROW] = reinterpret_cast<float (*)[GROW]>(s_raw);
+  __bf16 (*s_w)[2][kNB][WROW] = reinterpret_cast<__bf16 (*)[2][kNB][WROW]>(s_raw);
+  float (*s_df)[DFROW] = reinterpret_cast<float (*)[DFROW]>(s_raw + kWBytes);
 
   const int tile = blockIdx.x;
   const int lane = threadIdx.x & 63;
@@ -123,13 +167,51 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
   const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
   const int64_t HW = (int64_t)a.W * a.H;
   const uint2 rg = a.ranges[tile];
-  const uint32_t walk = min(a.tile_maxlast[tile], rg.y - rg.x);
+  const int walk = (int)min(a.tile_maxlast[tile], rg.y - rg.x);
   const int64_t row0 = a.row_base[tile];
-  if (row0 + walk > (uint64_t)a.row_cap) {
+  if (row0 + walk > a.row_cap) {
     if (threadIdx.x == 0) a.report[kRepStatus] = (unsigned long long)FE_ERR_ROW_OVERFLOW;
     return;   // uniform: nothing of this tile can be stored
   }
   if (walk == 0) return;
+
+  // Batches are walked back to front: batch k covers list positions
+  // [r1 - kNB, r1) clipped at 0, r1 = walk - k kNB.  Staging is
+  // software-pipelined: the Gaussian ids of batch k+2 and the records /
+  // feature rows of batch k+1 are loaded into registers while batch k is
+  // processed.
+  constexpr int FQ = DP / 4;                               // 4-channel groups per row
+  constexpr int FI = (kNB * FQ + NT - 1) / NT;             // feature groups per thread
+  uint32_t id_n[FI + 1];
+  FeatGroup<FT> fv[FI];
+  float2 p_xy = make_float2(0.f, 0.f);
+  float4 p_co = make_float4(0.f, 0.f, 0.f, 0.f), p_rgb = p_co;
+  short4 p_box = make_short4(1, 1, 0, 0);
+  auto load_ids = [&](int r1) {
+    const int r0 = r1 > kNB ? r1 - kNB : 0;
+#pragma unroll
+    for (int k = 0; k < FI; ++k) {
+      const int i = (int)(threadIdx.x + k * NT) / FQ;
+      id_n[k] = (k * NT + (int)threadIdx.x < kNB * FQ && r0 + i < r1) ? a.gauss[rg.x + r0 + i] : 0xFFFFFFFFu;
+    }
+    id_n[FI] = ((int)threadIdx.x < kNB && r0 + (int)threadIdx.x < r1) ? a.gauss[rg.x + r0 + threadIdx.x] : 0xFFFFFFFFu;
+  };
+  auto load_data = [&]() {
+#pragma unroll
+    for (int k = 0; k < FI; ++k) {
+      const int c = ((int)(threadIdx.x + k * NT) % FQ) * 4;
+      fv[k].clear();
+      if (id_n[k] != 0xFFFFFFFFu && c < a.D) fv[k].load(a.feat, (int64_t)id_n[k] * a.D, c, a.D, a.vec);
+    }
+    if (id_n[FI] != 0xFFFFFFFFu) {
+      const uint32_t g = id_n[FI];
+      p_xy = a.xy[g];
+      p_co = a.conic_o[g];
+      p_rgb = a.rgb[g];
+      p_box = a.box[g];
+    }
+  };
+  load_ids(walk);
 
   // ---- per-pixel state ----
   float gr0 = 0.f, gr1 = 0.f, gr2 = 0.f;
@@ -143,23 +225,29 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
     T = a.final_T[p];
     last = a.n_contrib[p];
   }
-  float acc = T * ((gr0 * a.bg[0] + gr1 * a.bg[1]) + gr2 * a.bg[2]);
-  int wave_last = last;
-  for (int o = 32; o > 0; o >>= 1) wave_last = max(wave_last, __shfl_xor(wave_last, o, 64));
 
   // ---- upstream feature gradient of the wave's 64 pixels, in both operand layouts,
-  //      staged through LDS one 32-channel slice at a time (coalesced loads) ----
+  //      staged through LDS one 32-channel slice at a time; the loads of slice
+  //      cb + 1 are in flight while slice cb is converted ----
   bf16x8 g1[2][KS1][2];   // GEMM1 B: [pixel block][k step][hi, lo]; lane: pixel l%32, channels 8(l/32)+j
   bf16x8 g2[CB][4][2];    // GEMM2 B: [channel block][k step][hi, lo]; lane: channel l%32, pixels 8(l/32)+j
+  float gv[32];
+  auto load_g = [&](int cb) {
+#pragma unroll
+    for (int c = 0; c < 32; ++c) {
+      const int ch = 32 * cb + c;
+      gv[c] = (inside && ch < a.D) ? a.d_feat[ch * HW + (int64_t)py * a.W + px] : 0.f;
+    }
+  };
+  load_g(0);
+  load_data();
+  load_ids(walk - kNB);
 #pragma unroll
   for (int cb = 0; cb < CB; ++cb) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < 32 * NT; e += NT) {
-      const int c = e / NT, q = e % NT;
-      const int qx = tx0 + q % a.tile_w, qy = ty0 + q / a.tile_w;
-      const int ch = 32 * cb + c;
-      s_g[c][q] = (ch < a.D && qx < a.W && qy < a.H) ? a.d_feat[ch * HW + (int64_t)qy * a.W + qx] : 0.f;
-    }
+    if (cb > 0) __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 32; ++c) s_g[c][threadIdx.x] = gv[c];
+    if (cb + 1 < CB) load_g(cb + 1);
     __syncthreads();
 #pragma unroll
     for (int pb = 0; pb < 2; ++pb)
@@ -182,44 +270,48 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
         g2[cb][s][1][j] = l;
       }
   }
+  float acc = T * ((gr0 * a.bg[0] + gr1 * a.bg[1]) + gr2 * a.bg[2]);
+  int wave_last = last;
+  for (int o = 32; o > 0; o >>= 1) wave_last = max(wave_last, __shfl_xor(wave_last, o, 64));
 
-  for (int e = threadIdx.x; e < kNB * DP; e += NT) (&s_df[0][0])[e] = 0.f;
+  __syncthreads();   // the gradient slices are consumed; the region now holds W and dF
+  for (int e = threadIdx.x; e < kNB * DFROW; e += NT) (&s_df[0][0])[e] = 0.f;
   for (int e = threadIdx.x; e < 12 * kNB; e += NT) (&s_red[0][0])[e] = 0.f;
 
-  const uint32_t end = rg.x + walk;
-  for (uint32_t b1 = end; b1 > rg.x;) {
-    const uint32_t b0 = b1 - rg.x > (uint32_t)kNB ? b1 - kNB : rg.x;
-    const int nb = (int)(b1 - b0);
-    const int pos0 = (int)(b0 - rg.x);
+  for (int r1 = walk; r1 > 0; r1 -= kNB) {
+    const int pos0 = r1 > kNB ? r1 - kNB : 0;
+    const int nb = r1 - pos0;
     __syncthreads();
-    // ---- stage the batch ----
-    for (int t = threadIdx.x; t < kNB; t += NT) {
-      if (t < nb) {
-        const uint32_t g = a.gauss[b0 + t];
-        s_xy[t] = a.xy[g];
-        s_co[t] = a.conic_o[g];
-        s_rgb[t] = a.rgb[g];
-        const short4 b = a.box[g];
-        s_box[t] = make_int4(b.x, b.y, b.z, b.w);
-      }
+    // ---- stage the batch from registers ----
+    if ((int)threadIdx.x < kNB) {
+      s_xy[threadIdx.x] = p_xy;
+      s_co[threadIdx.x] = p_co;
+      s_rgb[threadIdx.x] = p_rgb;
+      s_box[threadIdx.x] = make_int4(p_box.x, p_box.y, p_box.z, p_box.w);
     }
-    for (int e = threadIdx.x; e < kNB * (DP / 4); e += NT) {
-      const int i = e / (DP / 4);
-      const int c = (e % (DP / 4)) * 4;
-      const int64_t g = i < nb ? (int64_t)a.gauss[b0 + i] : 0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const float v = (i < nb && c + j < a.D) ? feat_val<FT>(a.feat, g * a.D + c + j) : 0.f;
-        if constexpr (F32) {
-          __bf16 h, m;
-          split2(v, h, m);
-          s_f[0][i][c + j] = h;
-          s_f[1][i][c + j] = m;
-        } else {
-          s_f[0][i][c + j] = (__bf16)v;   // exact: the value is a bf16
+    for (int k = 0; k < FI; ++k) {
+      const int e = threadIdx.x + k * NT;
+      if (e < kNB * FQ) {
+        const int i = e / FQ;
+        const int c = (e % FQ) * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float v = i < nb ? fv[k].get(j) : 0.f;
+          if constexpr (F32) {
+            __bf16 h, m;
+            split2(v, h, m);
+            s_f[0][i][c + j] = h;
+            s_f[1][i][c + j] = m;
+          } else {
+            s_f[0][i][c + j] = (__bf16)v;   // exact: the value is a bf16
+          }
         }
       }
     }
+    // ---- issue the next batches' loads ----
+    load_data();
+    load_ids(r1 - 2 * kNB);
     __syncthreads();
     if (wave_last > pos0) {
       // ---- GEMM1: S^T (Gaussians x pixels) = F (Gaussians x D) . G^T (D x pixels) ----
@@ -367,25 +459,31 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
       }
     }
     __syncthreads();
-    // ---- rows of this batch: [dL/df (D) | u v A B C o r g b | pad] ----
-    for (int e = threadIdx.x; e < nb * a.RS; e += NT) {
-      const int i = e / a.RS;
-      const int c = e % a.RS;
-      float v = 0.f;
-      if (c < a.D) {
-        v = s_df[i][c];
-        s_df[i][c] = 0.f;
-      } else if (c < a.D + 9) {
-        v = s_red[c - a.D][i];
-        s_red[c - a.D][i] = 0.f;
+    // ---- rows of this batch: [dL/df (D) | u v A B C o r g b | pad], one
+    //      float4 per lane, one row per wave at a time; the sums are cleared
+    //      for the next batch as they are read ----
+    for (int i = wave; i < nb; i += NW) {
+      for (int c0 = 4 * lane; c0 < a.RS; c0 += 256) {
+        float v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int c = c0 + j;
+          v[j] = 0.f;
+          if (c < a.D) {
+            v[j] = s_df[i][c];
+            s_df[i][c] = 0.f;
+          } else if (c < a.D + 9) {
+            v[j] = s_red[c - a.D][i];
+            s_red[c - a.D][i] = 0.f;
+          }
+        }
+        *reinterpret_cast<float4*>(&a.rows[(row0 + pos0 + i) * a.RS + c0]) = make_float4(v[0], v[1], v[2], v[3]);
       }
-      a.rows[(row0 + pos0 + i) * a.RS + c] = v;
     }
     for (int i = threadIdx.x; i < nb; i += NT) {
-      const uint32_t pos = b0 + i;
+      const uint32_t pos = rg.x + pos0 + i;
       a.rowidx[a.epos ? a.epos[pos] : pos] = (uint32_t)(row0 + pos0 + i + 1);
     }
-    b1 = b0;
   }
 }
 
@@ -504,6 +602,8 @@ hipError_t launch_composite_bwd_mfma(const fe_config* cfg, const fe_camera* cam,
   a.tiles_x = v.tiles_x;
   a.D = cfg->feat_dim;
   a.RS = backward_row_stride(cfg->feat_dim);
+  const size_t esz = cfg->feat_dtype == FE_BF16 ? 2 : 4;
+  a.vec = cfg->feat_dim % 4 == 0 && reinterpret_cast<uintptr_t>(g->feat) % (4 * esz) == 0;
   const int nt = cfg->tile_w * cfg->tile_h;
   return cfg->feat_dtype == FE_BF16 ? dispatch_bwd<uint16_t>(cfg->feat_dim, nt, a, v.tiles, s)
                                     : dispatch_bwd<float>(cfg->feat_dim, nt, a, v.tiles, s);
