@@ -137,12 +137,17 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
   constexpr int WROW = 64 + 8;
   constexpr int DFROW = DP + 8;        // rows 4 apart land 32 banks apart
   constexpr int GROW = NT + 1;
+  // GEMM2 work is split into CB units per wave, a unit being one 32-channel
+  // block over one wave's 64 pixels (a pixel chunk).  With CB >= NW a wave
+  // owns whole channel blocks (all chunks) and stores its sums directly;
+  // otherwise KSPL waves share a block and leave partial sums in LDS.
+  constexpr int KSPL = NW > CB ? NW / CB : 1;
   // The upstream-gradient slice is needed only before the first batch; the
-  // weight transposes and the per-batch dF sums only after it: they share
-  // one LDS region.
+  // weight transposes and the partial dF sums only after it: they share one
+  // LDS region.
   constexpr size_t kGBytes = sizeof(float) * 32 * GROW;
   constexpr size_t kWBytes = sizeof(__bf16) * NW * 2 * kNB * WROW;
-  constexpr size_t kDFBytes = sizeof(float) * kNB * DFROW;
+  constexpr size_t kDFBytes = KSPL > 1 ? sizeof(float) * KSPL * kNB * DFROW : 0;
   constexpr size_t kShared = kGBytes > kWBytes + kDFBytes ? kGBytes : kWBytes + kDFBytes;
   __shared__ float2 s_xy[kNB];
   __shared__ float4 s_co[kNB];
@@ -153,11 +158,15 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
   __shared__ __attribute__((aligned(16))) unsigned char s_raw[kShared];
   float (*s_g)[GROW] = reinterpret_cast<float (*)[GROW]>(s_raw);
   __bf16 (*s_w)[2][kNB][WROW] = reinterpret_cast<__bf16 (*)[2][kNB][WROW]>(s_raw);
-  float (*s_df)[DFROW] = reinterpret_cast<float (*)[DFROW]>(s_raw + kWBytes);
+  float (*s_df)[kNB][DFROW] = reinterpret_cast<float (*)[kNB][DFROW]>(s_raw + kWBytes);   // [KSPL]
+  __shared__ int s_live[NW];
 
   const int tile = blockIdx.x;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
+  // GEMM2 unit u of this wave: channel block and pixel chunk
+  auto unit_cb = [&](int u) { return CB >= NW ? wave + NW * (u / NW) : wave % CB; };
+  auto unit_chunk = [&](int u) { return CB >= NW ? u % NW : (wave / CB) * CB + u; };
   const int tile_h = NT / a.tile_w;
   const int tx0 = (tile % a.tiles_x) * a.tile_w;
   const int ty0 = (tile / a.tiles_x) * tile_h;
@@ -182,29 +191,28 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
   // processed.
   constexpr int FQ = DP / 4;                               // 4-channel groups per row
   constexpr int FI = (kNB * FQ + NT - 1) / NT;             // feature groups per thread
-  uint32_t id_n[FI + 1];
+  uint32_t id_n;                                          // Gaussian (tid % kNB) of the next batch
   FeatGroup<FT> fv[FI];
   float2 p_xy = make_float2(0.f, 0.f);
   float4 p_co = make_float4(0.f, 0.f, 0.f, 0.f), p_rgb = p_co;
   short4 p_box = make_short4(1, 1, 0, 0);
+  // Staging thread t works on Gaussian t % kNB of a batch (feature groups
+  // t / kNB + k NT / kNB), so it needs one id.
+  const int si = (int)threadIdx.x % kNB;
   auto load_ids = [&](int r1) {
     const int r0 = r1 > kNB ? r1 - kNB : 0;
-#pragma unroll
-    for (int k = 0; k < FI; ++k) {
-      const int i = (int)(threadIdx.x + k * NT) / FQ;
-      id_n[k] = (k * NT + (int)threadIdx.x < kNB * FQ && r0 + i < r1) ? a.gauss[rg.x + r0 + i] : 0xFFFFFFFFu;
-    }
-    id_n[FI] = ((int)threadIdx.x < kNB && r0 + (int)threadIdx.x < r1) ? a.gauss[rg.x + r0 + threadIdx.x] : 0xFFFFFFFFu;
+    id_n = r0 + si < r1 ? a.gauss[rg.x + r0 + si] : 0xFFFFFFFFu;
   };
   auto load_data = [&]() {
 #pragma unroll
     for (int k = 0; k < FI; ++k) {
-      const int c = ((int)(threadIdx.x + k * NT) % FQ) * 4;
+      const int e = threadIdx.x + k * NT;
+      const int c = (e / kNB) * 4;
       fv[k].clear();
-      if (id_n[k] != 0xFFFFFFFFu && c < a.D) fv[k].load(a.feat, (int64_t)id_n[k] * a.D, c, a.D, a.vec);
+      if (e < kNB * FQ && id_n != 0xFFFFFFFFu && c < a.D) fv[k].load(a.feat, (int64_t)id_n * a.D, c, a.D, a.vec);
     }
-    if (id_n[FI] != 0xFFFFFFFFu) {
-      const uint32_t g = id_n[FI];
+    if ((int)threadIdx.x < kNB && id_n != 0xFFFFFFFFu) {
+      const uint32_t g = id_n;
       p_xy = a.xy[g];
       p_co = a.conic_o[g];
       p_rgb = a.rgb[g];
@@ -230,7 +238,7 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
   //      staged through LDS one 32-channel slice at a time; the loads of slice
   //      cb + 1 are in flight while slice cb is converted ----
   bf16x8 g1[2][KS1][2];   // GEMM1 B: [pixel block][k step][hi, lo]; lane: pixel l%32, channels 8(l/32)+j
-  bf16x8 g2[CB][4][2];    // GEMM2 B: [channel block][k step][hi, lo]; lane: channel l%32, pixels 8(l/32)+j
+  bf16x8 g2[CB][4][2];    // GEMM2 B: [unit][k step][hi, lo]; lane: channel l%32, pixels 8(l/32)+j of the chunk
   float gv[32];
   auto load_g = [&](int cb) {
 #pragma unroll
@@ -261,21 +269,25 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
           g1[pb][2 * cb + s2][1][j] = l;
         }
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+    for (int u = 0; u < CB; ++u) {
+      if (unit_cb(u) != cb) continue;
+      const int q0 = 64 * unit_chunk(u) + 8 * (lane >> 5);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        __bf16 h, l;
-        split2(s_g[lane & 31][64 * wave + 16 * s + 8 * (lane >> 5) + j], h, l);
-        g2[cb][s][0][j] = h;
-        g2[cb][s][1][j] = l;
-      }
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          __bf16 h, l;
+          split2(s_g[lane & 31][q0 + 16 * s + j], h, l);
+          g2[u][s][0][j] = h;
+          g2[u][s][1][j] = l;
+        }
+    }
   }
   float acc = T * ((gr0 * a.bg[0] + gr1 * a.bg[1]) + gr2 * a.bg[2]);
   int wave_last = last;
   for (int o = 32; o > 0; o >>= 1) wave_last = max(wave_last, __shfl_xor(wave_last, o, 64));
 
   __syncthreads();   // the gradient slices are consumed; the region now holds W and dF
-  for (int e = threadIdx.x; e < kNB * DFROW; e += NT) (&s_df[0][0])[e] = 0.f;
   for (int e = threadIdx.x; e < 12 * kNB; e += NT) (&s_red[0][0])[e] = 0.f;
 
   for (int r1 = walk; r1 > 0; r1 -= kNB) {
@@ -293,8 +305,8 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
     for (int k = 0; k < FI; ++k) {
       const int e = threadIdx.x + k * NT;
       if (e < kNB * FQ) {
-        const int i = e / FQ;
-        const int c = (e % FQ) * 4;
+        const int i = e % kNB;
+        const int c = (e / kNB) * 4;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const float v = i < nb ? fv[k].get(j) : 0.f;
@@ -313,7 +325,9 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
     load_data();
     load_ids(r1 - 2 * kNB);
     __syncthreads();
-    if (wave_last > pos0) {
+    const bool live = wave_last > pos0;
+    if (lane == 0) s_live[wave] = live ? 1 : 0;
+    if (live) {
       // ---- GEMM1: S^T (Gaussians x pixels) = F (Gaussians x D) . G^T (D x pixels) ----
       f32x16 s1[2] = {f32x16{}, f32x16{}};
 #pragma unroll
@@ -341,7 +355,6 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
       // ---- back-to-front walk of this lane's pixel, in groups of 8 ----
       // Branch-free so that the independent per-pair work of a group
       // interleaves; only the transmittance / suffix recurrences are serial.
-      float wv[kNB];
       constexpr int GR = 8;
 #pragma unroll
       for (int gi = kNB / GR - 1; gi >= 0; --gi) {
@@ -401,7 +414,13 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
           vals[9] = 0.f;
           vals[10] = 0.f;
           vals[11] = 0.f;
-          wv[i] = wg[u];
+          {
+            // W^T of the wave into LDS (Gaussian-major, pixels contiguous)
+            __bf16 h, l;
+            split2(wg[u], h, l);
+            s_w[wave][0][i][lane] = h;
+            s_w[wave][1][i][lane] = l;
+          }
           // sum over the wave's 64 pixels: halve with the 32- and 16-lane
           // swaps (each lane keeps 3 of the 12 values, summed over 4 lanes),
           // then a 16-lane row sum; lane 15 of row r holds values 3r..3r+2
@@ -427,57 +446,77 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
             for (int k = 0; k < 3; ++k) atomicAdd(&s_red[base + k][gi * GR + u], red[u][k]);
         }
       }
-      // ---- W^T of the wave into LDS (Gaussian-major, pixels contiguous) ----
+    }
+    __syncthreads();
+    // ---- GEMM2: dF (Gaussians x D) = W^T (Gaussians x pixels) . G (pixels x D),
+    //      one unit per (channel block, pixel chunk); two accumulators so
+    //      that two MFMA chains interleave ----
+    {
+      f32x16 d[2] = {f32x16{}, f32x16{}};
 #pragma unroll
-      for (int i = 0; i < kNB; ++i) {
-        __bf16 h, l;
-        split2(wv[i], h, l);
-        s_w[wave][0][i][lane] = h;
-        s_w[wave][1][i][lane] = l;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      // ---- GEMM2: dF (Gaussians x D) = W^T (Gaussians x pixels) . G (pixels x D) ----
+      for (int u = 0; u < CB; ++u) {
+        const int chunk = unit_chunk(u);
+        if (s_live[chunk]) {
 #pragma unroll
-      for (int cb = 0; cb < CB; ++cb) {
-        f32x16 d = f32x16{};
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int kp = 16 * s + 8 * (lane >> 5);
-          const bf16x8 wh = *reinterpret_cast<const bf16x8*>(&s_w[wave][0][lane & 31][kp]);
-          const bf16x8 wl = *reinterpret_cast<const bf16x8*>(&s_w[wave][1][lane & 31][kp]);
-          d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh, g2[cb][s][0], d, 0, 0, 0);
-          d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh, g2[cb][s][1], d, 0, 0, 0);
-          d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wl, g2[cb][s][0], d, 0, 0, 0);
+          for (int s = 0; s < 4; ++s) {
+            const int kp = 16 * s + 8 * (lane >> 5);
+            const bf16x8 wh = *reinterpret_cast<const bf16x8*>(&s_w[chunk][0][lane & 31][kp]);
+            const bf16x8 wl = *reinterpret_cast<const bf16x8*>(&s_w[chunk][1][lane & 31][kp]);
+            d[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh, g2[u][s][0], d[0], 0, 0, 0);
+            d[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh, g2[u][s][1], d[1], 0, 0, 0);
+            d[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wl, g2[u][s][0], d[0], 0, 0, 0);
+          }
         }
+        // a channel block is complete after its last unit of this wave
+        const bool block_end = CB >= NW ? (u % NW == NW - 1) : (u == CB - 1);
+        if (block_end) {
+          const int cb = unit_cb(u);
+          const int c = 32 * cb + (lane & 31);
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-          atomicAdd(&s_df[i][32 * cb + (lane & 31)], d[v]);
+          for (int v = 0; v < 16; ++v) {
+            const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+            const float x = d[0][v] + d[1][v];
+            if constexpr (KSPL == 1) {
+              if (i < nb && c < a.D) a.rows[(row0 + pos0 + i) * a.RS + c] = x;
+            } else {
+              s_df[wave / CB][i][c] = x;
+            }
+          }
+          d[0] = d[1] = f32x16{};
         }
       }
     }
-    __syncthreads();
-    // ---- rows of this batch: [dL/df (D) | u v A B C o r g b | pad], one
-    //      float4 per lane, one row per wave at a time; the sums are cleared
-    //      for the next batch as they are read ----
-    for (int i = wave; i < nb; i += NW) {
-      for (int c0 = 4 * lane; c0 < a.RS; c0 += 256) {
-        float v[4];
+    if constexpr (KSPL > 1) __syncthreads();   // partial sums of all waves are in LDS
+    // ---- rest of the rows of this batch: [dL/df (D) | u v A B C o r g b | pad];
+    //      the 9 sums are cleared for the next batch as they are read ----
+    {
+      for (int i = wave; i < nb; i += NW) {
+        for (int c0 = (KSPL > 1 ? 0 : (a.D & ~3)) + 4 * lane; c0 < a.RS; c0 += 256) {
+          float v[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int c = c0 + j;
-          v[j] = 0.f;
-          if (c < a.D) {
-            v[j] = s_df[i][c];
-            s_df[i][c] = 0.f;
-          } else if (c < a.D + 9) {
-            v[j] = s_red[c - a.D][i];
-            s_red[c - a.D][i] = 0.f;
+          for (int j = 0; j < 4; ++j) {
+            const int c = c0 + j;
+            v[j] = 0.f;
+            if (c < a.D) {
+              if constexpr (KSPL > 1) {
+#pragma unroll
+                for (int k = 0; k < KSPL; ++k) v[j] += s_df[k][i][c];
+              }
+            } else if (c < a.D + 9) {
+              v[j] = s_red[c - a.D][i];
+              s_red[c - a.D][i] = 0.f;
+            }
+          }
+          float* dst = &a.rows[(row0 + pos0 + i) * a.RS + c0];
+          if (KSPL > 1 || c0 >= a.D) {
+            *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+          } else {
+            // group straddling the end of the D columns stored by GEMM2
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              if (c0 + j >= a.D) dst[j] = v[j];
           }
         }
-        *reinterpret_cast<float4*>(&a.rows[(row0 + pos0 + i) * a.RS + c0]) = make_float4(v[0], v[1], v[2], v[3]);
       }
     }
     for (int i = threadIdx.x; i < nb; i += NT) {
