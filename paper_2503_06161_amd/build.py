@@ -38,11 +38,22 @@ def _compile(src: str) -> str:
     return obj
 
 
+def _source_stamps() -> dict:
+    files = [os.path.join(CSRC, f) for f in os.listdir(CSRC)]
+    files.append(os.path.join(HERE, "..", "include", "fe4dgs_rast.h"))
+    return {f: os.stat(f).st_mtime_ns for f in files if os.path.isfile(f)}
+
+
 def build(jobs: int | None = None, verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(len(SOURCES), os.cpu_count() or 1)
+    before = _source_stamps()
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
+    # hipcc reads a source once for the device pass and once for the host
+    # pass: a file changed meanwhile gives host stubs without device code
+    if _source_stamps() != before:
+        raise RuntimeError("sources changed during the build; build again")
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -84,48 +84,6 @@ __device__ __forceinline__ float row_sum16(float v) {
   return v;
 }
 
-// Four consecutive channels of a feature row, kept in their storage form
-// while in flight (two registers for bf16).  `vec` (uniform) says the row
-// start and the channel group are aligned for one vector load.
-template <typename FT>
-struct FeatGroup;
-template <>
-struct FeatGroup<float> {
-  float4 v;
-  __device__ __forceinline__ void clear() { v = make_float4(0.f, 0.f, 0.f, 0.f); }
-  __device__ __forceinline__ void load(const void* p, int64_t base, int c, int D, bool vec) {
-    const float* f = static_cast<const float*>(p) + base + c;
-    if (vec) {
-      v = *reinterpret_cast<const float4*>(f);
-    } else {
-      v.x = c < D ? f[0] : 0.f;
-      v.y = c + 1 < D ? f[1] : 0.f;
-      v.z = c + 2 < D ? f[2] : 0.f;
-      v.w = c + 3 < D ? f[3] : 0.f;
-    }
-  }
-  __device__ __forceinline__ float get(int j) const { return j == 0 ? v.x : j == 1 ? v.y : j == 2 ? v.z : v.w; }
-};
-template <>
-struct FeatGroup<uint16_t> {
-  uint2 v;
-  __device__ __forceinline__ void clear() { v = make_uint2(0u, 0u); }
-  __device__ __forceinline__ void load(const void* p, int64_t base, int c, int D, bool vec) {
-    const uint16_t* f = static_cast<const uint16_t*>(p) + base + c;
-    if (vec) {
-      v = *reinterpret_cast<const uint2*>(f);
-    } else {
-      const uint32_t e0 = c < D ? f[0] : 0u, e1 = c + 1 < D ? f[1] : 0u;
-      const uint32_t e2 = c + 2 < D ? f[2] : 0u, e3 = c + 3 < D ? f[3] : 0u;
-      v = make_uint2(e0 | (e1 << 16), e2 | (e3 << 16));
-    }
-  }
-  __device__ __forceinline__ float get(int j) const {
-    const uint32_t w = j < 2 ? v.x : v.y;
-    return __uint_as_float((j & 1) ? (w & 0xFFFF0000u) : (w << 16));
-  }
-};
-
 template <int DP, typename FT, int NT>
 __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
   constexpr bool F32 = std::is_same<FT, float>::value;
@@ -393,9 +351,21 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
           dag[u] = ct[u] ? da : 0.f;
         }
         float red[GR][3];
+        bool any[GR];
 #pragma unroll
         for (int u = 0; u < GR; ++u) {
           const int i = gi * GR + u;
+          {
+            // W^T of the wave into LDS (Gaussian-major, pixels contiguous)
+            __bf16 h, l;
+            split2(wg[u], h, l);
+            s_w[wave][0][i][lane] = h;
+            s_w[wave][1][i][lane] = l;
+          }
+          // a Gaussian that no pixel of the wave blends adds nothing
+          any[u] = __ballot(ct[u]) != 0ull;
+          red[u][0] = red[u][1] = red[u][2] = 0.f;
+          if (!any[u]) continue;
           const float4 co = s_co[i];
           const float opG = co.w * Gv[u];
           const bool unclamped = opG <= kAlphaMax;
@@ -414,13 +384,6 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
           vals[9] = 0.f;
           vals[10] = 0.f;
           vals[11] = 0.f;
-          {
-            // W^T of the wave into LDS (Gaussian-major, pixels contiguous)
-            __bf16 h, l;
-            split2(wg[u], h, l);
-            s_w[wave][0][i][lane] = h;
-            s_w[wave][1][i][lane] = l;
-          }
           // sum over the wave's 64 pixels: halve with the 32- and 16-lane
           // swaps (each lane keeps 3 of the 12 values, summed over 4 lanes),
           // then a 16-lane row sum; lane 15 of row r holds values 3r..3r+2
@@ -442,8 +405,9 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
           const int base = 6 * (lane >> 5) + 3 * ((lane >> 4) & 1);
 #pragma unroll
           for (int u = 0; u < GR; ++u)
+            if (any[u])
 #pragma unroll
-            for (int k = 0; k < 3; ++k) atomicAdd(&s_red[base + k][gi * GR + u], red[u][k]);
+              for (int k = 0; k < 3; ++k) atomicAdd(&s_red[base + k][gi * GR + u], red[u][k]);
         }
       }
     }
@@ -538,54 +502,100 @@ struct ReduceArgs {
   float* grad2d;                // [n][12]
   float* grad_feat;             // [n][D]
   int accumulate;
+  int vec_out;                  // grad_feat rows allow aligned float4 stores
 };
 
-// 16 lanes per Gaussian; each lane owns CPL consecutive channels.  The
-// Gaussian's pairs are contiguous in emit order, so its row indices are one
-// coalesced read.
-template <int CPL>
+// LPG lanes per Gaussian (a power of two dividing 64); lane k owns the
+// 4-channel groups k, k + LPG, ... of the row.  A Gaussian's pairs are
+// contiguous in emit order, so its row indices are one coalesced read; up to
+// four rows are loaded before they are summed, so that several row reads are
+// in flight per lane.
+template <int LPG, int GPL>
 __global__ __launch_bounds__(256) void reduce_rows_kernel(ReduceArgs a) {
-  const int sub = threadIdx.x & 15;
-  const int64_t g = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int sub = threadIdx.x & (LPG - 1);
+  const int gbase = (int)(threadIdx.x & 63) & ~(LPG - 1);      // first lane of the group in the wave
+  const int64_t g = ((int64_t)blockIdx.x * 256 + threadIdx.x) / LPG;
   const bool live = g < a.n;
-  float accd[CPL];
+  float4 acc[GPL];
 #pragma unroll
-  for (int k = 0; k < CPL; ++k) accd[k] = 0.f;
+  for (int k = 0; k < GPL; ++k) acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
   float acc9 = 0.f;
   const bool ok = a.report[kRepStatus] == 0ull;
   const uint32_t cnt = (live && ok) ? a.count[g] : 0u;
   const uint32_t e0 = cnt ? a.eoff[g] : 0u;
   uint32_t cmax = cnt;
-  for (int o = 32; o > 0; o >>= 1) cmax = max(cmax, (uint32_t)__shfl_xor((int)cmax, o, 64));
-  for (uint32_t base = 0; base < cmax; base += 16) {
+  for (int o = 32; o >= LPG; o >>= 1) cmax = max(cmax, (uint32_t)__shfl_xor((int)cmax, o, 64));
+  const int D4 = a.D >> 2;                  // whole 4-channel groups
+  for (uint32_t base = 0; base < cmax; base += LPG) {
     const uint32_t ri = base + sub < cnt ? a.rowidx[e0 + base + sub] : 0u;
     const unsigned long long m = __ballot(ri != 0u);
-    uint32_t mine = (uint32_t)((m >> (threadIdx.x & 48)) & 0xFFFFull);
-    int most = __popc(mine);
-    for (int o = 32; o > 0; o >>= 1) most = max(most, __shfl_xor(most, o, 64));
-    for (int k = 0; k < most; ++k) {
-      const int b = mine ? __ffs(mine) - 1 : 0;
-      const uint32_t r = (uint32_t)__shfl((int)ri, (int)(threadIdx.x & 48) + b, 64);
-      if (mine != 0u) {
-        const float* src = a.rows + (int64_t)(r - 1) * a.RS;
+    unsigned long long mine = LPG == 64 ? m : (m >> gbase) & ((1ull << (LPG & 63)) - 1ull);
+    int most = __popcll(mine);
+    for (int o = 32; o >= LPG; o >>= 1) most = max(most, __shfl_xor(most, o, 64));
+    for (int k = 0; k < most; k += 4) {
+      uint32_t r[4];
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-          const int ch = sub * CPL + c;
-          if (ch < a.D) accd[c] += src[ch];
-        }
-        if (sub < 9) acc9 += src[a.D + sub];
+      for (int t = 0; t < 4; ++t) {
+        const int b = mine ? __ffsll(mine) - 1 : 0;
+        r[t] = (uint32_t)__shfl((int)ri, gbase + b, 64);
+        r[t] = mine ? r[t] : 0u;
         mine &= mine - 1;
+      }
+      float4 v[4][GPL];
+      float t9[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float* src = a.rows + (int64_t)(r[t] ? r[t] - 1 : 0) * a.RS;
+#pragma unroll
+        for (int q = 0; q < GPL; ++q) {
+          const int grp = sub + q * LPG;
+          v[t][q] = (r[t] && grp < D4) ? *reinterpret_cast<const float4*>(src + 4 * grp) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        // channels past the last whole group, and the 9 projected-space sums
+        const int c = 4 * D4 + sub;
+        t9[t] = (r[t] && c < a.D + 9) ? src[c] : 0.f;
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+#pragma unroll
+        for (int q = 0; q < GPL; ++q) {
+          acc[q].x += v[t][q].x;
+          acc[q].y += v[t][q].y;
+          acc[q].z += v[t][q].z;
+          acc[q].w += v[t][q].w;
+        }
+        acc9 += t9[t];
       }
     }
   }
   if (!live) return;
   float* fo = a.grad_feat + g * a.D;
 #pragma unroll
-  for (int c = 0; c < CPL; ++c) {
-    const int ch = sub * CPL + c;
-    if (ch < a.D) fo[ch] = a.accumulate ? fo[ch] + accd[c] : accd[c];
+  for (int q = 0; q < GPL; ++q) {
+    const int grp = sub + q * LPG;
+    if (grp < D4) {
+      float4 x = acc[q];
+      if (a.vec_out) {
+        float4* o4 = reinterpret_cast<float4*>(fo + 4 * grp);
+        if (a.accumulate) {
+          const float4 y = *o4;
+          x = make_float4(x.x + y.x, x.y + y.y, x.z + y.z, x.w + y.w);
+        }
+        *o4 = x;
+      } else {
+        const float xs[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) fo[4 * grp + j] = a.accumulate ? fo[4 * grp + j] + xs[j] : xs[j];
+      }
+    }
   }
-  if (sub < 12) a.grad2d[g * 12 + sub] = sub < 9 ? acc9 : 0.f;
+  // lane sub holds column 4 D4 + sub: a leftover channel or one of the 9 sums
+  const int c = 4 * D4 + sub;
+  if (c < a.D) fo[c] = a.accumulate ? fo[c] + acc9 : acc9;
+  // the 9 sums sit in lanes (D - 4 D4) .. (D - 4 D4 + 8)
+  const int k9 = c - a.D;
+  if (k9 >= 0 && k9 < 9) a.grad2d[g * 12 + k9] = acc9;
+  if (sub < 3) a.grad2d[g * 12 + 9 + sub] = 0.f;
 }
 
 template <int DP, typename FT>
@@ -663,13 +673,20 @@ hipError_t launch_reduce_rows(const fe_config* cfg, const StateView& v, const ui
   a.grad2d = grad2d;
   a.grad_feat = grad_feat;
   a.accumulate = (cfg->flags & FE_FLAG_NO_ZERO_GRADS) ? 1 : 0;
-  const unsigned blocks = (unsigned)((v.n + 15) / 16);
+  a.vec_out = cfg->feat_dim % 4 == 0 && reinterpret_cast<uintptr_t>(grad_feat) % 16 == 0;
   const int D = cfg->feat_dim;
-  if (D <= 16) hipLaunchKernelGGL(reduce_rows_kernel<1>, dim3(blocks), dim3(256), 0, s, a);
-  else if (D <= 32) hipLaunchKernelGGL(reduce_rows_kernel<2>, dim3(blocks), dim3(256), 0, s, a);
-  else if (D <= 64) hipLaunchKernelGGL(reduce_rows_kernel<4>, dim3(blocks), dim3(256), 0, s, a);
-  else if (D <= 128) hipLaunchKernelGGL(reduce_rows_kernel<8>, dim3(blocks), dim3(256), 0, s, a);
-  else hipLaunchKernelGGL(reduce_rows_kernel<16>, dim3(blocks), dim3(256), 0, s, a);
+  // lanes per Gaussian: enough 4-channel groups per lane for the row, and at
+  // least 16 lanes so that the leftover channels and the 9 sums have a lane
+  if (D <= 64) {
+    const unsigned blocks = (unsigned)((v.n + 15) / 16);
+    hipLaunchKernelGGL((reduce_rows_kernel<16, 1>), dim3(blocks), dim3(256), 0, s, a);
+  } else if (D <= 128) {
+    const unsigned blocks = (unsigned)((v.n + 7) / 8);
+    hipLaunchKernelGGL((reduce_rows_kernel<32, 1>), dim3(blocks), dim3(256), 0, s, a);
+  } else {
+    const unsigned blocks = (unsigned)((v.n + 3) / 4);
+    hipLaunchKernelGGL((reduce_rows_kernel<64, 1>), dim3(blocks), dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -134,4 +134,46 @@ __device__ __forceinline__ float load_as_float<uint16_t>(const void* p, int64_t 
   return bf16_bits_to_float(static_cast<const uint16_t*>(p)[i]);
 }
 
+// Four consecutive channels of a feature row, kept in their storage form
+// while in flight (two registers for bf16).  `vec` (uniform) says the row
+// start and the channel group are aligned for one vector load.
+template <typename FT>
+struct FeatGroup;
+template <>
+struct FeatGroup<float> {
+  float4 v;
+  __device__ __forceinline__ void clear() { v = make_float4(0.f, 0.f, 0.f, 0.f); }
+  __device__ __forceinline__ void load(const void* p, int64_t base, int c, int D, bool vec) {
+    const float* f = static_cast<const float*>(p) + base + c;
+    if (vec) {
+      v = *reinterpret_cast<const float4*>(f);
+    } else {
+      v.x = c < D ? f[0] : 0.f;
+      v.y = c + 1 < D ? f[1] : 0.f;
+      v.z = c + 2 < D ? f[2] : 0.f;
+      v.w = c + 3 < D ? f[3] : 0.f;
+    }
+  }
+  __device__ __forceinline__ float get(int j) const { return j == 0 ? v.x : j == 1 ? v.y : j == 2 ? v.z : v.w; }
+};
+template <>
+struct FeatGroup<uint16_t> {
+  uint2 v;
+  __device__ __forceinline__ void clear() { v = make_uint2(0u, 0u); }
+  __device__ __forceinline__ void load(const void* p, int64_t base, int c, int D, bool vec) {
+    const uint16_t* f = static_cast<const uint16_t*>(p) + base + c;
+    if (vec) {
+      v = *reinterpret_cast<const uint2*>(f);
+    } else {
+      const uint32_t e0 = c < D ? f[0] : 0u, e1 = c + 1 < D ? f[1] : 0u;
+      const uint32_t e2 = c + 2 < D ? f[2] : 0u, e3 = c + 3 < D ? f[3] : 0u;
+      v = make_uint2(e0 | (e1 << 16), e2 | (e3 << 16));
+    }
+  }
+  __device__ __forceinline__ float get(int j) const {
+    const uint32_t w = j < 2 ? v.x : v.y;
+    return __uint_as_float((j & 1) ? (w & 0xFFFF0000u) : (w << 16));
+  }
+};
+
 }  // namespace fe

@@ -34,8 +34,9 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kNB = 32;            // Gaussians per batch
-constexpr int kRowPad = 8;         // bf16 padding per LDS feature row (bank spread)
-constexpr int kRow = kNB + kRowPad;
+typedef short i16x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 struct MfmaArgs {
   const uint2* ranges;
@@ -54,6 +55,7 @@ struct MfmaArgs {
   float bg[3];
   int32_t W, H, tile_w, tiles_x;
   int32_t D;
+  bool vec;                      // feature rows allow aligned 4-channel vector loads
 };
 
 __device__ __forceinline__ bool pair_alpha(float fpx, float fpy, int px, int py, float2 m, float4 co,
@@ -79,21 +81,31 @@ __device__ __forceinline__ void split3(float x, __bf16& hi, __bf16& mid, __bf16&
   lo = (__bf16)r2;
 }
 
-template <typename FT>
-__device__ __forceinline__ void load4(const void* feat, int64_t base, int c, int D, float v[4]);
-
-template <>
-__device__ __forceinline__ void load4<float>(const void* feat, int64_t base, int c, int D, float v[4]) {
-  const float* p = static_cast<const float*>(feat) + base;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) v[j] = c + j < D ? p[c + j] : 0.f;
+// bf16 bits of four channels, packed two per register
+__device__ __forceinline__ uint2 pack_bf16x4(__bf16 a0, __bf16 a1, __bf16 a2, __bf16 a3) {
+  auto bits = [](__bf16 h) { return (uint32_t)__builtin_bit_cast(uint16_t, h); };
+  return make_uint2(bits(a0) | (bits(a1) << 16), bits(a2) | (bits(a3) << 16));
 }
 
-template <>
-__device__ __forceinline__ void load4<uint16_t>(const void* feat, int64_t base, int c, int D, float v[4]) {
-  const uint16_t* p = static_cast<const uint16_t*>(feat) + base;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) v[j] = c + j < D ? bf16_bits_to_float(p[c + j]) : 0.f;
+// MFMA A operand (channels x Gaussians) from the Gaussian-major feature
+// tile with two LDS transpose loads.  ds_read_b64_tr_b16 works on groups of
+// 16 lanes: lane m of a group receives element m % 4 of the 4-element chunks
+// addressed by lanes m / 4 + 4 j (j = 0..3) of its group.  Lane L therefore
+// addresses row 8 (L / 32) + (L % 16) / 4 (+ 4 for the second load), column
+// 16 ((L / 16) % 2) + 4 (L % 4) of the 32-channel block, and receives
+// channel L % 32 of Gaussians 8 (L / 32) + 0..7.
+template <int FROW>
+__device__ __forceinline__ bf16x8 load_a_tr(const __bf16* plane, int krow0, int c0, int lane) {
+  const int r = krow0 + 8 * (lane >> 5) + ((lane & 15) >> 2);
+  const int c = c0 + 16 * ((lane >> 4) & 1) + 4 * (lane & 3);
+  typedef __attribute__((address_space(3))) i16x4 lds_i16x4;
+  const i16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4*)(plane + r * FROW + c));
+  const i16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4*)(plane + (r + 4) * FROW + c));
+  // whole-register reinterpretation: per-element bf16 casts of the loaded
+  // vectors were mis-compiled (elements 1..3 replaced by element 0)
+  const u32x2 l2 = __builtin_bit_cast(u32x2, lo), h2 = __builtin_bit_cast(u32x2, hi);
+  const u32x4 q = {l2[0], l2[1], h2[0], h2[1]};
+  return __builtin_bit_cast(bf16x8, q);
 }
 
 // occupancy target: two waves per SIMD where everything fits without spills
@@ -106,11 +118,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(fwd_waves_pe
 void composite_fwd_mfma_kernel(MfmaArgs a) {
   constexpr int NPL = std::is_same<FT, float>::value ? 3 : 1;   // feature planes (hi, mid, lo)
   constexpr int CB = DP / 32;                                    // channel blocks
+  // Gaussian-major feature rows; a stride of 16 banks mod 64 keeps the
+  // transpose loads of 32 lanes (4 rows x 2 column halves) conflict-free
+  constexpr int FROW = DP + 32;
   __shared__ float2 s_xy[kNB];
   __shared__ float4 s_co[kNB];
   __shared__ float4 s_rgb[kNB];
   __shared__ int4 s_box[kNB];
-  __shared__ __attribute__((aligned(16))) __bf16 s_ft[NPL][DP][kRow];
+  __shared__ __attribute__((aligned(16))) __bf16 s_f[NPL][kNB][FROW];
   __shared__ int s_maxlast;
 
   const int tile = blockIdx.x;
@@ -141,7 +156,7 @@ void composite_fwd_mfma_kernel(MfmaArgs a) {
   constexpr int FQ = DP / 4;                               // 4-channel groups per row
   constexpr int FI = (kNB * FQ + NT - 1) / NT;             // feature groups per thread
   uint32_t id_n[FI + 1];                                   // ids of the next batch to load
-  float fv[FI][4];                                         // prefetched feature groups
+  FeatGroup<FT> fv[FI];                                    // prefetched feature groups
   float2 p_xy = make_float2(0.f, 0.f);
   float4 p_co = make_float4(0.f, 0.f, 0.f, 0.f), p_rgb = p_co;
   short4 p_box = make_short4(1, 1, 0, 0);
@@ -157,9 +172,8 @@ void composite_fwd_mfma_kernel(MfmaArgs a) {
 #pragma unroll
     for (int k = 0; k < FI; ++k) {
       const int c = ((threadIdx.x + k * NT) % FQ) * 4;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) fv[k][j] = 0.f;
-      if (id_n[k] != 0xFFFFFFFFu) load4<FT>(a.feat, (int64_t)id_n[k] * a.D, c, a.D, fv[k]);
+      fv[k].clear();
+      if (id_n[k] != 0xFFFFFFFFu && c < a.D) fv[k].load(a.feat, (int64_t)id_n[k] * a.D, c, a.D, a.vec);
     }
     if (id_n[FI] != 0xFFFFFFFFu) {
       const uint32_t g = id_n[FI];
@@ -190,19 +204,19 @@ void composite_fwd_mfma_kernel(MfmaArgs a) {
       if (e < kNB * FQ) {
         const int i = e / FQ;
         const int c = (e % FQ) * 4;
+        __bf16 pl[NPL][4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const float v = i < nb ? fv[k][j] : 0.f;
+          const float v = i < nb ? fv[k].get(j) : 0.f;
           if constexpr (NPL == 1) {
-            s_ft[0][c + j][i] = (__bf16)v;   // exact: the value is a bf16
+            pl[0][j] = (__bf16)v;   // exact: the value is a bf16
           } else {
-            __bf16 h, m, l;
-            split3(v, h, m, l);
-            s_ft[0][c + j][i] = h;
-            s_ft[1][c + j][i] = m;
-            s_ft[2][c + j][i] = l;
+            split3(v, pl[0][j], pl[1][j], pl[2][j]);
           }
         }
+#pragma unroll
+        for (int p = 0; p < NPL; ++p)
+          *reinterpret_cast<uint2*>(&s_f[p][i][c]) = pack_bf16x4(pl[p][0], pl[p][1], pl[p][2], pl[p][3]);
       }
     }
     // ---- issue the next batch's loads ----
@@ -269,13 +283,11 @@ void composite_fwd_mfma_kernel(MfmaArgs a) {
         split3(__uint_as_float(r[1]), h, m, l);
         bw[1][0][j] = h; bw[1][1][j] = m; bw[1][2][j] = l;
       }
-      const int krow = 16 * s + 8 * (lane >> 5);
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) {
-        const int c = 32 * cb + (lane & 31);
         bf16x8 fa[NPL];
 #pragma unroll
-        for (int p = 0; p < NPL; ++p) fa[p] = *reinterpret_cast<const bf16x8*>(&s_ft[p][c][krow]);
+        for (int p = 0; p < NPL; ++p) fa[p] = load_a_tr<FROW>(&s_f[p][0][0], 16 * s, 32 * cb, lane);
 #pragma unroll
         for (int pb = 0; pb < 2; ++pb) {
           f32x16 z = acc[pb][cb];
@@ -375,6 +387,8 @@ hipError_t launch_composite_fwd_mfma(const fe_config* cfg, const fe_camera* cam,
   a.tile_w = cfg->tile_w;
   a.tiles_x = v.tiles_x;
   a.D = cfg->feat_dim;
+  const size_t esz = cfg->feat_dtype == FE_BF16 ? 2 : 4;
+  a.vec = cfg->feat_dim % 4 == 0 && reinterpret_cast<uintptr_t>(g->feat) % (4 * esz) == 0;
   const int nt = cfg->tile_w * cfg->tile_h;
   return cfg->feat_dtype == FE_BF16 ? dispatch<uint16_t>(cfg->feat_dim, nt, a, v.tiles, s)
                                     : dispatch<float>(cfg->feat_dim, nt, a, v.tiles, s);
