@@ -31,6 +31,7 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kNB = 32;
 
@@ -118,6 +119,10 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
   __bf16 (*s_w)[2][kNB][WROW] = reinterpret_cast<__bf16 (*)[2][kNB][WROW]>(s_raw);
   float (*s_df)[kNB][DFROW] = reinterpret_cast<float (*)[kNB][DFROW]>(s_raw + kWBytes);   // [KSPL]
   __shared__ int s_live[NW];
+  __shared__ float s_gr[3][NT];                              // upstream colour gradient of the tile
+  // MFMA B operands of the colour sums, per wave and 32-pixel k step: lane l
+  // holds colour l % 16 (zero from 3 on) at pixels 8 (l / 16) + 0..7, hi / lo
+  __shared__ bf16x8 s_grb[NW][2][2][64];
 
   const int tile = blockIdx.x;
   const int lane = threadIdx.x & 63;
@@ -205,6 +210,9 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
       gv[c] = (inside && ch < a.D) ? a.d_feat[ch * HW + (int64_t)py * a.W + px] : 0.f;
     }
   };
+  s_gr[0][threadIdx.x] = gr0;
+  s_gr[1][threadIdx.x] = gr1;
+  s_gr[2][threadIdx.x] = gr2;
   load_g(0);
   load_data();
   load_ids(walk - kNB);
@@ -245,6 +253,23 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
   int wave_last = last;
   for (int o = 32; o > 0; o >>= 1) wave_last = max(wave_last, __shfl_xor(wave_last, o, 64));
 
+  {
+    const int n = lane & 15;
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      bf16x8 h, l;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const float x = n < 3 ? s_gr[n < 3 ? n : 0][64 * wave + 32 * ks + 8 * (lane >> 4) + j] : 0.f;
+        __bf16 xh, xl;
+        split2(x, xh, xl);
+        h[j] = xh;
+        l[j] = xl;
+      }
+      s_grb[wave][ks][0][lane] = h;
+      s_grb[wave][ks][1][lane] = l;
+    }
+  }
   __syncthreads();   // the gradient slices are consumed; the region now holds W and dF
   for (int e = threadIdx.x; e < 12 * kNB; e += NT) (&s_red[0][0])[e] = 0.f;
 
@@ -350,43 +375,45 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
           wg[u] = ct[u] ? w : 0.f;
           dag[u] = ct[u] ? da : 0.f;
         }
-        float red[GR][3];
-        bool any[GR];
 #pragma unroll
         for (int u = 0; u < GR; ++u) {
-          const int i = gi * GR + u;
-          {
-            // W^T of the wave into LDS (Gaussian-major, pixels contiguous)
-            __bf16 h, l;
-            split2(wg[u], h, l);
-            s_w[wave][0][i][lane] = h;
-            s_w[wave][1][i][lane] = l;
-          }
-          // a Gaussian that no pixel of the wave blends adds nothing
-          any[u] = __ballot(ct[u]) != 0ull;
-          red[u][0] = red[u][1] = red[u][2] = 0.f;
-          if (!any[u]) continue;
-          const float4 co = s_co[i];
-          const float opG = co.w * Gv[u];
-          const bool unclamped = opG <= kAlphaMax;
-          const float dq = unclamped ? -0.5f * opG * dag[u] : 0.f;
-          const float dx = dxv[u], dy = dyv[u];
+          // W^T of the wave into LDS (Gaussian-major, pixels contiguous)
+          __bf16 h, l;
+          split2(wg[u], h, l);
+          s_w[wave][0][gi * GR + u][lane] = h;
+          s_w[wave][1][gi * GR + u][lane] = l;
+        }
+        // Sums over the wave's 64 pixels of [dL/du, dL/dv, dL/dA, dL/dB,
+        // dL/dC, dL/do] for two Gaussians at a time (12 values): halve with
+        // the 32-lane swap (lanes >= 32 keep the second Gaussian), then the
+        // 16-lane swap (odd rows keep values 3..5), then a 16-lane row sum;
+        // lane 15 of row r holds Gaussian u0 + r / 2, values 3 (r % 2) + 0..2.
+        // A pair that no pixel of the wave blends adds nothing.
+        float red[GR / 2][3];
+        bool anyp[GR / 2];
+#pragma unroll
+        for (int up = 0; up < GR / 2; ++up) {
+          const int u0 = 2 * up;
+          anyp[up] = __ballot(ct[u0] | ct[u0 + 1]) != 0ull;
+          red[up][0] = red[up][1] = red[up][2] = 0.f;
+          if (!anyp[up]) continue;
           float vals[12];
-          vals[0] = -2.0f * dq * (co.x * dx + co.y * dy);
-          vals[1] = -2.0f * dq * (co.y * dx + co.z * dy);
-          vals[2] = dq * dx * dx;
-          vals[3] = dq * 2.0f * dx * dy;
-          vals[4] = dq * dy * dy;
-          vals[5] = unclamped ? Gv[u] * dag[u] : 0.f;
-          vals[6] = wg[u] * gr0;
-          vals[7] = wg[u] * gr1;
-          vals[8] = wg[u] * gr2;
-          vals[9] = 0.f;
-          vals[10] = 0.f;
-          vals[11] = 0.f;
-          // sum over the wave's 64 pixels: halve with the 32- and 16-lane
-          // swaps (each lane keeps 3 of the 12 values, summed over 4 lanes),
-          // then a 16-lane row sum; lane 15 of row r holds values 3r..3r+2
+#pragma unroll
+          for (int hf = 0; hf < 2; ++hf) {
+            const int u = u0 + hf;
+            const float4 co = s_co[gi * GR + u];
+            const float opG = co.w * Gv[u];
+            const bool unclamped = opG <= kAlphaMax;
+            const float dq = unclamped ? -0.5f * opG * dag[u] : 0.f;
+            const float dx = dxv[u], dy = dyv[u];
+            float* v = vals + 6 * hf;
+            v[0] = -2.0f * dq * (co.x * dx + co.y * dy);
+            v[1] = -2.0f * dq * (co.y * dx + co.z * dy);
+            v[2] = dq * dx * dx;
+            v[3] = dq * 2.0f * dx * dy;
+            v[4] = dq * dy * dy;
+            v[5] = unclamped ? Gv[u] * dag[u] : 0.f;
+          }
           float h6[6];
 #pragma unroll
           for (int k = 0; k < 6; ++k) {
@@ -398,16 +425,41 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
           for (int k = 0; k < 3; ++k) {
             const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(h6[k]), __float_as_uint(h6[k + 3]),
                                                             false, false);
-            red[u][k] = row_sum16(__uint_as_float(r[0]) + __uint_as_float(r[1]));
+            red[up][k] = row_sum16(__uint_as_float(r[0]) + __uint_as_float(r[1]));
           }
         }
         if ((lane & 15) == 15) {
-          const int base = 6 * (lane >> 5) + 3 * ((lane >> 4) & 1);
+          const int base = 3 * ((lane >> 4) & 1);
 #pragma unroll
-          for (int u = 0; u < GR; ++u)
-            if (any[u])
+          for (int up = 0; up < GR / 2; ++up)
+            if (anyp[up])
 #pragma unroll
-              for (int k = 0; k < 3; ++k) atomicAdd(&s_red[base + k][gi * GR + u], red[u][k]);
+              for (int k = 0; k < 3; ++k) atomicAdd(&s_red[base + k][gi * GR + 2 * up + (lane >> 5)], red[up][k]);
+        }
+      }
+      // ---- colour sums dL/dc_i = sum_p w_i(p) g_rgb(p) of the wave's pixels on the
+      //      matrix cores: 16x16x32 MFMAs, A = W^T (16 Gaussians x 32 pixels) from
+      //      LDS, B = the tile's upstream colour gradient (columns 0..2) ----
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb) {
+        f32x4 cs = f32x4{};
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+          const int kp = 32 * ks + 8 * (lane >> 4);
+          const bf16x8 wh = *reinterpret_cast<const bf16x8*>(&s_w[wave][0][16 * mb + (lane & 15)][kp]);
+          const bf16x8 wl = *reinterpret_cast<const bf16x8*>(&s_w[wave][1][16 * mb + (lane & 15)][kp]);
+          const bf16x8 gh = s_grb[wave][ks][0][lane];
+          const bf16x8 gl = s_grb[wave][ks][1][lane];
+          cs = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, gh, cs, 0, 0, 0);
+          cs = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, gl, cs, 0, 0, 0);
+          cs = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl, gh, cs, 0, 0, 0);
+        }
+        if ((lane & 15) < 3) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) atomicAdd(&s_red[6 + (lane & 15)][16 * mb + 4 * (lane >> 4) + v], cs[v]);
         }
       }
     }
