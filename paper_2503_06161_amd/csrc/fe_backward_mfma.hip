@@ -138,6 +138,20 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
   const bool inside = (px < a.W) & (py < a.H);
   const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
   const int64_t HW = (int64_t)a.W * a.H;
+  // The upstream feature gradient of this thread's pixel is loaded first, GS
+  // 32-channel slices at once (all of them for D <= 128), so that its latency
+  // overlaps the tile's list lookups and the first batch's loads.
+  constexpr int GS = CB < (F32 ? 2 : 4) ? CB : (F32 ? 2 : 4);
+  float gv[GS][32];
+  auto load_g = [&](int cb, float* dst) {
+#pragma unroll
+    for (int c = 0; c < 32; ++c) {
+      const int ch = 32 * cb + c;
+      dst[c] = (inside && ch < a.D) ? a.d_feat[ch * HW + (int64_t)py * a.W + px] : 0.f;
+    }
+  };
+#pragma unroll
+  for (int cb = 0; cb < GS; ++cb) load_g(cb, gv[cb]);
   const uint2 rg = a.ranges[tile];
   const int walk = (int)min(a.tile_maxlast[tile], rg.y - rg.x);
   const int64_t row0 = a.row_base[tile];
@@ -155,6 +169,7 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
   constexpr int FQ = DP / 4;                               // 4-channel groups per row
   constexpr int FI = (kNB * FQ + NT - 1) / NT;             // feature groups per thread
   uint32_t id_n;                                          // Gaussian (tid % kNB) of the next batch
+  uint32_t ep_n = 0, ep_data = 0, ep_cur = 0;             // its emit position (row index slot), pipelined
   FeatGroup<FT> fv[FI];
   float2 p_xy = make_float2(0.f, 0.f);
   float4 p_co = make_float4(0.f, 0.f, 0.f, 0.f), p_rgb = p_co;
@@ -164,7 +179,9 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
   const int si = (int)threadIdx.x % kNB;
   auto load_ids = [&](int r1) {
     const int r0 = r1 > kNB ? r1 - kNB : 0;
-    id_n = r0 + si < r1 ? a.gauss[rg.x + r0 + si] : 0xFFFFFFFFu;
+    const bool ok = r0 + si < r1;
+    id_n = ok ? a.gauss[rg.x + r0 + si] : 0xFFFFFFFFu;
+    ep_n = (ok && (int)threadIdx.x < kNB) ? (a.epos ? a.epos[rg.x + r0 + si] : rg.x + r0 + si) : 0u;
   };
   auto load_data = [&]() {
 #pragma unroll
@@ -174,6 +191,7 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
       fv[k].clear();
       if (e < kNB * FQ && id_n != 0xFFFFFFFFu && c < a.D) fv[k].load(a.feat, (int64_t)id_n * a.D, c, a.D, a.vec);
     }
+    ep_data = ep_n;
     if ((int)threadIdx.x < kNB && id_n != 0xFFFFFFFFu) {
       const uint32_t g = id_n;
       p_xy = a.xy[g];
@@ -198,30 +216,20 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
   }
 
   // ---- upstream feature gradient of the wave's 64 pixels, in both operand layouts,
-  //      staged through LDS one 32-channel slice at a time; the loads of slice
-  //      cb + 1 are in flight while slice cb is converted ----
+  //      staged through LDS one 32-channel slice at a time ----
   bf16x8 g1[2][KS1][2];   // GEMM1 B: [pixel block][k step][hi, lo]; lane: pixel l%32, channels 8(l/32)+j
   bf16x8 g2[CB][4][2];    // GEMM2 B: [unit][k step][hi, lo]; lane: channel l%32, pixels 8(l/32)+j of the chunk
-  float gv[32];
-  auto load_g = [&](int cb) {
-#pragma unroll
-    for (int c = 0; c < 32; ++c) {
-      const int ch = 32 * cb + c;
-      gv[c] = (inside && ch < a.D) ? a.d_feat[ch * HW + (int64_t)py * a.W + px] : 0.f;
-    }
-  };
   s_gr[0][threadIdx.x] = gr0;
   s_gr[1][threadIdx.x] = gr1;
   s_gr[2][threadIdx.x] = gr2;
-  load_g(0);
   load_data();
   load_ids(walk - kNB);
 #pragma unroll
   for (int cb = 0; cb < CB; ++cb) {
     if (cb > 0) __syncthreads();
 #pragma unroll
-    for (int c = 0; c < 32; ++c) s_g[c][threadIdx.x] = gv[c];
-    if (cb + 1 < CB) load_g(cb + 1);
+    for (int c = 0; c < 32; ++c) s_g[c][threadIdx.x] = gv[cb % GS][c];
+    if (cb + GS < CB) load_g(cb + GS, gv[cb % GS]);
     __syncthreads();
 #pragma unroll
     for (int pb = 0; pb < 2; ++pb)
@@ -271,13 +279,14 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
     }
   }
   __syncthreads();   // the gradient slices are consumed; the region now holds W and dF
-  for (int e = threadIdx.x; e < 12 * kNB; e += NT) (&s_red[0][0])[e] = 0.f;
 
   for (int r1 = walk; r1 > 0; r1 -= kNB) {
     const int pos0 = r1 > kNB ? r1 - kNB : 0;
     const int nb = r1 - pos0;
     __syncthreads();
-    // ---- stage the batch from registers ----
+    // ---- stage the batch from registers; clear the per-Gaussian sums ----
+    ep_cur = ep_data;
+    for (int e = threadIdx.x; e < 12 * kNB; e += NT) (&s_red[0][0])[e] = 0.f;
     if ((int)threadIdx.x < kNB) {
       s_xy[threadIdx.x] = p_xy;
       s_co[threadIdx.x] = p_co;
@@ -342,7 +351,7 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
 #pragma unroll
       for (int gi = kNB / GR - 1; gi >= 0; --gi) {
         float al[GR], Gv[GR], dxv[GR], dyv[GR];
-        bool ct[GR];
+        bool ct[GR], unc[GR];
 #pragma unroll
         for (int u = 0; u < GR; ++u) {
           const int i = gi * GR + u;
@@ -353,14 +362,19 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
           const float q = __builtin_fmaf(co.x * dx, dx, __builtin_fmaf(co.z * dy, dy, 2.0f * co.y * dx * dy));
           const bool inb = (px >= b.x) & (px <= b.z) & (py >= b.y) & (py <= b.w);
           const float G = __expf(-0.5f * q);
-          const float alpha = fminf(kAlphaMax, co.w * G);
+          const float opG = co.w * G;
+          const float alpha = fminf(kAlphaMax, opG);
           ct[u] = (i < nb) & (pos0 + i < last) & inb & (q <= kQMax) & (alpha >= kAlphaMin);
+          unc[u] = opG <= kAlphaMax;   // alpha not clamped: it depends on opacity and q
           al[u] = alpha;
           Gv[u] = G;
           dxv[u] = dx;
           dyv[u] = dy;
         }
-        float wg[GR], dag[GR];
+        // X = G dL/dalpha for blended, unclamped pairs: every projected-space
+        // gradient of the pair is X times a factor of the Gaussian (opacity,
+        // conic) and of (dx, dy), applied after the pixel sums
+        float wg[GR], xg[GR];
 #pragma unroll
         for (int u = GR - 1; u >= 0; --u) {
           const int i = gi * GR + u;
@@ -373,7 +387,7 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
           T = ct[u] ? Tn : T;
           acc = ct[u] ? __builtin_fmaf(w, sv, acc) : acc;
           wg[u] = ct[u] ? w : 0.f;
-          dag[u] = ct[u] ? da : 0.f;
+          xg[u] = (ct[u] & unc[u]) ? Gv[u] * da : 0.f;
         }
 #pragma unroll
         for (int u = 0; u < GR; ++u) {
@@ -383,8 +397,8 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
           s_w[wave][0][gi * GR + u][lane] = h;
           s_w[wave][1][gi * GR + u][lane] = l;
         }
-        // Sums over the wave's 64 pixels of [dL/du, dL/dv, dL/dA, dL/dB,
-        // dL/dC, dL/do] for two Gaussians at a time (12 values): halve with
+        // Sums over the wave's 64 pixels of [X dx, X dy, X dx^2, X dx dy,
+        // X dy^2, X] for two Gaussians at a time (12 values): halve with
         // the 32-lane swap (lanes >= 32 keep the second Gaussian), then the
         // 16-lane swap (odd rows keep values 3..5), then a 16-lane row sum;
         // lane 15 of row r holds Gaussian u0 + r / 2, values 3 (r % 2) + 0..2.
@@ -401,18 +415,15 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
 #pragma unroll
           for (int hf = 0; hf < 2; ++hf) {
             const int u = u0 + hf;
-            const float4 co = s_co[gi * GR + u];
-            const float opG = co.w * Gv[u];
-            const bool unclamped = opG <= kAlphaMax;
-            const float dq = unclamped ? -0.5f * opG * dag[u] : 0.f;
-            const float dx = dxv[u], dy = dyv[u];
+            const float X = xg[u];
+            const float Xdx = X * dxv[u], Xdy = X * dyv[u];
             float* v = vals + 6 * hf;
-            v[0] = -2.0f * dq * (co.x * dx + co.y * dy);
-            v[1] = -2.0f * dq * (co.y * dx + co.z * dy);
-            v[2] = dq * dx * dx;
-            v[3] = dq * 2.0f * dx * dy;
-            v[4] = dq * dy * dy;
-            v[5] = unclamped ? Gv[u] * dag[u] : 0.f;
+            v[0] = Xdx;
+            v[1] = Xdy;
+            v[2] = Xdx * dxv[u];
+            v[3] = Xdx * dyv[u];
+            v[4] = Xdy * dyv[u];
+            v[5] = X;
           }
           float h6[6];
 #pragma unroll
@@ -503,42 +514,57 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
       }
     }
     if constexpr (KSPL > 1) __syncthreads();   // partial sums of all waves are in LDS
-    // ---- rest of the rows of this batch: [dL/df (D) | u v A B C o r g b | pad];
-    //      the 9 sums are cleared for the next batch as they are read ----
+    // ---- rest of the rows of this batch: [dL/df (D) | u v A B C o r g b | pad],
+    //      one float4 per thread and step.  The walk left the pixel sums S, Sx,
+    //      Sy, Sxx, Sxy, Syy of X, X dx, X dy, X dx^2, X dx dy, X dy^2; with the
+    //      Gaussian's conic (a, b, c) and opacity o the projected-space
+    //      gradients are o (a Sx + b Sy), o (b Sx + c Sy), -o Sxx / 2, -o Sxy,
+    //      -o Syy / 2 and S ----
     {
-      for (int i = wave; i < nb; i += NW) {
-        for (int c0 = (KSPL > 1 ? 0 : (a.D & ~3)) + 4 * lane; c0 < a.RS; c0 += 256) {
-          float v[4];
+      const int cstart = KSPL > 1 ? 0 : (a.D & ~3);   // columns before cstart were stored by GEMM2
+      const int nq = (a.RS - cstart) >> 2;
+      for (int t = threadIdx.x; t < nb * nq; t += NT) {
+        const int i = t / nq;
+        const int c0 = cstart + 4 * (t - i * nq);
+        const float4 co = s_co[i];
+        float v[4];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int c = c0 + j;
-            v[j] = 0.f;
-            if (c < a.D) {
-              if constexpr (KSPL > 1) {
+        for (int j = 0; j < 4; ++j) {
+          const int c = c0 + j;
+          float x = 0.f;
+          if (c < a.D) {
+            if constexpr (KSPL > 1) {
 #pragma unroll
-                for (int k = 0; k < KSPL; ++k) v[j] += s_df[k][i][c];
-              }
-            } else if (c < a.D + 9) {
-              v[j] = s_red[c - a.D][i];
-              s_red[c - a.D][i] = 0.f;
+              for (int k = 0; k < KSPL; ++k) x += s_df[k][i][c];
+            }
+          } else {
+            switch (c - a.D) {
+              case 0: x = co.w * (co.x * s_red[0][i] + co.y * s_red[1][i]); break;
+              case 1: x = co.w * (co.y * s_red[0][i] + co.z * s_red[1][i]); break;
+              case 2: x = -0.5f * co.w * s_red[2][i]; break;
+              case 3: x = -co.w * s_red[3][i]; break;
+              case 4: x = -0.5f * co.w * s_red[4][i]; break;
+              case 5: x = s_red[5][i]; break;
+              case 6: x = s_red[6][i]; break;
+              case 7: x = s_red[7][i]; break;
+              case 8: x = s_red[8][i]; break;
+              default: break;
             }
           }
-          float* dst = &a.rows[(row0 + pos0 + i) * a.RS + c0];
-          if (KSPL > 1 || c0 >= a.D) {
-            *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
-          } else {
-            // group straddling the end of the D columns stored by GEMM2
+          v[j] = x;
+        }
+        float* dst = &a.rows[(row0 + pos0 + i) * a.RS + c0];
+        if (KSPL > 1 || c0 >= a.D) {
+          *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+        } else {
+          // group straddling the end of the D columns stored by GEMM2
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-              if (c0 + j >= a.D) dst[j] = v[j];
-          }
+          for (int j = 0; j < 4; ++j)
+            if (c0 + j >= a.D) dst[j] = v[j];
         }
       }
     }
-    for (int i = threadIdx.x; i < nb; i += NT) {
-      const uint32_t pos = rg.x + pos0 + i;
-      a.rowidx[a.epos ? a.epos[pos] : pos] = (uint32_t)(row0 + pos0 + i + 1);
-    }
+    if ((int)threadIdx.x < nb) a.rowidx[ep_cur] = (uint32_t)(row0 + pos0 + threadIdx.x + 1);
   }
 }
 
