@@ -35,7 +35,8 @@ def _parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-tiles", type=int, default=8)
+    ap.add_argument("--cpu-sample-tiles", type=int, default=0,
+                    help="tiles blended by the CPU oracle (0: every tile, i.e. one whole frame)")
     ap.add_argument("--forms", default="bf16,f32")
     ap.add_argument("--variant", default="mfma", choices=["mfma", "valu"],
                     help="compositing kernels: matrix cores (default) or vector ALU")
@@ -179,10 +180,10 @@ def run_batched(steps, warmup):
 
 
 def cpu_baseline(sc, sample_tiles):
-    """The float64 oracle, as it is, on a bounded sample of the same frame:
-    projection + binning + projection backward for all Gaussians, and the
-    blending forward+backward of `sample_tiles` evenly spaced tiles; the frame
-    time is extrapolated to all tiles."""
+    """The float64 oracle, as it is, forward + backward on the same frame:
+    projection, binning and projection backward of all Gaussians, and the
+    blending forward+backward of every tile (or of `sample_tiles` evenly spaced
+    tiles, with the frame time extrapolated to all tiles)."""
     import numpy as np
     import torch
     import oracle
@@ -191,19 +192,26 @@ def cpu_baseline(sc, sample_tiles):
                feat=bf16_round(sc.feat))
     cfg = oracle.OracleConfig(tile_w=16, tile_h=16, sh_degree=sc.sh_degree)
     ntiles = -(-sc.cam.width // 16) * -(-sc.cam.height // 16)
-    sample = list(np.linspace(0, ntiles - 1, sample_tiles).astype(int))
-    oracle.render_backward(**inp, cam=sc.cam, cfg=cfg, d_rgb=sc.d_rgb, d_feat=sc.d_feat, tiles=sample[:1])
-    t0 = time.perf_counter()
-    oracle.render_backward(**inp, cam=sc.cam, cfg=cfg, d_rgb=sc.d_rgb, d_feat=sc.d_feat, tiles=[])
-    t1 = time.perf_counter()
-    oracle.render_backward(**inp, cam=sc.cam, cfg=cfg, d_rgb=sc.d_rgb, d_feat=sc.d_feat, tiles=sample)
-    t2 = time.perf_counter()
-    per_tile = max((t2 - t1) - (t1 - t0), 0.0) / len(sample)
-    per_frame = (t1 - t0) + per_tile * ntiles
+    oracle.render_backward(**inp, cam=sc.cam, cfg=cfg, d_rgb=sc.d_rgb, d_feat=sc.d_feat, tiles=[0])   # warm-up
+    if sample_tiles <= 0 or sample_tiles >= ntiles:
+        t0 = time.perf_counter()
+        oracle.render_backward(**inp, cam=sc.cam, cfg=cfg, d_rgb=sc.d_rgb, d_feat=sc.d_feat)
+        per_frame = time.perf_counter() - t0
+        what = f"one whole frame ({per_frame:.1f} s of CPU work)"
+    else:
+        sample = list(np.linspace(0, ntiles - 1, sample_tiles).astype(int))
+        t0 = time.perf_counter()
+        oracle.render_backward(**inp, cam=sc.cam, cfg=cfg, d_rgb=sc.d_rgb, d_feat=sc.d_feat, tiles=[])
+        t1 = time.perf_counter()
+        oracle.render_backward(**inp, cam=sc.cam, cfg=cfg, d_rgb=sc.d_rgb, d_feat=sc.d_feat, tiles=sample)
+        t2 = time.perf_counter()
+        per_tile = max((t2 - t1) - (t1 - t0), 0.0) / len(sample)
+        per_frame = (t1 - t0) + per_tile * ntiles
+        what = (f"projection, binning and projection backward of all {sc.n} Gaussians plus {len(sample)} of "
+                f"{ntiles} tiles blended forward+backward ({t2 - t0:.1f} s of CPU work), extrapolated to all tiles")
     return dict(value=1.0 / per_frame, unit="frames/s", cores=torch.get_num_threads(), kind="oracle",
-                sample=f"float64 oracle fwd+bwd: projection, binning and projection backward of all "
-                       f"{sc.n} Gaussians plus {len(sample)} of {ntiles} tiles blended forward+backward "
-                       f"({t2 - t0:.1f} s of CPU work); frame time extrapolated to all tiles")
+                sample=f"float64 oracle fwd+bwd of the {sc.cam.width}x{sc.cam.height}, {sc.n}-Gaussian, "
+                       f"D={sc.feat_dim} frame: {what}")
 
 
 def _kernel_source_hash():

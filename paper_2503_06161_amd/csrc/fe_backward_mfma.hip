@@ -568,6 +568,485 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
   }
 }
 
+#ifndef WS_GR
+#define WS_GR 4
+#endif
+// Wave-specialized form of the same computation (D <= 128 and at least as
+// many 32-channel blocks as 64-pixel chunks).  The block has 2 NT threads:
+// NT "walker" threads (one pixel each) run GEMM1, the back-to-front walk and
+// the per-Gaussian pixel sums of batch k; NT "contractor" threads run GEMM2
+// and write the rows of batch k-1, then stage the records and feature rows of
+// batch k+1.  Each role keeps only its own operand layout of the upstream
+// feature gradient in registers (128 VGPRs at D = 128), so two waves share
+// each SIMD and the latency of one role hides behind the other's issue.  One
+// barrier per batch: the weights and liveness are double-buffered, the batch
+// records double- (conic/opacity and the sums triple-) buffered.
+template <int DP, typename FT, int NT>
+__global__ __launch_bounds__(2 * NT) void composite_bwd_ws_kernel(BwdArgs a) {
+  constexpr bool F32 = std::is_same<FT, float>::value;
+  constexpr int NPF = F32 ? 2 : 1;
+  constexpr int CB = DP / 32;
+  constexpr int KS1 = DP / 16;
+  constexpr int NW = NT / 64;
+  static_assert(CB >= NW, "each contractor wave owns whole channel blocks");
+  constexpr int FROW = DP + 8;
+  constexpr int WROW = 64 + 8;
+  constexpr int GROW = NT + 1;
+  constexpr size_t kGBytes = sizeof(float) * 32 * GROW;
+  constexpr size_t kWBytes = sizeof(__bf16) * 2 * NW * 2 * kNB * WROW;
+  constexpr size_t kShared = kGBytes > kWBytes ? kGBytes : kWBytes;
+  __shared__ float2 s_xy[2][kNB];
+  __shared__ float4 s_co[3][kNB];
+  __shared__ float4 s_rgb[2][kNB];
+  __shared__ int4 s_box[2][kNB];
+  __shared__ __attribute__((aligned(16))) __bf16 s_f[2][NPF][kNB][FROW];
+  __shared__ float s_red[3][12][kNB];
+  __shared__ int s_live[2][NW];
+  __shared__ __attribute__((aligned(16))) unsigned char s_raw[kShared];
+  float (*s_g)[GROW] = reinterpret_cast<float (*)[GROW]>(s_raw);
+  __bf16 (*s_w)[NW][2][kNB][WROW] = reinterpret_cast<__bf16 (*)[NW][2][kNB][WROW]>(s_raw);   // [2]
+  __shared__ float s_gr[3][NT];
+  __shared__ bf16x8 s_grb[NW][2][2][64];
+
+  const int tile = blockIdx.x;
+  const bool walker = (int)threadIdx.x < NT;
+  const int q = walker ? (int)threadIdx.x : (int)threadIdx.x - NT;   // thread index within the role
+  const int lane = q & 63;
+  const int wave = q >> 6;                                            // wave index within the role
+  auto unit_cb = [&](int u) { return wave + NW * (u / NW); };
+  auto unit_chunk = [&](int u) { return u % NW; };
+  const int tile_h = NT / a.tile_w;
+  const int tx0 = (tile % a.tiles_x) * a.tile_w;
+  const int ty0 = (tile / a.tiles_x) * tile_h;
+  const int px = tx0 + q % a.tile_w;
+  const int py = ty0 + q / a.tile_w;
+  const bool inside = (px < a.W) & (py < a.H);
+  const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+  const int64_t HW = (int64_t)a.W * a.H;
+  // walkers: the upstream feature gradient of their pixel, all slices issued first
+  constexpr int GS = CB < (F32 ? 2 : 4) ? CB : (F32 ? 2 : 4);
+  float gv[GS][32];
+  auto load_g = [&](int cb, float* dst) {
+#pragma unroll
+    for (int c = 0; c < 32; ++c) {
+      const int ch = 32 * cb + c;
+      dst[c] = (walker && inside && ch < a.D) ? a.d_feat[ch * HW + (int64_t)py * a.W + px] : 0.f;
+    }
+  };
+  if (walker) {
+#pragma unroll
+    for (int cb = 0; cb < GS; ++cb) load_g(cb, gv[cb]);
+  }
+  const uint2 rg = a.ranges[tile];
+  const int walk = (int)min(a.tile_maxlast[tile], rg.y - rg.x);
+  const int64_t row0 = a.row_base[tile];
+  if (row0 + walk > a.row_cap) {
+    if (threadIdx.x == 0) a.report[kRepStatus] = (unsigned long long)FE_ERR_ROW_OVERFLOW;
+    return;   // uniform: nothing of this tile can be stored
+  }
+  if (walk == 0) return;
+  const int nbatch = (walk + kNB - 1) / kNB;
+  // batch k covers list positions [pos0(k), pos0(k) + nb(k)), walked back to front
+  auto bpos0 = [&](int k) { const int r1 = walk - k * kNB; return r1 > kNB ? r1 - kNB : 0; };
+  auto bnb = [&](int k) { return walk - k * kNB - bpos0(k); };
+
+  // ---- contractors: software-pipelined staging (ids of batch k+2, records
+  //      and feature rows of batch k+1 in registers while batch k is staged) ----
+  constexpr int FQ = DP / 4;
+  constexpr int FI = (kNB * FQ + NT - 1) / NT;
+  uint32_t id_n = 0xFFFFFFFFu;
+  uint32_t ep_n = 0, ep_data = 0, ep_s = 0, ep_w = 0;      // emit position of Gaussian q % kNB, pipelined
+  FeatGroup<FT> fv[FI];
+  float2 p_xy = make_float2(0.f, 0.f);
+  float4 p_co = make_float4(0.f, 0.f, 0.f, 0.f), p_rgb = p_co;
+  short4 p_box = make_short4(1, 1, 0, 0);
+  const int si = q % kNB;
+  auto load_ids = [&](int k) {
+    const int r0 = bpos0(k), r1 = r0 + bnb(k);
+    const bool ok = k < nbatch && r0 + si < r1;
+    id_n = ok ? a.gauss[rg.x + r0 + si] : 0xFFFFFFFFu;
+    ep_n = (ok && q < kNB) ? (a.epos ? a.epos[rg.x + r0 + si] : rg.x + r0 + si) : 0u;
+  };
+  auto load_data = [&]() {
+#pragma unroll
+    for (int k = 0; k < FI; ++k) {
+      const int e = q + k * NT;
+      const int c = (e / kNB) * 4;
+      fv[k].clear();
+      if (e < kNB * FQ && id_n != 0xFFFFFFFFu && c < a.D) fv[k].load(a.feat, (int64_t)id_n * a.D, c, a.D, a.vec);
+    }
+    ep_data = ep_n;
+    if (q < kNB && id_n != 0xFFFFFFFFu) {
+      p_xy = a.xy[id_n];
+      p_co = a.conic_o[id_n];
+      p_rgb = a.rgb[id_n];
+      p_box = a.box[id_n];
+    }
+  };
+  auto stage = [&](int k) {
+    const int b2 = k & 1, b3 = k % 3, nb = bnb(k);
+    ep_s = ep_data;
+    if (q < kNB) {
+      s_xy[b2][q] = p_xy;
+      s_co[b3][q] = p_co;
+      s_rgb[b2][q] = p_rgb;
+      s_box[b2][q] = make_int4(p_box.x, p_box.y, p_box.z, p_box.w);
+    }
+#pragma unroll
+    for (int k2 = 0; k2 < FI; ++k2) {
+      const int e = q + k2 * NT;
+      if (e < kNB * FQ) {
+        const int i = e % kNB;
+        const int c = (e / kNB) * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float v = i < nb ? fv[k2].get(j) : 0.f;
+          if constexpr (F32) {
+            __bf16 h, m;
+            split2(v, h, m);
+            s_f[b2][0][i][c + j] = h;
+            s_f[b2][1][i][c + j] = m;
+          } else {
+            s_f[b2][0][i][c + j] = (__bf16)v;   // exact: the value is a bf16
+          }
+        }
+      }
+    }
+  };
+  if (!walker) {
+    load_ids(0);
+    load_data();
+    load_ids(1);
+  }
+
+  // ---- walkers: per-pixel state ----
+  float gr0 = 0.f, gr1 = 0.f, gr2 = 0.f;
+  float T = 1.0f;
+  int last = 0;
+  if (walker && inside) {
+    const int64_t p = (int64_t)py * a.W + px;
+    gr0 = a.d_rgb[p];
+    gr1 = a.d_rgb[HW + p];
+    gr2 = a.d_rgb[2 * HW + p];
+    T = a.final_T[p];
+    last = a.n_contrib[p];
+  }
+  if (walker) {
+    s_gr[0][q] = gr0;
+    s_gr[1][q] = gr1;
+    s_gr[2][q] = gr2;
+  }
+
+  // ---- upstream feature gradient into the two operand layouts, one 32-channel
+  //      slice at a time through LDS: walkers keep the GEMM1 layout of their
+  //      pixels, contractors the GEMM2 layout of their channel blocks ----
+  // One register array holds the walker's GEMM1 operand or the contractor's
+  // GEMM2 operand (both DP/4 fragments), so the two roles share registers.
+  bf16x8 gop[DP / 4];
+  auto g1 = [&](int pb, int s, int h) -> bf16x8& { return gop[(pb * KS1 + s) * 2 + h]; };   // pixel block, k step, hi/lo
+  auto g2 = [&](int u, int s, int h) -> bf16x8& { return gop[(u * 4 + s) * 2 + h]; };       // unit, k step, hi/lo
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) {
+    if (cb > 0) __syncthreads();
+    if (walker) {
+#pragma unroll
+      for (int c = 0; c < 32; ++c) s_g[c][q] = gv[cb % GS][c];
+      if (cb + GS < CB) load_g(cb + GS, gv[cb % GS]);
+    }
+    __syncthreads();
+    if (walker) {
+#pragma unroll
+      for (int pb = 0; pb < 2; ++pb)
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            __bf16 h, l;
+            split2(s_g[16 * s2 + 8 * (lane >> 5) + j][64 * wave + 32 * pb + (lane & 31)], h, l);
+            g1(pb, 2 * cb + s2, 0)[j] = h;
+            g1(pb, 2 * cb + s2, 1)[j] = l;
+          }
+    } else {
+#pragma unroll
+      for (int u = 0; u < CB; ++u) {
+        if (unit_cb(u) != cb) continue;
+        const int q0 = 64 * unit_chunk(u) + 8 * (lane >> 5);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            __bf16 h, l;
+            split2(s_g[lane & 31][q0 + 16 * s + j], h, l);
+            g2(u, s, 0)[j] = h;
+            g2(u, s, 1)[j] = l;
+          }
+      }
+    }
+  }
+  float acc = T * ((gr0 * a.bg[0] + gr1 * a.bg[1]) + gr2 * a.bg[2]);
+  int wave_last = last;
+  for (int o = 32; o > 0; o >>= 1) wave_last = max(wave_last, __shfl_xor(wave_last, o, 64));
+  if (walker) {
+    const int n = lane & 15;
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      bf16x8 h, l;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const float x = n < 3 ? s_gr[n < 3 ? n : 0][64 * wave + 32 * ks + 8 * (lane >> 4) + j] : 0.f;
+        __bf16 xh, xl;
+        split2(x, xh, xl);
+        h[j] = xh;
+        l[j] = xl;
+      }
+      s_grb[wave][ks][0][lane] = h;
+      s_grb[wave][ks][1][lane] = l;
+    }
+  } else {
+    for (int e = q; e < 3 * 12 * kNB; e += NT) (&s_red[0][0][0])[e] = 0.f;
+    stage(0);
+    load_data();
+    load_ids(2);
+  }
+  __syncthreads();   // gradient slices consumed (the region now holds W), batch 0 staged
+
+  // The two roles run separate loops with the same number of barriers, so
+  // that the registers of one role are not live in the other's loop.
+  if (walker) {
+    for (int it = 0; it <= nbatch; ++it) {
+      if (it < nbatch) {
+        // ================= walkers: batch it =================
+        const int b2 = it & 1, b3 = it % 3;
+        const int pos0 = bpos0(it), nb = bnb(it);
+        const bool live = wave_last > pos0;
+        if (lane == 0) s_live[b2][wave] = live ? 1 : 0;
+        if (live) {
+          // GEMM1: S^T (Gaussians x pixels) = F (Gaussians x D) . G^T (D x pixels)
+          f32x16 s1[2] = {f32x16{}, f32x16{}};
+#pragma unroll
+          for (int s = 0; s < KS1; ++s) {
+            const int kc = 16 * s + 8 * (lane >> 5);
+            bf16x8 fa[NPF];
+#pragma unroll
+            for (int p = 0; p < NPF; ++p) fa[p] = *reinterpret_cast<const bf16x8*>(&s_f[b2][p][lane & 31][kc]);
+#pragma unroll
+            for (int pb = 0; pb < 2; ++pb) {
+              s1[pb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[0], g1(pb, s, 0), s1[pb], 0, 0, 0);
+              s1[pb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[0], g1(pb, s, 1), s1[pb], 0, 0, 0);
+              if constexpr (F32) s1[pb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[1], g1(pb, s, 0), s1[pb], 0, 0, 0);
+            }
+          }
+          float S[kNB];
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(s1[0][v]), __float_as_uint(s1[1][v]),
+                                                            false, false);
+            S[8 * (v >> 2) + (v & 3)] = __uint_as_float(r[0]);
+            S[8 * (v >> 2) + 4 + (v & 3)] = __uint_as_float(r[1]);
+          }
+          constexpr int GR = WS_GR;
+#pragma unroll
+          for (int gi = kNB / GR - 1; gi >= 0; --gi) {
+            float al[GR], Gv[GR], dxv[GR], dyv[GR];
+            bool ct[GR], unc[GR];
+#pragma unroll
+            for (int u = 0; u < GR; ++u) {
+              const int i = gi * GR + u;
+              const float2 m = s_xy[b2][i];
+              const float4 co = s_co[b3][i];
+              const int4 b = s_box[b2][i];
+              const float dx = fpx - m.x, dy = fpy - m.y;
+              const float qq = __builtin_fmaf(co.x * dx, dx, __builtin_fmaf(co.z * dy, dy, 2.0f * co.y * dx * dy));
+              const bool inb = (px >= b.x) & (px <= b.z) & (py >= b.y) & (py <= b.w);
+              const float G = __expf(-0.5f * qq);
+              const float opG = co.w * G;
+              const float alpha = fminf(kAlphaMax, opG);
+              ct[u] = (i < nb) & (pos0 + i < last) & inb & (qq <= kQMax) & (alpha >= kAlphaMin);
+              unc[u] = opG <= kAlphaMax;
+              al[u] = alpha;
+              Gv[u] = G;
+              dxv[u] = dx;
+              dyv[u] = dy;
+            }
+            float wg[GR], xg[GR];
+#pragma unroll
+            for (int u = GR - 1; u >= 0; --u) {
+              const int i = gi * GR + u;
+              const float4 c = s_rgb[b2][i];
+              const float sv = S[i] + ((gr0 * c.x + gr1 * c.y) + gr2 * c.z);
+              const float inv_om = __builtin_amdgcn_rcpf(1.0f - al[u]);
+              const float Tn = T * inv_om;
+              const float w = al[u] * Tn;
+              const float da = Tn * sv - acc * inv_om;
+              T = ct[u] ? Tn : T;
+              acc = ct[u] ? __builtin_fmaf(w, sv, acc) : acc;
+              wg[u] = ct[u] ? w : 0.f;
+              xg[u] = (ct[u] & unc[u]) ? Gv[u] * da : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < GR; ++u) {
+              __bf16 h, l;
+              split2(wg[u], h, l);
+              s_w[b2][wave][0][gi * GR + u][lane] = h;
+              s_w[b2][wave][1][gi * GR + u][lane] = l;
+            }
+            float red[GR / 2][3];
+            bool anyp[GR / 2];
+#pragma unroll
+            for (int up = 0; up < GR / 2; ++up) {
+              const int u0 = 2 * up;
+              anyp[up] = __ballot(ct[u0] | ct[u0 + 1]) != 0ull;
+              red[up][0] = red[up][1] = red[up][2] = 0.f;
+              if (!anyp[up]) continue;
+              float vals[12];
+#pragma unroll
+              for (int hf = 0; hf < 2; ++hf) {
+                const int u = u0 + hf;
+                const float X = xg[u];
+                const float Xdx = X * dxv[u], Xdy = X * dyv[u];
+                float* v = vals + 6 * hf;
+                v[0] = Xdx;
+                v[1] = Xdy;
+                v[2] = Xdx * dxv[u];
+                v[3] = Xdx * dyv[u];
+                v[4] = Xdy * dyv[u];
+                v[5] = X;
+              }
+              float h6[6];
+#pragma unroll
+              for (int k = 0; k < 6; ++k) {
+                const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(vals[k]), __float_as_uint(vals[k + 6]),
+                                                                false, false);
+                h6[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+              }
+#pragma unroll
+              for (int k = 0; k < 3; ++k) {
+                const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(h6[k]), __float_as_uint(h6[k + 3]),
+                                                                false, false);
+                red[up][k] = row_sum16(__uint_as_float(r[0]) + __uint_as_float(r[1]));
+              }
+            }
+            if ((lane & 15) == 15) {
+              const int base = 3 * ((lane >> 4) & 1);
+#pragma unroll
+              for (int up = 0; up < GR / 2; ++up)
+                if (anyp[up])
+#pragma unroll
+                  for (int k = 0; k < 3; ++k)
+                    atomicAdd(&s_red[b3][base + k][gi * GR + 2 * up + (lane >> 5)], red[up][k]);
+            }
+          }
+          // colour sums of the wave's pixels on the matrix cores
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+          for (int mb = 0; mb < 2; ++mb) {
+            f32x4 cs = f32x4{};
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+              const int kp = 32 * ks + 8 * (lane >> 4);
+              const bf16x8 wh = *reinterpret_cast<const bf16x8*>(&s_w[b2][wave][0][16 * mb + (lane & 15)][kp]);
+              const bf16x8 wl = *reinterpret_cast<const bf16x8*>(&s_w[b2][wave][1][16 * mb + (lane & 15)][kp]);
+              const bf16x8 gh = s_grb[wave][ks][0][lane];
+              const bf16x8 gl = s_grb[wave][ks][1][lane];
+              cs = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, gh, cs, 0, 0, 0);
+              cs = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, gl, cs, 0, 0, 0);
+              cs = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl, gh, cs, 0, 0, 0);
+            }
+            if ((lane & 15) < 3) {
+#pragma unroll
+              for (int v = 0; v < 4; ++v)
+                atomicAdd(&s_red[b3][6 + (lane & 15)][16 * mb + 4 * (lane >> 4) + v], cs[v]);
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+  } else {
+    for (int it = 0; it <= nbatch; ++it) {
+      // ================= contractors: GEMM2 and rows of batch it-1, staging of batch it+1 =================
+      if (it >= 1) {
+        const int k = it - 1;
+        const int b2 = k & 1, b3 = k % 3;
+        const int pos0 = bpos0(k), nb = bnb(k);
+        f32x16 d[2] = {f32x16{}, f32x16{}};
+#pragma unroll
+        for (int u = 0; u < CB; ++u) {
+          const int chunk = unit_chunk(u);
+          if (s_live[b2][chunk]) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+              const int kp = 16 * s + 8 * (lane >> 5);
+              const bf16x8 wh = *reinterpret_cast<const bf16x8*>(&s_w[b2][chunk][0][lane & 31][kp]);
+              const bf16x8 wl = *reinterpret_cast<const bf16x8*>(&s_w[b2][chunk][1][lane & 31][kp]);
+              d[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh, g2(u, s, 0), d[0], 0, 0, 0);
+              d[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh, g2(u, s, 1), d[1], 0, 0, 0);
+              d[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wl, g2(u, s, 0), d[0], 0, 0, 0);
+            }
+          }
+          if (u % NW == NW - 1) {   // the channel block is complete
+            const int c = 32 * unit_cb(u) + (lane & 31);
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+              const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+              if (i < nb && c < a.D) a.rows[(row0 + pos0 + i) * a.RS + c] = d[0][v] + d[1][v];
+            }
+            d[0] = d[1] = f32x16{};
+          }
+        }
+        // rest of the rows: the six walk sums turned into projected-space
+        // gradients with the Gaussian's conic and opacity, the colour sums
+        const int cstart = a.D & ~3;
+        const int nq = (a.RS - cstart) >> 2;
+        for (int t = q; t < nb * nq; t += NT) {
+          const int i = t / nq;
+          const int c0 = cstart + 4 * (t - i * nq);
+          const float4 co = s_co[b3][i];
+          float v[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            float x = 0.f;
+            switch (c0 + j - a.D) {
+              case 0: x = co.w * (co.x * s_red[b3][0][i] + co.y * s_red[b3][1][i]); break;
+              case 1: x = co.w * (co.y * s_red[b3][0][i] + co.z * s_red[b3][1][i]); break;
+              case 2: x = -0.5f * co.w * s_red[b3][2][i]; break;
+              case 3: x = -co.w * s_red[b3][3][i]; break;
+              case 4: x = -0.5f * co.w * s_red[b3][4][i]; break;
+              case 5: x = s_red[b3][5][i]; break;
+              case 6: x = s_red[b3][6][i]; break;
+              case 7: x = s_red[b3][7][i]; break;
+              case 8: x = s_red[b3][8][i]; break;
+              default: break;
+            }
+            v[j] = x;
+          }
+          float* dst = &a.rows[(row0 + pos0 + i) * a.RS + c0];
+          if (c0 >= a.D) {
+            *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+          } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              if (c0 + j >= a.D) dst[j] = v[j];
+          }
+        }
+        if (q < nb) a.rowidx[ep_w] = (uint32_t)(row0 + pos0 + q + 1);
+      }
+      // the sums of batch it-2 were read in the previous step: clear them for batch it+1
+      if (it >= 2)
+        for (int e = q; e < 12 * kNB; e += NT) (&s_red[(it - 2) % 3][0][0])[e] = 0.f;
+      ep_w = ep_s;
+      if (it + 1 < nbatch) {
+        stage(it + 1);
+        load_data();
+        load_ids(it + 3);
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // ---- per-Gaussian sum of the rows of the tiles it was walked in ----
 struct ReduceArgs {
   int64_t n;
@@ -678,6 +1157,21 @@ __global__ __launch_bounds__(256) void reduce_rows_kernel(ReduceArgs a) {
 
 template <int DP, typename FT>
 hipError_t launch_bwd_nt(int nt, const BwdArgs& a, int tiles, hipStream_t s) {
+  // wave-specialized kernel wherever contractor waves own whole channel blocks
+  if constexpr (DP <= 128) {
+    if (DP / 32 >= nt / 64) {
+      switch (nt) {
+        case 64: hipLaunchKernelGGL((composite_bwd_ws_kernel<DP, FT, 64>), dim3(tiles), dim3(128), 0, s, a); break;
+        case 128:
+          if constexpr (DP >= 64) hipLaunchKernelGGL((composite_bwd_ws_kernel<DP, FT, 128>), dim3(tiles), dim3(256), 0, s, a);
+          break;
+        default:
+          if constexpr (DP >= 128) hipLaunchKernelGGL((composite_bwd_ws_kernel<DP, FT, 256>), dim3(tiles), dim3(512), 0, s, a);
+          break;
+      }
+      return hipGetLastError();
+    }
+  }
   switch (nt) {
     case 64: hipLaunchKernelGGL((composite_bwd_mfma_kernel<DP, FT, 64>), dim3(tiles), dim3(64), 0, s, a); break;
     case 128: hipLaunchKernelGGL((composite_bwd_mfma_kernel<DP, FT, 128>), dim3(tiles), dim3(128), 0, s, a); break;
