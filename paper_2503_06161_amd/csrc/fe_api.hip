@@ -25,14 +25,12 @@ bool compute_layout(const fe_config* cfg, const fe_camera* cam, int64_t n, Layou
   L->nscan_blocks = ceil_div(n, kScanChunk);
   int bits = 0;
   while ((1ll << bits) < (int64_t)L->tiles) ++bits;
-  // one 11-bit pass covers up to 2048 tiles; beyond that, 8-bit passes
-  if (bits <= 11) {
-    L->tile_passes = bits > 0 ? 1 : 0;
-    L->tile_bits = bits <= 8 ? 8 : 11;
-  } else {
-    L->tile_passes = (bits + 7) / 8;
-    L->tile_bits = 8;
-  }
+  // 8-bit passes on the tile id: with 256 bins a chunk of 2048 keys scatters
+  // into runs long enough to write whole cache lines, and its histogram row
+  // stays small (an 11-bit digit was measured slower: its 2048-bin rows are
+  // as large as the chunks and every write is an isolated 4 bytes)
+  L->tile_passes = (bits + 7) / 8;
+  L->tile_bits = 8;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;
@@ -62,7 +60,6 @@ bool compute_layout(const fe_config* cfg, const fe_camera* cam, int64_t n, Layou
   L->hist_k = take(4 * (size_t)(1 << L->tile_bits) * L->nchunks_k);
   L->tile_maxlast = take(4 * (size_t)L->tiles);
   L->gofe = take(4 * (size_t)L->cap);
-  L->inv = take(4 * (size_t)L->cap);
   L->epos = take(4 * (size_t)L->cap);
   L->eoff = take(4 * n);
   L->total = o;
@@ -94,7 +91,6 @@ StateView make_view(const Layout& L, void* base) {
   v.report = reinterpret_cast<unsigned long long*>(b + L.report);
   v.tile_maxlast = reinterpret_cast<uint32_t*>(b + L.tile_maxlast);
   v.gofe = reinterpret_cast<uint32_t*>(b + L.gofe);
-  v.inv = reinterpret_cast<uint32_t*>(b + L.inv);
   v.epos = reinterpret_cast<uint32_t*>(b + L.epos);
   v.eoff = reinterpret_cast<uint32_t*>(b + L.eoff);
   v.n = L.n;

@@ -54,7 +54,6 @@ struct StateView {
   uint2* ranges;
   uint32_t* tile_maxlast;   // [tiles] largest n_contrib per tile (compositing walk length)
   uint32_t* gofe;           // [cap] Gaussian of each emitted pair (emit order)
-  uint32_t* inv;            // [cap] sorted position of each emitted pair
   uint32_t* epos;           // [cap] emit position of each sorted pair
   uint32_t* eoff;           // [n] first emit position of each Gaussian
   unsigned long long* report;
@@ -70,7 +69,7 @@ struct StateView {
 struct Layout {
   size_t total;
   size_t xy, conic_o, rgb, box, dkey_a, dkey_b, didx_a, didx_b, count, offsets, scan_sums, hist_n;
-  size_t tile_a, gauss_a, tile_b, gauss_b, hist_k, totals, ranges, report, tile_maxlast, gofe, inv, epos, eoff;
+  size_t tile_a, gauss_a, tile_b, gauss_b, hist_k, totals, ranges, report, tile_maxlast, gofe, epos, eoff;
   int64_t n, cap;
   int32_t tiles_x, tiles_y, tiles, nchunks_n, nchunks_k, nscan_blocks, tile_passes, tile_bits;
 };

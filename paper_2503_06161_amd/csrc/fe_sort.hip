@@ -2,7 +2,7 @@
 //
 // Order of work (all integer, HBM-bound):
 //   1. stable LSD radix sort of the Gaussians by the bits of their float32
-//      view-space depth (4 passes of 8 bits; culled Gaussians carry the key
+//      view-space depth (3 passes of 11 bits; culled Gaussians carry the key
 //      0xFFFFFFFF and emit nothing);
 //   2. exclusive scan of the per-Gaussian tile counts taken in depth order;
 //   3. emit one (tile id, Gaussian index) pair per tile of each Gaussian's
@@ -135,7 +135,6 @@ struct RadixArgs {
   uint32_t* keys_out;
   uint32_t* vals_out;
   const uint32_t* gather;            // optional: write gather[val] instead of val ...
-  uint32_t* inv;                     // ... and inv[val] = output position
   uint32_t* epos;                    // ... and epos[output position] = val
   const unsigned long long* n_dev;   // item count on the device (may be NULL)
   int64_t n_const;                   // used when n_dev is NULL
@@ -260,7 +259,6 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(RadixArgs a
         if (a.keys_out) a.keys_out[pos] = key[j];
         if (a.gather) {
           a.vals_out[pos] = a.gather[val[j]];
-          a.inv[val[j]] = pos;
           a.epos[pos] = val[j];
         } else {
           a.vals_out[pos] = val[j];
@@ -363,13 +361,13 @@ hipError_t launch_sort_and_bin(const fe_config* cfg, const StateView& v, hipStre
   // 1. depth sort of all n Gaussians: three 11-bit passes (A -> B -> A -> B);
   //    the first pass takes the implicit index as value
   {
-    RadixArgs a0{v.dkey_a, nullptr, v.dkey_b, v.didx_b, nullptr, nullptr, nullptr, nullptr, v.n, v.n, v.hist_n,
+    RadixArgs a0{v.dkey_a, nullptr, v.dkey_b, v.didx_b, nullptr, nullptr, nullptr, v.n, v.n, v.hist_n,
                  v.totals, v.nchunks_n, 0};
     if ((e = radix_pass<11>(a0, s)) != hipSuccess) return e;
-    RadixArgs a1{v.dkey_b, v.didx_b, v.dkey_a, v.didx_a, nullptr, nullptr, nullptr, nullptr, v.n, v.n, v.hist_n,
+    RadixArgs a1{v.dkey_b, v.didx_b, v.dkey_a, v.didx_a, nullptr, nullptr, nullptr, v.n, v.n, v.hist_n,
                  v.totals + kRadixBinsMax, v.nchunks_n, 11};
     if ((e = radix_pass<11>(a1, s)) != hipSuccess) return e;
-    RadixArgs a2{v.dkey_a, v.didx_a, v.dkey_b, v.didx_b, nullptr, nullptr, nullptr, nullptr, v.n, v.n, v.hist_n,
+    RadixArgs a2{v.dkey_a, v.didx_a, v.dkey_b, v.didx_b, nullptr, nullptr, nullptr, v.n, v.n, v.hist_n,
                  v.totals + 2 * kRadixBinsMax, v.nchunks_n, 22};
     if ((e = radix_pass<11>(a2, s)) != hipSuccess) return e;
   }
@@ -399,15 +397,15 @@ hipError_t launch_sort_and_bin(const fe_config* cfg, const StateView& v, hipStre
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // 4. stable passes on the tile digits.  The value carried is the emit
   //    position; the last pass writes the Gaussian index it maps to and the
-  //    inverse map emit position -> sorted position.
+  //    map sorted position -> emit position.
   uint32_t* tk_in = ea.tile_out;
   uint32_t* tk_out = odd ? v.tile_a : v.tile_b;
   const uint32_t* tv_in = nullptr;
   for (int p = 0; p < v.tile_passes; ++p) {
     const bool final_pass = p == v.tile_passes - 1;
     uint32_t* tv_out = final_pass ? v.gauss_a : v.gauss_b;
-    RadixArgs a{tk_in, tv_in, tk_out, tv_out, final_pass ? v.gofe : nullptr, final_pass ? v.inv : nullptr,
-                final_pass ? v.epos : nullptr, total, 0, v.cap, v.hist_k, v.totals + (3 + p) * kRadixBinsMax,
+    RadixArgs a{tk_in, tv_in, tk_out, tv_out, final_pass ? v.gofe : nullptr, final_pass ? v.epos : nullptr,
+                total, 0, v.cap, v.hist_k, v.totals + (3 + p) * kRadixBinsMax,
                 v.nchunks_k, p * v.tile_bits};
     if ((e = (v.tile_bits == 11 ? radix_pass<11>(a, s) : radix_pass<8>(a, s))) != hipSuccess) return e;
     uint32_t* t = tk_in; tk_in = tk_out; tk_out = t;
