@@ -202,10 +202,20 @@ __global__ __launch_bounds__(kScanThreads) void radix_scan_kernel(RadixArgs a) {
   }
 }
 
+// Scatter of one chunk: rank equal digits inside each wavefront with ballot
+// masks (stable by position), turn the ranks into the chunk's local digit
+// order, stage key / value / destination in LDS in that order, and write them
+// out so that consecutive threads store consecutive destinations of the same
+// digit run (runs of equal digits are contiguous in the output).
 template <int BITS>
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(RadixArgs a) {
   constexpr int BINS = 1 << BITS;
   __shared__ uint32_t cnt[4][BINS];
+  __shared__ uint32_t lbase[BINS];          // exclusive prefix of the chunk's digit counts
+  __shared__ uint32_t s_key[kSortChunk];
+  __shared__ uint32_t s_val[kSortChunk];
+  __shared__ uint32_t s_pos[kSortChunk];
+  __shared__ uint32_t s_warp[4];
   const int64_t n = radix_count(a);
   const int64_t base = (int64_t)blockIdx.x * kSortChunk;
   if (base >= n) return;   // uniform per block
@@ -221,6 +231,11 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(RadixArgs a
     const bool valid = i < n;
     key[j] = valid ? a.keys_in[i] : 0u;
     val[j] = valid ? (a.vals_in ? a.vals_in[i] : (uint32_t)i) : 0u;
+  }
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const int64_t i = wbase + (int64_t)j * 64 + lane;
+    const bool valid = i < n;
     const uint32_t d = (key[j] >> a.shift) & (BINS - 1);
     dig[j] = d;
     unsigned long long m = __ballot(valid);
@@ -240,29 +255,63 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(RadixArgs a
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   }
   __syncthreads();
-  // per-digit offsets of the four wavefronts' sub-chunks
-  for (int d = threadIdx.x; d < BINS; d += kSortThreads) {
-    uint32_t o = a.hist[(size_t)d * a.nchunks + blockIdx.x];
-    for (int w = 0; w < 4; ++w) {
-      const uint32_t c = cnt[w][d];
-      cnt[w][d] = o;
-      o += c;
+  // per digit: global offsets of the four wavefronts' sub-chunks, and the
+  // chunk's local digit order (exclusive scan of the digit counts)
+  constexpr int DPT = (BINS + kSortThreads - 1) / kSortThreads;   // digits per thread
+  uint32_t tot[DPT];
+  uint32_t mysum = 0;
+#pragma unroll
+  for (int k = 0; k < DPT; ++k) {
+    const int d = threadIdx.x * DPT + k;
+    uint32_t t = 0;
+    if (d < BINS) {
+      uint32_t o = a.hist[(size_t)d * a.nchunks + blockIdx.x];
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const uint32_t c = cnt[w][d];
+        cnt[w][d] = o;         // global start of wave w's run of digit d
+        o += c;
+        t += c;
+      }
     }
+    tot[k] = t;
+    mysum += t;
+  }
+  uint32_t total;
+  uint32_t lo = block_exclusive_scan(mysum, s_warp, total);
+#pragma unroll
+  for (int k = 0; k < DPT; ++k) {
+    const int d = threadIdx.x * DPT + k;
+    if (d < BINS) lbase[d] = lo;
+    lo += tot[k];
   }
   __syncthreads();
+  // local position of an item: digit base + items of the same digit in
+  // earlier wavefronts + its rank; global position: wave run start + rank
 #pragma unroll
   for (int j = 0; j < kSortItems; ++j) {
     const int64_t i = wbase + (int64_t)j * 64 + lane;
     if (i < n) {
-      const uint32_t pos = cnt[wave][dig[j]] + rank[j];
-      if (pos < (uint64_t)n) {   // always true for a consistent histogram; guards the write
-        if (a.keys_out) a.keys_out[pos] = key[j];
-        if (a.gather) {
-          a.vals_out[pos] = a.gather[val[j]];
-          a.epos[pos] = val[j];
-        } else {
-          a.vals_out[pos] = val[j];
-        }
+      const uint32_t d = dig[j];
+      const uint32_t pos = cnt[wave][d] + rank[j];
+      const uint32_t lpos = lbase[d] + (cnt[wave][d] - cnt[0][d]) + rank[j];
+      s_key[lpos] = key[j];
+      s_val[lpos] = val[j];
+      s_pos[lpos] = pos;
+    }
+  }
+  __syncthreads();
+  const int cnt_here = (int)min((int64_t)kSortChunk, n - base);
+  for (int t = threadIdx.x; t < cnt_here; t += kSortThreads) {
+    const uint32_t pos = s_pos[t];
+    if (pos < (uint64_t)n) {   // always true for a consistent histogram; guards the write
+      const uint32_t v = s_val[t];
+      if (a.keys_out) a.keys_out[pos] = s_key[t];
+      if (a.gather) {
+        a.vals_out[pos] = a.gather[v];
+        a.epos[pos] = v;
+      } else {
+        a.vals_out[pos] = v;
       }
     }
   }
