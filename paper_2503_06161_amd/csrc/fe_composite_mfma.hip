@@ -344,8 +344,288 @@ void composite_fwd_mfma_kernel(MfmaArgs a) {
   }
 }
 
+// Wave-specialized form (BF16-stored features, D <= 128, at least as many
+// 32-channel blocks as 64-pixel chunks).  The block has 2 NT threads: NT
+// "walker" threads (one pixel each) compute the weights of batch k front to
+// back and leave them in LDS as float32 rows (pixel-major), while NT
+// "accumulator" threads own whole channel blocks over all pixels of the tile,
+// run the D-channel contraction of batch k-1 on the matrix cores (splitting
+// each weight into three exact bf16 parts as they read it) and stage batch
+// k+1.  The roles need about half the registers each, so two waves share a
+// SIMD.  One barrier per batch (the early-termination count); weights and
+// records are double-buffered, feature rows triple-buffered.
+template <int DP, int NT>
+__global__ __launch_bounds__(2 * NT) void composite_fwd_ws_kernel(MfmaArgs a) {
+  constexpr int CB = DP / 32;
+  constexpr int NW = NT / 64;
+  static_assert(CB >= NW, "each accumulator wave owns whole channel blocks");
+  constexpr int CPW = CB / NW;                 // channel blocks per accumulator wave
+  constexpr int NPB = NT / 32;                 // 32-pixel blocks of the tile
+  constexpr int FROW = DP + 32;
+  constexpr int WROW = kNB + 4;                // float32 weight row of a pixel (bank spread)
+  __shared__ float2 s_xy[2][kNB];
+  __shared__ float4 s_co[2][kNB];
+  __shared__ float4 s_rgb[2][kNB];
+  __shared__ int4 s_box[2][kNB];
+  __shared__ __attribute__((aligned(16))) __bf16 s_f[3][kNB][FROW];
+  __shared__ __attribute__((aligned(16))) float s_w[2][NT][WROW];
+  __shared__ int s_any[2][NW][2];              // the chunk has a nonzero weight in the k step
+  __shared__ int s_maxlast;
+
+  const int tile = blockIdx.x;
+  const bool walker = (int)threadIdx.x < NT;
+  const int q = walker ? (int)threadIdx.x : (int)threadIdx.x - NT;
+  const int lane = q & 63;
+  const int wave = q >> 6;
+  const int tile_h = NT / a.tile_w;
+  const int px = (tile % a.tiles_x) * a.tile_w + q % a.tile_w;
+  const int py = (tile / a.tiles_x) * tile_h + q / a.tile_w;
+  const bool inside = walker & (px < a.W) & (py < a.H);
+  const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+  const uint2 rg = a.ranges[tile];
+  const int nbatch = (int)((rg.y - rg.x + kNB - 1) / kNB);
+  if (threadIdx.x == 0) s_maxlast = 0;
+
+  // ---- accumulators: software-pipelined staging ----
+  constexpr int FQ = DP / 4;
+  constexpr int FI = (kNB * FQ + NT - 1) / NT;
+  uint32_t id_n[FI + 1];
+  FeatGroup<uint16_t> fv[FI];
+  float2 p_xy = make_float2(0.f, 0.f);
+  float4 p_co = make_float4(0.f, 0.f, 0.f, 0.f), p_rgb = p_co;
+  short4 p_box = make_short4(1, 1, 0, 0);
+  auto load_ids = [&](int k) {
+    const uint32_t b0 = rg.x + (uint32_t)k * kNB;
+#pragma unroll
+    for (int j = 0; j < FI; ++j) {
+      const int i = (q + j * NT) / FQ;
+      id_n[j] = (j * NT + q < kNB * FQ && k < nbatch && b0 + i < rg.y) ? a.gauss[b0 + i] : 0xFFFFFFFFu;
+    }
+    id_n[FI] = (q < kNB && k < nbatch && b0 + q < rg.y) ? a.gauss[b0 + q] : 0xFFFFFFFFu;
+  };
+  auto load_data = [&]() {
+#pragma unroll
+    for (int j = 0; j < FI; ++j) {
+      const int c = ((q + j * NT) % FQ) * 4;
+      fv[j].clear();
+      if (id_n[j] != 0xFFFFFFFFu && c < a.D) fv[j].load(a.feat, (int64_t)id_n[j] * a.D, c, a.D, a.vec);
+    }
+    if (id_n[FI] != 0xFFFFFFFFu) {
+      const uint32_t g = id_n[FI];
+      p_xy = a.xy[g];
+      p_co = a.conic_o[g];
+      p_rgb = a.rgb[g];
+      p_box = a.box[g];
+    }
+  };
+  auto stage = [&](int k) {
+    const int b2 = k & 1, b3 = k % 3;
+    const int nb = (int)min((uint32_t)kNB, rg.y - (rg.x + (uint32_t)k * kNB));
+    if (q < kNB) {
+      s_xy[b2][q] = p_xy;
+      s_co[b2][q] = p_co;
+      s_rgb[b2][q] = p_rgb;
+      s_box[b2][q] = make_int4(p_box.x, p_box.y, p_box.z, p_box.w);
+    }
+#pragma unroll
+    for (int j = 0; j < FI; ++j) {
+      const int e = q + j * NT;
+      if (e < kNB * FQ) {
+        const int i = e / FQ;
+        const int c = (e % FQ) * 4;
+        // the stored bf16 bits go to LDS unchanged (channel c in the low half)
+        *reinterpret_cast<uint2*>(&s_f[b3][i][c]) = i < nb ? fv[j].v : make_uint2(0u, 0u);
+      }
+    }
+  };
+
+  if (walker) {
+    // ================= walkers =================
+    float T = 1.0f;
+    float C0 = 0.f, C1 = 0.f, C2 = 0.f;
+    int last = 0;
+    bool done = !inside;
+    for (int kk = 0;; ++kk) {
+      const int k = __builtin_amdgcn_readfirstlane(kk);   // scalar: keeps the barrier loop uniform
+      const int alive = __syncthreads_count(!done);
+      const bool more = k < nbatch && alive > 0;
+      if (!more) break;
+      const int b2 = k & 1;
+      const int nb = (int)min((uint32_t)kNB, rg.y - (rg.x + (uint32_t)k * kNB));
+      const int pos0 = k * kNB;
+      const bool wave_live = __ballot(!done) != 0ull;
+      constexpr int GR = 8;
+#pragma unroll
+      for (int s = 0; s < kNB / 16; ++s) {
+        float wv[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) wv[i] = 0.f;
+        if (wave_live) {
+#pragma unroll
+          for (int gi = 0; gi < 16 / GR; ++gi) {
+            float al[GR];
+            bool act[GR];
+#pragma unroll
+            for (int u = 0; u < GR; ++u) {
+              const int i = 16 * s + gi * GR + u;
+              const float2 m = s_xy[b2][i];
+              const float4 co = s_co[b2][i];
+              const int4 b = s_box[b2][i];
+              const float dx = fpx - m.x, dy = fpy - m.y;
+              const float qq = __builtin_fmaf(co.x * dx, dx, __builtin_fmaf(co.z * dy, dy, 2.0f * co.y * dx * dy));
+              const bool inb = (px >= b.x) & (px <= b.z) & (py >= b.y) & (py <= b.w);
+              const float alpha = fminf(kAlphaMax, co.w * __expf(-0.5f * qq));
+              act[u] = (i < nb) & inb & (qq <= kQMax) & (alpha >= kAlphaMin);
+              al[u] = alpha;
+            }
+#pragma unroll
+            for (int u = 0; u < GR; ++u) {
+              const int i = 16 * s + gi * GR + u;
+              const float Tn = T * (1.0f - al[u]);
+              const bool live = act[u] & !done;
+              const bool stop = live & (Tn < kTStop);
+              const bool take = live & !stop;
+              done = done | stop;
+              const float w = take ? al[u] * T : 0.f;
+              const float4 c = s_rgb[b2][i];
+              C0 = __builtin_fmaf(w, c.x, C0);
+              C1 = __builtin_fmaf(w, c.y, C1);
+              C2 = __builtin_fmaf(w, c.z, C2);
+              wv[gi * GR + u] = w;
+              T = take ? Tn : T;
+              last = take ? pos0 + i + 1 : last;
+            }
+          }
+        }
+        bool any = false;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) any |= wv[i] != 0.f;
+        const bool wany = __ballot(any) != 0ull;
+        if (lane == 0) s_any[b2][wave][s] = wany ? 1 : 0;
+        if (wany) {
+#pragma unroll
+          for (int i = 0; i < 16; i += 4)
+            *reinterpret_cast<float4*>(&s_w[b2][q][16 * s + i]) = make_float4(wv[i], wv[i + 1], wv[i + 2], wv[i + 3]);
+        }
+      }
+    }
+    const int64_t HW = (int64_t)a.W * a.H;
+    if (inside) {
+      const int64_t p = (int64_t)py * a.W + px;
+      a.out_rgb[p] = __builtin_fmaf(T, a.bg[0], C0);
+      a.out_rgb[HW + p] = __builtin_fmaf(T, a.bg[1], C1);
+      a.out_rgb[2 * HW + p] = __builtin_fmaf(T, a.bg[2], C2);
+      a.out_T[p] = T;
+      a.out_n[p] = last;
+    }
+    if (last > 0) atomicMax(&s_maxlast, last);
+  } else {
+    // ================= accumulators =================
+    f32x16 acc[CPW][NPB];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c)
+#pragma unroll
+      for (int pb = 0; pb < NPB; ++pb) acc[c][pb] = f32x16{};
+    load_ids(0);
+    load_data();
+    load_ids(1);
+    stage(0);
+    load_data();
+    load_ids(2);
+    for (int kk = 0;; ++kk) {
+      // the batch counter is read back as a scalar so that the compiler keeps
+      // the loop (and its barrier) uniform
+      const int k = __builtin_amdgcn_readfirstlane(kk);
+      const int alive = __syncthreads_count(0);
+      const bool more = k < nbatch && alive > 0;
+      if (k >= 1) {
+        // contraction of batch k-1: Z (channels x pixels) += F^T W
+        const int b2 = (k - 1) & 1, b3 = (k - 1) % 3;
+#pragma unroll
+        for (int s = 0; s < kNB / 16; ++s) {
+          bf16x8 fa[CPW];
+#pragma unroll
+          for (int c = 0; c < CPW; ++c) fa[c] = load_a_tr<FROW>(&s_f[b3][0][0], 16 * s, 32 * (wave + NW * c), lane);
+#pragma unroll
+          for (int pb = 0; pb < NPB; ++pb) {
+            // the flag is wave-uniform: a scalar branch keeps the barrier loop uniform
+            if (!__builtin_amdgcn_readfirstlane(s_any[b2][pb >> 1][s])) continue;
+            const float* wr = &s_w[b2][32 * pb + (lane & 31)][16 * s + 8 * (lane >> 5)];
+            const float4 w0 = *reinterpret_cast<const float4*>(wr);
+            const float4 w1 = *reinterpret_cast<const float4*>(wr + 4);
+            const float wf[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+            bf16x8 bw[3];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              __bf16 h, m, l;
+              split3(wf[j], h, m, l);
+              bw[0][j] = h;
+              bw[1][j] = m;
+              bw[2][j] = l;
+            }
+#pragma unroll
+            for (int c = 0; c < CPW; ++c) {
+              f32x16 z = acc[c][pb];
+              z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[c], bw[0], z, 0, 0, 0);
+              z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[c], bw[1], z, 0, 0, 0);
+              z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[c], bw[2], z, 0, 0, 0);
+              acc[c][pb] = z;
+            }
+          }
+        }
+      }
+      if (!more) break;
+      if (k + 1 < nbatch) {
+        stage(k + 1);
+        load_data();
+        load_ids(k + 3);
+      }
+    }
+    // feature image: accumulator row = channel, column = pixel
+    const int64_t HW = (int64_t)a.W * a.H;
+#pragma unroll
+    for (int pb = 0; pb < NPB; ++pb) {
+      const int lpo = 32 * pb + (lane & 31);
+      const int ox = (tile % a.tiles_x) * a.tile_w + lpo % a.tile_w;
+      const int oy = (tile / a.tiles_x) * tile_h + lpo / a.tile_w;
+      if (ox < a.W && oy < a.H) {
+        const int64_t p = (int64_t)oy * a.W + ox;
+#pragma unroll
+        for (int c = 0; c < CPW; ++c)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const int ch = 32 * (wave + NW * c) + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+            if (ch < a.D) a.out_feat[ch * HW + p] = acc[c][pb][v];
+          }
+      }
+    }
+  }
+  // per-tile walk length (used by the backward to size its partial rows)
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a.tile_maxlast[tile] = (uint32_t)s_maxlast;
+    if (s_maxlast > 0) atomicAdd(&a.report[kRepRows], (unsigned long long)s_maxlast);
+  }
+}
+
 template <int DP, typename FT>
 hipError_t launch_nt(int nt, const MfmaArgs& a, int tiles, hipStream_t s) {
+  // wave-specialized kernel for BF16 features wherever accumulator waves own
+  // whole channel blocks
+  if constexpr (std::is_same<FT, uint16_t>::value && DP <= 128) {
+    if (DP / 32 >= nt / 64) {
+      switch (nt) {
+        case 64: hipLaunchKernelGGL((composite_fwd_ws_kernel<DP, 64>), dim3(tiles), dim3(128), 0, s, a); break;
+        case 128:
+          if constexpr (DP >= 64) hipLaunchKernelGGL((composite_fwd_ws_kernel<DP, 128>), dim3(tiles), dim3(256), 0, s, a);
+          break;
+        default:
+          if constexpr (DP >= 128) hipLaunchKernelGGL((composite_fwd_ws_kernel<DP, 256>), dim3(tiles), dim3(512), 0, s, a);
+          break;
+      }
+      return hipGetLastError();
+    }
+  }
   switch (nt) {
     case 64: hipLaunchKernelGGL((composite_fwd_mfma_kernel<DP, FT, 64>), dim3(tiles), dim3(64), 0, s, a); break;
     case 128: hipLaunchKernelGGL((composite_fwd_mfma_kernel<DP, FT, 128>), dim3(tiles), dim3(128), 0, s, a); break;
