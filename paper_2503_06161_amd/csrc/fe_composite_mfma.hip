@@ -81,6 +81,22 @@ __device__ __forceinline__ void split3(float x, __bf16& hi, __bf16& mid, __bf16&
   lo = (__bf16)r2;
 }
 
+// Two float32 values -> three packed bf16 pairs (hi, mid, lo), each pair
+// holding (value 0, value 1) in its (low, high) half.  Truncation splitting:
+// hi keeps the top 8 significant bits, mid the next 8 significant bits of the
+// (exact) remainder and lo the rest, so hi + mid + lo == x exactly for every
+// normal x.  One byte permute packs the high halves of two values.
+__device__ __forceinline__ void split3_pair(float x0, float x1, uint32_t& hi, uint32_t& mid, uint32_t& lo) {
+  constexpr uint32_t kTop = 0xFFFF0000u, kSel = 0x07060302u;   // high halves of (x1, x0)
+  const uint32_t u0 = __float_as_uint(x0), u1 = __float_as_uint(x1);
+  hi = __builtin_amdgcn_perm(u1, u0, kSel);
+  const float r0 = x0 - __uint_as_float(u0 & kTop), r1 = x1 - __uint_as_float(u1 & kTop);
+  const uint32_t v0 = __float_as_uint(r0), v1 = __float_as_uint(r1);
+  mid = __builtin_amdgcn_perm(v1, v0, kSel);
+  const float t0 = r0 - __uint_as_float(v0 & kTop), t1 = r1 - __uint_as_float(v1 & kTop);
+  lo = __builtin_amdgcn_perm(__float_as_uint(t1), __float_as_uint(t0), kSel);
+}
+
 // bf16 bits of four channels, packed two per register
 __device__ __forceinline__ uint2 pack_bf16x4(__bf16 a0, __bf16 a1, __bf16 a2, __bf16 a3) {
   auto bits = [](__bf16 h) { return (uint32_t)__builtin_bit_cast(uint16_t, h); };
@@ -344,23 +360,20 @@ void composite_fwd_mfma_kernel(MfmaArgs a) {
   }
 }
 
-// Wave-specialized form (BF16-stored features, D <= 128, at least as many
-// 32-channel blocks as 64-pixel chunks).  The block has 2 NT threads: NT
-// "walker" threads (one pixel each) compute the weights of batch k front to
-// back and leave them in LDS as float32 rows (pixel-major), while NT
-// "accumulator" threads own whole channel blocks over all pixels of the tile,
-// run the D-channel contraction of batch k-1 on the matrix cores (splitting
-// each weight into three exact bf16 parts as they read it) and stage batch
-// k+1.  The roles need about half the registers each, so two waves share a
-// SIMD.  One barrier per batch (the early-termination count); weights and
-// records are double-buffered, feature rows triple-buffered.
+// Wave-specialized form (BF16-stored features, D <= 128).  The block has
+// 2 NT threads: NT "walker" threads (one pixel each) compute the weights of
+// batch k front to back and leave them in LDS as float32 rows (pixel-major),
+// while NT "accumulator" threads run the D-channel contraction of batch k-1
+// on the matrix cores and stage batch k+1.  Accumulator wave w owns the 64
+// pixels of walker wave w and all channel blocks, so every weight is split
+// into its three exact bf16 parts once, by the one wave that consumes it.
+// The roles need about half the registers each, so two waves share a SIMD.
+// One barrier per batch (the early-termination count); weights and records
+// are double-buffered, feature rows triple-buffered.
 template <int DP, int NT>
 __global__ __launch_bounds__(2 * NT) void composite_fwd_ws_kernel(MfmaArgs a) {
   constexpr int CB = DP / 32;
   constexpr int NW = NT / 64;
-  static_assert(CB >= NW, "each accumulator wave owns whole channel blocks");
-  constexpr int CPW = CB / NW;                 // channel blocks per accumulator wave
-  constexpr int NPB = NT / 32;                 // 32-pixel blocks of the tile
   constexpr int FROW = DP + 32;
   constexpr int WROW = kNB + 4;                // float32 weight row of a pixel (bank spread)
   __shared__ float2 s_xy[2][kNB];
@@ -521,11 +534,10 @@ __global__ __launch_bounds__(2 * NT) void composite_fwd_ws_kernel(MfmaArgs a) {
     if (last > 0) atomicMax(&s_maxlast, last);
   } else {
     // ================= accumulators =================
-    f32x16 acc[CPW][NPB];
+    // acc[c][pb]: channels 32 c.. x pixels 64 wave + 32 pb..
+    f32x16 acc[CB][2];
 #pragma unroll
-    for (int c = 0; c < CPW; ++c)
-#pragma unroll
-      for (int pb = 0; pb < NPB; ++pb) acc[c][pb] = f32x16{};
+    for (int c = 0; c < CB; ++c) acc[c][0] = acc[c][1] = f32x16{};
     load_ids(0);
     load_data();
     load_ids(1);
@@ -543,32 +555,32 @@ __global__ __launch_bounds__(2 * NT) void composite_fwd_ws_kernel(MfmaArgs a) {
         const int b2 = (k - 1) & 1, b3 = (k - 1) % 3;
 #pragma unroll
         for (int s = 0; s < kNB / 16; ++s) {
-          bf16x8 fa[CPW];
+          // the flag is wave-uniform: a scalar branch keeps the barrier loop uniform
+          if (!__builtin_amdgcn_readfirstlane(s_any[b2][wave][s])) continue;
+          bf16x8 fa[CB];
 #pragma unroll
-          for (int c = 0; c < CPW; ++c) fa[c] = load_a_tr<FROW>(&s_f[b3][0][0], 16 * s, 32 * (wave + NW * c), lane);
+          for (int c = 0; c < CB; ++c) fa[c] = load_a_tr<FROW>(&s_f[b3][0][0], 16 * s, 32 * c, lane);
 #pragma unroll
-          for (int pb = 0; pb < NPB; ++pb) {
-            // the flag is wave-uniform: a scalar branch keeps the barrier loop uniform
-            if (!__builtin_amdgcn_readfirstlane(s_any[b2][pb >> 1][s])) continue;
-            const float* wr = &s_w[b2][32 * pb + (lane & 31)][16 * s + 8 * (lane >> 5)];
+          for (int pb = 0; pb < 2; ++pb) {
+            const float* wr = &s_w[b2][64 * wave + 32 * pb + (lane & 31)][16 * s + 8 * (lane >> 5)];
             const float4 w0 = *reinterpret_cast<const float4*>(wr);
             const float4 w1 = *reinterpret_cast<const float4*>(wr + 4);
             const float wf[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
-            bf16x8 bw[3];
+            u32x4 bw[3];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-              __bf16 h, m, l;
-              split3(wf[j], h, m, l);
+            for (int j = 0; j < 4; ++j) {
+              uint32_t h, m, l;
+              split3_pair(wf[2 * j], wf[2 * j + 1], h, m, l);
               bw[0][j] = h;
               bw[1][j] = m;
               bw[2][j] = l;
             }
 #pragma unroll
-            for (int c = 0; c < CPW; ++c) {
+            for (int c = 0; c < CB; ++c) {
               f32x16 z = acc[c][pb];
-              z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[c], bw[0], z, 0, 0, 0);
-              z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[c], bw[1], z, 0, 0, 0);
-              z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[c], bw[2], z, 0, 0, 0);
+#pragma unroll
+              for (int t = 0; t < 3; ++t)
+                z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[c], __builtin_bit_cast(bf16x8, bw[t]), z, 0, 0, 0);
               acc[c][pb] = z;
             }
           }
@@ -584,17 +596,17 @@ __global__ __launch_bounds__(2 * NT) void composite_fwd_ws_kernel(MfmaArgs a) {
     // feature image: accumulator row = channel, column = pixel
     const int64_t HW = (int64_t)a.W * a.H;
 #pragma unroll
-    for (int pb = 0; pb < NPB; ++pb) {
-      const int lpo = 32 * pb + (lane & 31);
+    for (int pb = 0; pb < 2; ++pb) {
+      const int lpo = 64 * wave + 32 * pb + (lane & 31);
       const int ox = (tile % a.tiles_x) * a.tile_w + lpo % a.tile_w;
       const int oy = (tile / a.tiles_x) * tile_h + lpo / a.tile_w;
       if (ox < a.W && oy < a.H) {
         const int64_t p = (int64_t)oy * a.W + ox;
 #pragma unroll
-        for (int c = 0; c < CPW; ++c)
+        for (int c = 0; c < CB; ++c)
 #pragma unroll
           for (int v = 0; v < 16; ++v) {
-            const int ch = 32 * (wave + NW * c) + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+            const int ch = 32 * c + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
             if (ch < a.D) a.out_feat[ch * HW + p] = acc[c][pb][v];
           }
       }
@@ -610,21 +622,14 @@ __global__ __launch_bounds__(2 * NT) void composite_fwd_ws_kernel(MfmaArgs a) {
 
 template <int DP, typename FT>
 hipError_t launch_nt(int nt, const MfmaArgs& a, int tiles, hipStream_t s) {
-  // wave-specialized kernel for BF16 features wherever accumulator waves own
-  // whole channel blocks
+  // wave-specialized kernel for BF16 features up to 128 channels
   if constexpr (std::is_same<FT, uint16_t>::value && DP <= 128) {
-    if (DP / 32 >= nt / 64) {
-      switch (nt) {
-        case 64: hipLaunchKernelGGL((composite_fwd_ws_kernel<DP, 64>), dim3(tiles), dim3(128), 0, s, a); break;
-        case 128:
-          if constexpr (DP >= 64) hipLaunchKernelGGL((composite_fwd_ws_kernel<DP, 128>), dim3(tiles), dim3(256), 0, s, a);
-          break;
-        default:
-          if constexpr (DP >= 128) hipLaunchKernelGGL((composite_fwd_ws_kernel<DP, 256>), dim3(tiles), dim3(512), 0, s, a);
-          break;
-      }
-      return hipGetLastError();
+    switch (nt) {
+      case 64: hipLaunchKernelGGL((composite_fwd_ws_kernel<DP, 64>), dim3(tiles), dim3(128), 0, s, a); break;
+      case 128: hipLaunchKernelGGL((composite_fwd_ws_kernel<DP, 128>), dim3(tiles), dim3(256), 0, s, a); break;
+      default: hipLaunchKernelGGL((composite_fwd_ws_kernel<DP, 256>), dim3(tiles), dim3(512), 0, s, a); break;
     }
+    return hipGetLastError();
   }
   switch (nt) {
     case 64: hipLaunchKernelGGL((composite_fwd_mfma_kernel<DP, FT, 64>), dim3(tiles), dim3(64), 0, s, a); break;
