@@ -435,8 +435,9 @@ __global__ __launch_bounds__(2 * NT) void composite_fwd_ws_kernel(MfmaArgs a) {
     const int b2 = k & 1, b3 = k % 3;
     const int nb = (int)min((uint32_t)kNB, rg.y - (rg.x + (uint32_t)k * kNB));
     if (q < kNB) {
+      // conic as (a, 2 b, c, opacity); padding entries get opacity 0
       s_xy[b2][q] = p_xy;
-      s_co[b2][q] = p_co;
+      s_co[b2][q] = make_float4(p_co.x, 2.0f * p_co.y, p_co.z, q < nb ? p_co.w : 0.f);
       s_rgb[b2][q] = p_rgb;
       s_box[b2][q] = make_int4(p_box.x, p_box.y, p_box.z, p_box.w);
     }
@@ -454,66 +455,61 @@ __global__ __launch_bounds__(2 * NT) void composite_fwd_ws_kernel(MfmaArgs a) {
 
   if (walker) {
     // ================= walkers =================
-    float T = 1.0f;
+    // T < 0 marks a finished pixel (|T| is its final transmittance), and a
+    // skipped pair carries alpha 0: a finished pixel or a skipped pair then
+    // leaves T, the colour and the weights unchanged with no per-pair mask
+    // logic, so the front-to-back chain is a few dependent VALU operations.
+    float T = inside ? 1.0f : -1.0f;
     float C0 = 0.f, C1 = 0.f, C2 = 0.f;
     int last = 0;
-    bool done = !inside;
     for (int kk = 0;; ++kk) {
       const int k = __builtin_amdgcn_readfirstlane(kk);   // scalar: keeps the barrier loop uniform
-      const int alive = __syncthreads_count(!done);
+      const int alive = __syncthreads_count(T > 0.f);
       const bool more = k < nbatch && alive > 0;
       if (!more) break;
       const int b2 = k & 1;
-      const int nb = (int)min((uint32_t)kNB, rg.y - (rg.x + (uint32_t)k * kNB));
       const int pos0 = k * kNB;
-      const bool wave_live = __ballot(!done) != 0ull;
-      constexpr int GR = 8;
+      const bool wave_live = __ballot(T > 0.f) != 0ull;
 #pragma unroll
       for (int s = 0; s < kNB / 16; ++s) {
         float wv[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) wv[i] = 0.f;
+        int lrel = 0;                                  // 1 + last pair of the 16 with a weight
         if (wave_live) {
+          // alpha of the 16 pairs, independent of each other (padding
+          // entries of the batch carry opacity 0 and are skipped here)
+          float al[16], om[16];
 #pragma unroll
-          for (int gi = 0; gi < 16 / GR; ++gi) {
-            float al[GR];
-            bool act[GR];
-#pragma unroll
-            for (int u = 0; u < GR; ++u) {
-              const int i = 16 * s + gi * GR + u;
-              const float2 m = s_xy[b2][i];
-              const float4 co = s_co[b2][i];
-              const int4 b = s_box[b2][i];
-              const float dx = fpx - m.x, dy = fpy - m.y;
-              const float qq = __builtin_fmaf(co.x * dx, dx, __builtin_fmaf(co.z * dy, dy, 2.0f * co.y * dx * dy));
-              const bool inb = (px >= b.x) & (px <= b.z) & (py >= b.y) & (py <= b.w);
-              const float alpha = fminf(kAlphaMax, co.w * __expf(-0.5f * qq));
-              act[u] = (i < nb) & inb & (qq <= kQMax) & (alpha >= kAlphaMin);
-              al[u] = alpha;
-            }
-#pragma unroll
-            for (int u = 0; u < GR; ++u) {
-              const int i = 16 * s + gi * GR + u;
-              const float Tn = T * (1.0f - al[u]);
-              const bool live = act[u] & !done;
-              const bool stop = live & (Tn < kTStop);
-              const bool take = live & !stop;
-              done = done | stop;
-              const float w = take ? al[u] * T : 0.f;
-              const float4 c = s_rgb[b2][i];
-              C0 = __builtin_fmaf(w, c.x, C0);
-              C1 = __builtin_fmaf(w, c.y, C1);
-              C2 = __builtin_fmaf(w, c.z, C2);
-              wv[gi * GR + u] = w;
-              T = take ? Tn : T;
-              last = take ? pos0 + i + 1 : last;
-            }
+          for (int u = 0; u < 16; ++u) {
+            const int i = 16 * s + u;
+            const float2 m = s_xy[b2][i];
+            const float4 co = s_co[b2][i];            // (a, 2 b, c, opacity)
+            const int4 b = s_box[b2][i];
+            const float dx = fpx - m.x, dy = fpy - m.y;
+            const float qq = __builtin_fmaf(co.x * dx, dx, __builtin_fmaf(co.z * dy, dy, co.y * dx * dy));
+            const bool inb = (px >= b.x) & (px <= b.z) & (py >= b.y) & (py <= b.w);
+            const float alpha = fminf(kAlphaMax, co.w * __expf(-0.5f * qq));
+            al[u] = (inb & (qq <= kQMax) & (alpha >= kAlphaMin)) ? alpha : 0.f;
+            om[u] = 1.0f - al[u];
           }
-        }
-        bool any = false;
+          // front-to-back transmittance chain
 #pragma unroll
-        for (int i = 0; i < 16; ++i) any |= wv[i] != 0.f;
-        const bool wany = __ballot(any) != 0ull;
+          for (int u = 0; u < 16; ++u) {
+            const float Tn = T * om[u];
+            const bool stop = Tn < kTStop;             // also true once T < 0
+            const float w = stop ? 0.f : al[u] * T;
+            T = stop ? -fabsf(T) : Tn;
+            const float4 c = s_rgb[b2][16 * s + u];
+            C0 = __builtin_fmaf(w, c.x, C0);
+            C1 = __builtin_fmaf(w, c.y, C1);
+            C2 = __builtin_fmaf(w, c.z, C2);
+            wv[u] = w;
+            lrel = w != 0.f ? u + 1 : lrel;
+          }
+          if (lrel > 0) last = pos0 + 16 * s + lrel;
+        }
+        const bool wany = __ballot(lrel > 0) != 0ull;
         if (lane == 0) s_any[b2][wave][s] = wany ? 1 : 0;
         if (wany) {
 #pragma unroll
@@ -522,6 +518,7 @@ __global__ __launch_bounds__(2 * NT) void composite_fwd_ws_kernel(MfmaArgs a) {
         }
       }
     }
+    T = fabsf(T);
     const int64_t HW = (int64_t)a.W * a.H;
     if (inside) {
       const int64_t p = (int64_t)py * a.W + px;
