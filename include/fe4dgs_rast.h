@@ -235,6 +235,16 @@ fe_status fe_read_report(const void* state, size_t state_bytes, fe_report* out, 
  * launches.  Frames are independent renders that share nothing but the
  * stream; per-frame results equal fe_render_forward / fe_render_backward on
  * that frame alone.
+ *
+ * With BF16 features, feat_dim <= 128, the matrix-core variant and frames of
+ * one image size, the compositing of all frames runs as one persistent launch
+ * per direction: after the per-frame projection and sorting, one workgroup
+ * orders every (frame, tile) item longest first (list length forward, walk
+ * length backward; empty walks are left out) and the persistent workgroups,
+ * one or more per compute unit, take items from that queue until it is empty.
+ * Otherwise each frame runs its own kernels inside the graph.  The workspace
+ * then also holds the queues and one argument record per frame (written by
+ * the first fe_batch_launch, before it captures).
  * ---------------------------------------------------------------------- */
 typedef struct fe_batch_plan fe_batch_plan;
 
@@ -247,7 +257,9 @@ size_t fe_batch_workspace_bytes(const fe_config* cfg, const fe_camera* cams, int
                                 const int64_t* n);
 
 /* Create a plan.  Arrays of length `frames`: cams, g, out, d_rgb, d_feat,
- * grads (d_rgb / d_feat / grads may be NULL for FE_MODE_FORWARD).  The plan
+ * grads (d_rgb / d_feat / grads may be NULL for FE_MODE_FORWARD; the gradient
+ * pointers of a frame with n == 0 may be NULL).  Returns FE_ERR_HIP when the
+ * device cannot be queried for the persistent launch size.  The plan
  * owns host memory and HIP graph handles only; `workspace` stays the
  * caller's.  The first fe_batch_launch captures the graph. */
 fe_status fe_batch_plan_create(const fe_config* cfg, const fe_camera* cams, int32_t frames,

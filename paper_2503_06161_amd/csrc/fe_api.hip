@@ -182,8 +182,9 @@ static fe_status check_gaussians(const fe_config* cfg, const fe_gaussians* g) {
   return FE_OK;
 }
 
-static fe_status forward_impl(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
-                              const fe_images* out, void* state, const Layout& L, hipStream_t s) {
+// forward up to the compositing: projection, binning and sorting
+static fe_status forward_pre(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g, void* state,
+                             const Layout& L, hipStream_t s) {
   StateView v = make_view(L, state);
   hipError_t e;
   const size_t zero_words = (L.ranges + sizeof(uint2) * (size_t)L.tiles - L.report) / 4;
@@ -194,10 +195,62 @@ static fe_status forward_impl(const fe_config* cfg, const fe_camera* cam, const 
   stage_mark(cfg, FE_STAGE_SORT, 0, s);
   if ((e = launch_sort_and_bin(cfg, v, s)) != hipSuccess) return FE_ERR_HIP;
   stage_mark(cfg, FE_STAGE_SORT, 1, s);
+  return FE_OK;
+}
+
+static fe_status forward_impl(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
+                              const fe_images* out, void* state, const Layout& L, hipStream_t s) {
+  const fe_status st = forward_pre(cfg, cam, g, state, L, s);
+  if (st != FE_OK) return st;
+  StateView v = make_view(L, state);
   stage_mark(cfg, FE_STAGE_COMPOSITE, 0, s);
-  e = cfg->variant == FE_VARIANT_VALU ? launch_composite_fwd(cfg, cam, g, v, out, s)
-                                       : launch_composite_fwd_mfma(cfg, cam, g, v, out, s);
+  const hipError_t e = cfg->variant == FE_VARIANT_VALU ? launch_composite_fwd(cfg, cam, g, v, out, s)
+                                                       : launch_composite_fwd_mfma(cfg, cam, g, v, out, s);
   stage_mark(cfg, FE_STAGE_COMPOSITE, 1, s);
+  return hip_status(e);
+}
+
+// backward of the matrix-core form around its compositing kernel: row
+// offsets of the tiles before, the per-Gaussian sums and the projection
+// backward after
+struct BwdBuffers {
+  float* grad2d;
+  uint32_t* row_base;
+  uint32_t* sums;
+  uint32_t* rowidx;
+  float* rows;
+  int64_t row_cap;
+};
+
+static BwdBuffers bwd_buffers(const fe_config* cfg, const fe_camera* cam, int64_t n, void* scratch) {
+  BwdScratch bs;
+  bwd_scratch_layout(cfg, cam, n, &bs);
+  char* sb = static_cast<char*>(scratch);
+  BwdBuffers b;
+  b.grad2d = reinterpret_cast<float*>(sb + bs.grad2d);
+  b.row_base = reinterpret_cast<uint32_t*>(sb + bs.row_base);
+  b.sums = reinterpret_cast<uint32_t*>(sb + bs.sums);
+  b.rowidx = reinterpret_cast<uint32_t*>(sb + bs.rowidx);
+  b.rows = reinterpret_cast<float*>(sb + bs.rows);
+  b.row_cap = bs.row_cap;
+  return b;
+}
+
+static fe_status backward_pre(const Layout& L, const void* state, const BwdBuffers& b, hipStream_t s) {
+  StateView v = make_view(L, const_cast<void*>(state));
+  if (launch_scan_u32(v.tile_maxlast, b.row_base, b.sums, v.tiles, s) != hipSuccess) return FE_ERR_HIP;
+  return hip_status(launch_zero_u32(b.rowidx, (size_t)L.cap, s));
+}
+
+static fe_status backward_post(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g, const Layout& L,
+                               const void* state, const BwdBuffers& b, const fe_grads* out, hipStream_t s) {
+  StateView v = make_view(L, const_cast<void*>(state));
+  stage_mark(cfg, FE_STAGE_REDUCE, 0, s);
+  if (launch_reduce_rows(cfg, v, b.rowidx, b.rows, b.grad2d, out->feat, s) != hipSuccess) return FE_ERR_HIP;
+  stage_mark(cfg, FE_STAGE_REDUCE, 1, s);
+  stage_mark(cfg, FE_STAGE_PROJECT_BWD, 0, s);
+  const hipError_t e = launch_project_bwd(make_cam_const(cam, cfg), cfg, g, v, b.grad2d, out, s);
+  stage_mark(cfg, FE_STAGE_PROJECT_BWD, 1, s);
   return hip_status(e);
 }
 
@@ -205,44 +258,30 @@ static fe_status backward_impl(const fe_config* cfg, const fe_camera* cam, const
                                const fe_images* fwd, const void* state, const Layout& L, const float* d_rgb,
                                const float* d_feat, const fe_grads* out, void* scratch, hipStream_t s) {
   StateView v = make_view(L, const_cast<void*>(state));
-  BwdScratch bs;
-  bwd_scratch_layout(cfg, cam, g->n, &bs);
-  char* sb = static_cast<char*>(scratch);
-  float* grad2d = reinterpret_cast<float*>(sb + bs.grad2d);
+  const BwdBuffers b = bwd_buffers(cfg, cam, g->n, scratch);
   hipError_t e;
   if (cfg->variant != FE_VARIANT_VALU) {
-    uint32_t* row_base = reinterpret_cast<uint32_t*>(sb + bs.row_base);
-    float* rows = reinterpret_cast<float*>(sb + bs.rows);
-    if ((e = launch_scan_u32(v.tile_maxlast, row_base, reinterpret_cast<uint32_t*>(sb + bs.sums), v.tiles, s)) !=
-        hipSuccess)
-      return FE_ERR_HIP;
+    fe_status st = backward_pre(L, state, b, s);
+    if (st != FE_OK) return st;
     stage_mark(cfg, FE_STAGE_COMPOSITE_BWD, 0, s);
-    uint32_t* rowidx = reinterpret_cast<uint32_t*>(sb + bs.rowidx);
-    if ((e = launch_zero_u32(rowidx, (size_t)L.cap, s)) != hipSuccess) return FE_ERR_HIP;
-    if ((e = launch_composite_bwd_mfma(cfg, cam, g, v, fwd, d_rgb, d_feat, row_base, rows, bs.row_cap, rowidx,
+    if ((e = launch_composite_bwd_mfma(cfg, cam, g, v, fwd, d_rgb, d_feat, b.row_base, b.rows, b.row_cap, b.rowidx,
                                        s)) != hipSuccess)
       return FE_ERR_HIP;
     stage_mark(cfg, FE_STAGE_COMPOSITE_BWD, 1, s);
-    stage_mark(cfg, FE_STAGE_REDUCE, 0, s);
-    if ((e = launch_reduce_rows(cfg, v, rowidx, rows, grad2d, out->feat, s)) != hipSuccess)
-      return FE_ERR_HIP;
-    stage_mark(cfg, FE_STAGE_REDUCE, 1, s);
-    stage_mark(cfg, FE_STAGE_PROJECT_BWD, 0, s);
-    e = launch_project_bwd(make_cam_const(cam, cfg), cfg, g, v, grad2d, out, s);
-    stage_mark(cfg, FE_STAGE_PROJECT_BWD, 1, s);
-    return hip_status(e);
+    return backward_post(cfg, cam, g, L, state, b, out, s);
   }
-  if ((e = launch_zero_u32(reinterpret_cast<uint32_t*>(grad2d), (size_t)12 * g->n, s)) != hipSuccess) return FE_ERR_HIP;
+  if ((e = launch_zero_u32(reinterpret_cast<uint32_t*>(b.grad2d), (size_t)12 * g->n, s)) != hipSuccess)
+    return FE_ERR_HIP;
   if (!(cfg->flags & FE_FLAG_NO_ZERO_GRADS)) {
     if ((e = launch_zero_u32(reinterpret_cast<uint32_t*>(out->feat), (size_t)cfg->feat_dim * g->n, s)) != hipSuccess)
       return FE_ERR_HIP;
   }
   stage_mark(cfg, FE_STAGE_COMPOSITE_BWD, 0, s);
-  if ((e = launch_composite_bwd(cfg, cam, g, v, fwd, d_rgb, d_feat, grad2d, out->feat, s)) != hipSuccess)
+  if ((e = launch_composite_bwd(cfg, cam, g, v, fwd, d_rgb, d_feat, b.grad2d, out->feat, s)) != hipSuccess)
     return FE_ERR_HIP;
   stage_mark(cfg, FE_STAGE_COMPOSITE_BWD, 1, s);
   stage_mark(cfg, FE_STAGE_PROJECT_BWD, 0, s);
-  e = launch_project_bwd(make_cam_const(cam, cfg), cfg, g, v, grad2d, out, s);
+  e = launch_project_bwd(make_cam_const(cam, cfg), cfg, g, v, b.grad2d, out, s);
   stage_mark(cfg, FE_STAGE_PROJECT_BWD, 1, s);
   return hip_status(e);
 }
@@ -373,7 +412,18 @@ fe_status fe_read_report(const void* state, size_t state_bytes, fe_report* out, 
 
 // ------------------------------------------------------------------------
 // Batched frames captured into one HIP graph.
+//
+// Where the wave-specialized compositing kernels apply (BF16 features,
+// D <= 128, frames of one image size), the compositing of all frames runs as
+// one persistent launch per direction: the per-frame stages before it run on
+// parallel branches, a single workgroup then builds a queue of every
+// (frame, tile) item ordered longest first, and the persistent workgroups take
+// items from it.  Otherwise every frame runs its own kernels.
 // ------------------------------------------------------------------------
+struct MultiLayout {
+  size_t rec_f, rec_b, rng, walk, items_f, items_b, qwords, total;
+};
+
 struct fe_batch_plan {
   fe_config cfg;
   int32_t frames;
@@ -385,24 +435,61 @@ struct fe_batch_plan {
   std::vector<fe_grads> grads;
   std::vector<Layout> layouts;
   std::vector<size_t> state_off, scratch_off;
+  bool persistent;
+  size_t multi_off;
+  MultiLayout ml;
+  int grid_f, grid_b;
   char* ws;
   hipGraph_t graph;
   hipGraphExec_t exec;
   bool captured;
 };
 
+static bool batch_persistent(const fe_config* cfg, const fe_camera* cams, int32_t frames) {
+  if (!composite_persistent_supported(cfg)) return false;
+  for (int f = 1; f < frames; ++f)
+    if (cams[f].width != cams[0].width || cams[f].height != cams[0].height) return false;
+  return true;
+}
+
+static size_t multi_layout(int32_t frames, int64_t tiles, MultiLayout* m) {
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  m->rec_f = take(frames * composite_fwd_record_bytes());
+  m->rec_b = take(frames * composite_bwd_record_bytes());
+  m->rng = take(frames * sizeof(void*));
+  m->walk = take(frames * sizeof(void*));
+  m->items_f = take((size_t)frames * tiles * sizeof(uint2));
+  m->items_b = take((size_t)frames * tiles * sizeof(uint2));
+  m->qwords = take(4 * sizeof(uint32_t));   // forward count, head; backward count, head
+  m->total = o;
+  return o;
+}
+
 static size_t batch_layout(const fe_config* cfg, const fe_camera* cams, int32_t frames, const int64_t* n,
                            std::vector<Layout>* layouts, std::vector<size_t>* st_off,
-                           std::vector<size_t>* sc_off) {
+                           std::vector<size_t>* sc_off, size_t* multi_off = nullptr, MultiLayout* ml = nullptr) {
   size_t o = 0;
+  int64_t tiles = 0;
   for (int f = 0; f < frames; ++f) {
     Layout L;
     if (!compute_layout(cfg, &cams[f], n[f], &L)) return 0;
+    tiles = L.tiles;
     if (layouts) layouts->push_back(L);
     if (st_off) st_off->push_back(o);
     o = align256(o + L.total);
     if (sc_off) sc_off->push_back(o);
     o = align256(o + fe_backward_scratch_bytes(cfg, &cams[f], n[f]));
+  }
+  if (batch_persistent(cfg, cams, frames)) {
+    MultiLayout m;
+    if (multi_off) *multi_off = o;
+    o = align256(o + multi_layout(frames, tiles, &m));
+    if (ml) *ml = m;
   }
   return o;
 }
@@ -432,19 +519,23 @@ fe_status fe_batch_plan_create(const fe_config* cfg, const fe_camera* cams, int3
     if (!out[f].rgb || !out[f].feat || !out[f].final_T || !out[f].n_contrib) return FE_ERR_INVALID_ARG;
     if (bwd) {
       if (!d_rgb[f] || !d_feat[f]) return FE_ERR_INVALID_ARG;
-      const fe_grads& gr = grads[f];
-      if (!gr.means || !gr.scales || !gr.quats || !gr.opacity || !gr.sh || !gr.feat) return FE_ERR_INVALID_ARG;
+      const fe_grads& gr = grads[f];   // a frame without Gaussians has no gradients
+      if (g[f].n > 0 && (!gr.means || !gr.scales || !gr.quats || !gr.opacity || !gr.sh || !gr.feat))
+        return FE_ERR_INVALID_ARG;
     }
     n[f] = g[f].n;
   }
   fe_batch_plan* p = new (std::nothrow) fe_batch_plan();
   if (!p) return FE_ERR_INVALID_ARG;
-  const size_t need = batch_layout(cfg, cams, frames, n.data(), &p->layouts, &p->state_off, &p->scratch_off);
+  p->multi_off = 0;
+  const size_t need = batch_layout(cfg, cams, frames, n.data(), &p->layouts, &p->state_off, &p->scratch_off,
+                                   &p->multi_off, &p->ml);
   if (workspace_bytes < need) {
     delete p;
     return FE_ERR_WORKSPACE_TOO_SMALL;
   }
   p->cfg = *cfg;
+  p->cfg.stage_events = nullptr;
   p->frames = frames;
   p->mode = mode;
   p->cams.assign(cams, cams + frames);
@@ -455,6 +546,16 @@ fe_status fe_batch_plan_create(const fe_config* cfg, const fe_camera* cams, int3
     p->d_feat.assign(d_feat, d_feat + frames);
     p->grads.assign(grads, grads + frames);
   }
+  p->persistent = batch_persistent(cfg, cams, frames);
+  p->grid_f = p->grid_b = 0;
+  if (p->persistent) {
+    p->grid_f = composite_fwd_persistent_grid(cfg);
+    p->grid_b = composite_bwd_persistent_grid(cfg);
+    if (p->grid_f < 1 || p->grid_b < 1) {
+      delete p;
+      return FE_ERR_HIP;
+    }
+  }
   p->ws = static_cast<char*>(workspace);
   p->graph = nullptr;
   p->exec = nullptr;
@@ -463,10 +564,50 @@ fe_status fe_batch_plan_create(const fe_config* cfg, const fe_camera* cams, int3
   return FE_OK;
 }
 
-// Frames are independent: frame f's forward (and backward) is enqueued on
-// branch stream f % kBranches, forked from and joined back into the capture
-// stream, so the captured graph has parallel chains the GPU may overlap.
+// Frames are independent: frame f's stages are enqueued on branch stream
+// f % kBranches, forked from and joined back into the capture stream, so the
+// captured graph has parallel chains the GPU may overlap.
 constexpr int kBranches = 4;
+
+struct Branches {
+  int n = 0;
+  hipStream_t s[kBranches] = {};
+  std::vector<hipEvent_t> events;
+  bool create(int frames) {
+    n = frames < kBranches ? frames : kBranches;
+    for (int b = 0; b < n; ++b)
+      if (hipStreamCreateWithFlags(&s[b], hipStreamNonBlocking) != hipSuccess) return false;
+    return true;
+  }
+  hipEvent_t event() {
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    events.push_back(e);
+    return e;
+  }
+  // the branches wait for everything enqueued on cs so far
+  bool fork(hipStream_t cs) {
+    hipEvent_t e = event();
+    if (!e || hipEventRecord(e, cs) != hipSuccess) return false;
+    for (int b = 0; b < n; ++b)
+      if (hipStreamWaitEvent(s[b], e, 0) != hipSuccess) return false;
+    return true;
+  }
+  // cs waits for everything enqueued on the branches so far
+  bool join(hipStream_t cs) {
+    bool ok = true;
+    for (int b = 0; b < n; ++b) {
+      hipEvent_t e = event();
+      ok = ok && e && hipEventRecord(e, s[b]) == hipSuccess && hipStreamWaitEvent(cs, e, 0) == hipSuccess;
+    }
+    return ok;
+  }
+  ~Branches() {
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    for (int b = 0; b < kBranches; ++b)
+      if (s[b]) (void)hipStreamDestroy(s[b]);
+  }
+};
 
 static fe_status frame_enqueue(fe_batch_plan* p, int f, hipStream_t s) {
   fe_status st = FE_OK;
@@ -478,36 +619,84 @@ static fe_status frame_enqueue(fe_batch_plan* p, int f, hipStream_t s) {
   return st;
 }
 
-struct Branches {
-  int n = 0;
-  hipStream_t s[kBranches] = {};
-  hipEvent_t fork = nullptr, join[kBranches] = {};
-  bool create(int frames) {
-    n = frames < kBranches ? frames : kBranches;
-    if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) return false;
-    for (int b = 0; b < n; ++b)
-      if (hipStreamCreateWithFlags(&s[b], hipStreamNonBlocking) != hipSuccess ||
-          hipEventCreateWithFlags(&join[b], hipEventDisableTiming) != hipSuccess)
-        return false;
-    return true;
-  }
-  ~Branches() {
-    for (int b = 0; b < kBranches; ++b) {
-      if (join[b]) (void)hipEventDestroy(join[b]);
-      if (s[b]) (void)hipStreamDestroy(s[b]);
+// Frame records and the per-frame pointer tables of the persistent path,
+// written once before the capture.
+static fe_status upload_multi(fe_batch_plan* p) {
+  const int F = p->frames;
+  const bool bwd = (p->mode & FE_MODE_BACKWARD) != 0;
+  char* m = p->ws + p->multi_off;
+  const size_t rf = composite_fwd_record_bytes(), rb = composite_bwd_record_bytes();
+  std::vector<char> recf(F * rf), recb(bwd ? F * rb : 0);
+  std::vector<const void*> rng(F), walk(F);
+  for (int f = 0; f < F; ++f) {
+    StateView v = make_view(p->layouts[f], p->ws + p->state_off[f]);
+    composite_fwd_record(&p->cfg, &p->cams[f], &p->g[f], v, &p->out[f], recf.data() + f * rf);
+    if (bwd) {
+      const BwdBuffers b = bwd_buffers(&p->cfg, &p->cams[f], p->g[f].n, p->ws + p->scratch_off[f]);
+      composite_bwd_record(&p->cfg, &p->cams[f], &p->g[f], v, &p->out[f], p->d_rgb[f], p->d_feat[f], b.row_base,
+                           b.rows, b.row_cap, b.rowidx, recb.data() + f * rb);
     }
-    if (fork) (void)hipEventDestroy(fork);
+    rng[f] = v.ranges;
+    walk[f] = v.tile_maxlast;
   }
-};
+  bool ok = hipMemcpy(m + p->ml.rec_f, recf.data(), recf.size(), hipMemcpyHostToDevice) == hipSuccess;
+  if (bwd) ok = ok && hipMemcpy(m + p->ml.rec_b, recb.data(), recb.size(), hipMemcpyHostToDevice) == hipSuccess;
+  ok = ok && hipMemcpy(m + p->ml.rng, rng.data(), F * sizeof(void*), hipMemcpyHostToDevice) == hipSuccess;
+  ok = ok && hipMemcpy(m + p->ml.walk, walk.data(), F * sizeof(void*), hipMemcpyHostToDevice) == hipSuccess;
+  return ok ? FE_OK : FE_ERR_HIP;
+}
+
+static fe_status composite_all(fe_batch_plan* p, bool backward, hipStream_t cs) {
+  char* m = p->ws + p->multi_off;
+  uint32_t* qw = reinterpret_cast<uint32_t*>(m + p->ml.qwords) + (backward ? 2 : 0);
+  TileQueueBuild qb;
+  qb.frames = p->frames;
+  qb.tiles = (int32_t)p->layouts[0].tiles;
+  qb.ranges = reinterpret_cast<const uint2* const*>(m + p->ml.rng);
+  qb.walk = backward ? reinterpret_cast<const uint32_t* const*>(m + p->ml.walk) : nullptr;
+  qb.items = reinterpret_cast<uint2*>(m + (backward ? p->ml.items_b : p->ml.items_f));
+  qb.count = qw;
+  qb.head = qw + 1;
+  if (launch_build_tile_queue(qb, cs) != hipSuccess) return FE_ERR_HIP;
+  TileQueue q{qb.items, qb.count, qb.head};
+  const hipError_t e = backward ? launch_composite_bwd_persistent(&p->cfg, m + p->ml.rec_b, q, p->grid_b, cs)
+                                : launch_composite_fwd_persistent(&p->cfg, m + p->ml.rec_f, q, p->grid_f, cs);
+  return hip_status(e);
+}
 
 static fe_status batch_enqueue(fe_batch_plan* p, hipStream_t cs, Branches& br) {
-  fe_status st = hipEventRecord(br.fork, cs) == hipSuccess ? FE_OK : FE_ERR_HIP;
-  for (int b = 0; st == FE_OK && b < br.n; ++b)
-    if (hipStreamWaitEvent(br.s[b], br.fork, 0) != hipSuccess) st = FE_ERR_HIP;
-  for (int f = 0; st == FE_OK && f < p->frames; ++f) st = frame_enqueue(p, f, br.s[f % br.n]);
-  // always join the branches so that the capture ends cleanly
-  for (int b = 0; b < br.n; ++b)
-    if (hipEventRecord(br.join[b], br.s[b]) == hipSuccess) (void)hipStreamWaitEvent(cs, br.join[b], 0);
+  fe_status st = FE_OK;
+  if (!p->persistent) {
+    if (!br.fork(cs)) return FE_ERR_HIP;
+    for (int f = 0; st == FE_OK && f < p->frames; ++f) st = frame_enqueue(p, f, br.s[f % br.n]);
+    // always join the branches so that the capture ends cleanly
+    return br.join(cs) ? st : FE_ERR_HIP;
+  }
+  auto per_frame = [&](auto&& stage) {
+    if (!br.fork(cs)) return FE_ERR_HIP;
+    fe_status r = FE_OK;
+    for (int f = 0; r == FE_OK && f < p->frames; ++f) r = stage(f, br.s[f % br.n]);
+    return br.join(cs) ? r : FE_ERR_HIP;
+  };
+  if (p->mode & FE_MODE_FORWARD) {
+    st = per_frame([&](int f, hipStream_t s) {
+      return forward_pre(&p->cfg, &p->cams[f], &p->g[f], p->ws + p->state_off[f], p->layouts[f], s);
+    });
+    if (st == FE_OK) st = composite_all(p, false, cs);
+  }
+  if (st == FE_OK && (p->mode & FE_MODE_BACKWARD)) {
+    auto buffers = [&](int f) { return bwd_buffers(&p->cfg, &p->cams[f], p->g[f].n, p->ws + p->scratch_off[f]); };
+    st = per_frame([&](int f, hipStream_t s) {
+      return p->g[f].n > 0 ? backward_pre(p->layouts[f], p->ws + p->state_off[f], buffers(f), s) : FE_OK;
+    });
+    if (st == FE_OK) st = composite_all(p, true, cs);
+    if (st == FE_OK)
+      st = per_frame([&](int f, hipStream_t s) {
+        return p->g[f].n > 0 ? backward_post(&p->cfg, &p->cams[f], &p->g[f], p->layouts[f],
+                                             p->ws + p->state_off[f], buffers(f), &p->grads[f], s)
+                             : FE_OK;
+      });
+  }
   return st;
 }
 
@@ -515,6 +704,10 @@ fe_status fe_batch_launch(fe_batch_plan* p, void* stream) {
   if (!p) return FE_ERR_INVALID_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (!p->captured) {
+    if (p->persistent) {
+      const fe_status st = upload_multi(p);
+      if (st != FE_OK) return st;
+    }
     // capture on a private non-default stream so that the caller's stream may be
     // the legacy default stream
     Branches br;

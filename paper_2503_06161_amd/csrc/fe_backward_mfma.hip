@@ -22,6 +22,7 @@
 // emit-position -> sorted-position map written by the tile sort.
 #include "fe_common.h"
 
+#include <cstring>
 #include <type_traits>
 
 #pragma clang fp contract(off)
@@ -85,8 +86,8 @@ __device__ __forceinline__ float row_sum16(float v) {
   return v;
 }
 
-template <int DP, typename FT, int NT>
-__global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
+template <int DP, typename FT, int NT, bool kLeaveEmpty>
+__device__ __forceinline__ void bwd_mfma_tile(const BwdArgs& a, const int tile) {
   constexpr bool F32 = std::is_same<FT, float>::value;
   constexpr int NPF = F32 ? 2 : 1;     // feature planes in GEMM1 (hi, mid)
   constexpr int CB = DP / 32;
@@ -124,7 +125,6 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
   // holds colour l % 16 (zero from 3 on) at pixels 8 (l / 16) + 0..7, hi / lo
   __shared__ bf16x8 s_grb[NW][2][2][64];
 
-  const int tile = blockIdx.x;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   // GEMM2 unit u of this wave: channel block and pixel chunk
@@ -152,14 +152,18 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
   };
 #pragma unroll
   for (int cb = 0; cb < GS; ++cb) load_g(cb, gv[cb]);
-  const uint2 rg = a.ranges[tile];
-  const int walk = (int)min(a.tile_maxlast[tile], rg.y - rg.x);
-  const int64_t row0 = a.row_base[tile];
-  if (row0 + walk > a.row_cap) {
-    if (threadIdx.x == 0) a.report[kRepStatus] = (unsigned long long)FE_ERR_ROW_OVERFLOW;
-    return;   // uniform: nothing of this tile can be stored
+  const uint2 rg = uniform_u2(a.ranges[tile]);
+  const int walk_all = __builtin_amdgcn_readfirstlane((int)min(a.tile_maxlast[tile], rg.y - rg.x));
+  const int64_t row0 = uniform_i64(a.row_base[tile]);
+  const bool overflow = __builtin_amdgcn_readfirstlane((int)(row0 + walk_all > a.row_cap));
+  if (overflow && threadIdx.x == 0) a.report[kRepStatus] = (unsigned long long)FE_ERR_ROW_OVERFLOW;
+  // nothing of an overflowing tile can be stored: it is walked as empty.  The
+  // per-tile kernel leaves empty tiles at once; inside the persistent loop the
+  // tile keeps a single exit (empty tiles are not queued there).
+  const int walk = __builtin_amdgcn_readfirstlane(overflow ? 0 : walk_all);
+  if constexpr (kLeaveEmpty) {
+    if (walk == 0) return;
   }
-  if (walk == 0) return;
 
   // Batches are walked back to front: batch k covers list positions
   // [r1 - kNB, r1) clipped at 0, r1 = walk - k kNB.  Staging is
@@ -280,7 +284,9 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
   }
   __syncthreads();   // the gradient slices are consumed; the region now holds W and dF
 
-  for (int r1 = walk; r1 > 0; r1 -= kNB) {
+  for (int r0 = walk;; r0 -= kNB) {
+    const int r1 = __builtin_amdgcn_readfirstlane(r0);   // scalar: keeps the barrier loop uniform
+    if (r1 <= 0) break;
     const int pos0 = r1 > kNB ? r1 - kNB : 0;
     const int nb = r1 - pos0;
     __syncthreads();
@@ -581,8 +587,8 @@ __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
 // each SIMD and the latency of one role hides behind the other's issue.  One
 // barrier per batch: the weights and liveness are double-buffered, the batch
 // records double- (conic/opacity and the sums triple-) buffered.
-template <int DP, typename FT, int NT>
-__global__ __launch_bounds__(2 * NT) void composite_bwd_ws_kernel(BwdArgs a) {
+template <int DP, typename FT, int NT, bool kLeaveEmpty>
+__device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
   constexpr bool F32 = std::is_same<FT, float>::value;
   constexpr int NPF = F32 ? 2 : 1;
   constexpr int CB = DP / 32;
@@ -608,7 +614,6 @@ __global__ __launch_bounds__(2 * NT) void composite_bwd_ws_kernel(BwdArgs a) {
   __shared__ float s_gr[3][NT];
   __shared__ bf16x8 s_grb[NW][2][2][64];
 
-  const int tile = blockIdx.x;
   const bool walker = (int)threadIdx.x < NT;
   const int q = walker ? (int)threadIdx.x : (int)threadIdx.x - NT;   // thread index within the role
   const int lane = q & 63;
@@ -637,15 +642,19 @@ __global__ __launch_bounds__(2 * NT) void composite_bwd_ws_kernel(BwdArgs a) {
 #pragma unroll
     for (int cb = 0; cb < GS; ++cb) load_g(cb, gv[cb]);
   }
-  const uint2 rg = a.ranges[tile];
-  const int walk = (int)min(a.tile_maxlast[tile], rg.y - rg.x);
-  const int64_t row0 = a.row_base[tile];
-  if (row0 + walk > a.row_cap) {
-    if (threadIdx.x == 0) a.report[kRepStatus] = (unsigned long long)FE_ERR_ROW_OVERFLOW;
-    return;   // uniform: nothing of this tile can be stored
+  const uint2 rg = uniform_u2(a.ranges[tile]);
+  const int walk_all = __builtin_amdgcn_readfirstlane((int)min(a.tile_maxlast[tile], rg.y - rg.x));
+  const int64_t row0 = uniform_i64(a.row_base[tile]);
+  const bool overflow = __builtin_amdgcn_readfirstlane((int)(row0 + walk_all > a.row_cap));
+  if (overflow && threadIdx.x == 0) a.report[kRepStatus] = (unsigned long long)FE_ERR_ROW_OVERFLOW;
+  // nothing of an overflowing tile can be stored: it is walked as empty.  The
+  // per-tile kernel leaves empty tiles at once; inside the persistent loop the
+  // tile keeps a single exit (empty tiles are not queued there).
+  const int walk = __builtin_amdgcn_readfirstlane(overflow ? 0 : walk_all);
+  if constexpr (kLeaveEmpty) {
+    if (walk == 0) return;
   }
-  if (walk == 0) return;
-  const int nbatch = (walk + kNB - 1) / kNB;
+  const int nbatch = __builtin_amdgcn_readfirstlane((walk + kNB - 1) / kNB);
   // batch k covers list positions [pos0(k), pos0(k) + nb(k)), walked back to front
   auto bpos0 = [&](int k) { const int r1 = walk - k * kNB; return r1 > kNB ? r1 - kNB : 0; };
   auto bnb = [&](int k) { return walk - k * kNB - bpos0(k); };
@@ -813,7 +822,9 @@ __global__ __launch_bounds__(2 * NT) void composite_bwd_ws_kernel(BwdArgs a) {
   // The two roles run separate loops with the same number of barriers, so
   // that the registers of one role are not live in the other's loop.
   if (walker) {
-    for (int it = 0; it <= nbatch; ++it) {
+    for (int i0 = 0;; ++i0) {
+      const int it = __builtin_amdgcn_readfirstlane(i0);   // scalar: keeps the barrier loop uniform
+      if (it > nbatch) break;
       if (it < nbatch) {
         // ================= walkers: batch it =================
         const int b2 = it & 1, b3 = it % 3;
@@ -965,7 +976,9 @@ __global__ __launch_bounds__(2 * NT) void composite_bwd_ws_kernel(BwdArgs a) {
       __syncthreads();
     }
   } else {
-    for (int it = 0; it <= nbatch; ++it) {
+    for (int i0 = 0;; ++i0) {
+      const int it = __builtin_amdgcn_readfirstlane(i0);   // scalar: keeps the barrier loop uniform
+      if (it > nbatch) break;
       // ================= contractors: GEMM2 and rows of batch it-1, staging of batch it+1 =================
       if (it >= 1) {
         const int k = it - 1;
@@ -1044,6 +1057,46 @@ __global__ __launch_bounds__(2 * NT) void composite_bwd_ws_kernel(BwdArgs a) {
       }
       __syncthreads();
     }
+  }
+}
+
+template <int DP, typename FT, int NT>
+__global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
+  bwd_mfma_tile<DP, FT, NT, true>(a, (int)blockIdx.x);
+}
+
+template <int DP, typename FT, int NT>
+__global__ __launch_bounds__(2 * NT) void composite_bwd_ws_kernel(BwdArgs a) {
+  bwd_ws_tile<DP, FT, NT, true>(a, (int)blockIdx.x);
+}
+
+// The wave-specialized form applies where contractor waves own whole channel
+// blocks; elsewhere one wave per 64 pixels runs both roles.
+template <int DP, int NT>
+constexpr bool bwd_uses_ws() { return DP <= 128 && DP / 32 >= NT / 64; }
+
+// Persistent form over many frames: each workgroup takes (frame, tile) items
+// from a queue sorted by walk length, longest first, until it is empty.
+template <int DP, typename FT, int NT>
+__global__ __launch_bounds__((bwd_uses_ws<DP, NT>() ? 2 * NT : NT)) void composite_bwd_persistent(
+    const BwdArgs* __restrict__ args, TileQueue tq) {
+  __shared__ uint32_t s_item;
+  const uint32_t n_items = __builtin_amdgcn_readfirstlane(*tq.count);
+  // items are fetched at the end of the loop (a divergent fetch at its head
+  // has been lowered into a nested loop with a per-lane exit); the second
+  // barrier keeps thread 0 from overwriting s_item before everyone read it
+  if (threadIdx.x == 0) s_item = atomicAdd(tq.head, 1u);
+  __syncthreads();
+  uint32_t it = __builtin_amdgcn_readfirstlane(s_item);
+  __syncthreads();
+  while (it < n_items) {
+    const uint2 item = tq.items[it];
+    if constexpr (bwd_uses_ws<DP, NT>()) bwd_ws_tile<DP, FT, NT, false>(args[item.x], (int)item.y);
+    else bwd_mfma_tile<DP, FT, NT, false>(args[item.x], (int)item.y);
+    if (threadIdx.x == 0) s_item = atomicAdd(tq.head, 1u);
+    __syncthreads();
+    it = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();
   }
 }
 
@@ -1155,27 +1208,20 @@ __global__ __launch_bounds__(256) void reduce_rows_kernel(ReduceArgs a) {
   if (sub < 3) a.grad2d[g * 12 + 9 + sub] = 0.f;
 }
 
+template <int DP, typename FT, int NT>
+static void launch_bwd_tiles(const BwdArgs& a, int tiles, hipStream_t s) {
+  if constexpr (bwd_uses_ws<DP, NT>())
+    hipLaunchKernelGGL((composite_bwd_ws_kernel<DP, FT, NT>), dim3(tiles), dim3(2 * NT), 0, s, a);
+  else
+    hipLaunchKernelGGL((composite_bwd_mfma_kernel<DP, FT, NT>), dim3(tiles), dim3(NT), 0, s, a);
+}
+
 template <int DP, typename FT>
 hipError_t launch_bwd_nt(int nt, const BwdArgs& a, int tiles, hipStream_t s) {
-  // wave-specialized kernel wherever contractor waves own whole channel blocks
-  if constexpr (DP <= 128) {
-    if (DP / 32 >= nt / 64) {
-      switch (nt) {
-        case 64: hipLaunchKernelGGL((composite_bwd_ws_kernel<DP, FT, 64>), dim3(tiles), dim3(128), 0, s, a); break;
-        case 128:
-          if constexpr (DP >= 64) hipLaunchKernelGGL((composite_bwd_ws_kernel<DP, FT, 128>), dim3(tiles), dim3(256), 0, s, a);
-          break;
-        default:
-          if constexpr (DP >= 128) hipLaunchKernelGGL((composite_bwd_ws_kernel<DP, FT, 256>), dim3(tiles), dim3(512), 0, s, a);
-          break;
-      }
-      return hipGetLastError();
-    }
-  }
   switch (nt) {
-    case 64: hipLaunchKernelGGL((composite_bwd_mfma_kernel<DP, FT, 64>), dim3(tiles), dim3(64), 0, s, a); break;
-    case 128: hipLaunchKernelGGL((composite_bwd_mfma_kernel<DP, FT, 128>), dim3(tiles), dim3(128), 0, s, a); break;
-    default: hipLaunchKernelGGL((composite_bwd_mfma_kernel<DP, FT, 256>), dim3(tiles), dim3(256), 0, s, a); break;
+    case 64: launch_bwd_tiles<DP, FT, 64>(a, tiles, s); break;
+    case 128: launch_bwd_tiles<DP, FT, 128>(a, tiles, s); break;
+    default: launch_bwd_tiles<DP, FT, 256>(a, tiles, s); break;
   }
   return hipGetLastError();
 }
@@ -1192,11 +1238,9 @@ hipError_t dispatch_bwd(int D, int nt, const BwdArgs& a, int tiles, hipStream_t 
 
 int backward_row_stride(int D) { return (D + 9 + 3) & ~3; }
 
-hipError_t launch_composite_bwd_mfma(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
-                                     const StateView& v, const fe_images* fwd, const float* d_rgb,
-                                     const float* d_feat, const uint32_t* row_base, float* rows,
-                                     int64_t row_cap, uint32_t* rowidx, hipStream_t s) {
-  if (v.tiles == 0) return hipSuccess;
+static BwdArgs make_bwd_args(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g, const StateView& v,
+                              const fe_images* fwd, const float* d_rgb, const float* d_feat,
+                              const uint32_t* row_base, float* rows, int64_t row_cap, uint32_t* rowidx) {
   BwdArgs a{};
   a.ranges = v.ranges;
   a.gauss = v.gauss_a;
@@ -1225,9 +1269,75 @@ hipError_t launch_composite_bwd_mfma(const fe_config* cfg, const fe_camera* cam,
   a.RS = backward_row_stride(cfg->feat_dim);
   const size_t esz = cfg->feat_dtype == FE_BF16 ? 2 : 4;
   a.vec = cfg->feat_dim % 4 == 0 && reinterpret_cast<uintptr_t>(g->feat) % (4 * esz) == 0;
+  return a;
+}
+
+hipError_t launch_composite_bwd_mfma(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
+                                     const StateView& v, const fe_images* fwd, const float* d_rgb,
+                                     const float* d_feat, const uint32_t* row_base, float* rows,
+                                     int64_t row_cap, uint32_t* rowidx, hipStream_t s) {
+  if (v.tiles == 0) return hipSuccess;
+  const BwdArgs a = make_bwd_args(cfg, cam, g, v, fwd, d_rgb, d_feat, row_base, rows, row_cap, rowidx);
   const int nt = cfg->tile_w * cfg->tile_h;
   return cfg->feat_dtype == FE_BF16 ? dispatch_bwd<uint16_t>(cfg->feat_dim, nt, a, v.tiles, s)
                                     : dispatch_bwd<float>(cfg->feat_dim, nt, a, v.tiles, s);
+}
+
+// ---- persistent multi-frame form (BF16 features, D <= 128) ----
+size_t composite_bwd_record_bytes() { return sizeof(BwdArgs); }
+
+void composite_bwd_record(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g, const StateView& v,
+                          const fe_images* fwd, const float* d_rgb, const float* d_feat, const uint32_t* row_base,
+                          float* rows, int64_t row_cap, uint32_t* rowidx, void* dst) {
+  const BwdArgs a = make_bwd_args(cfg, cam, g, v, fwd, d_rgb, d_feat, row_base, rows, row_cap, rowidx);
+  std::memcpy(dst, &a, sizeof(a));
+}
+
+template <int DP, int NT>
+static int bwd_grid() {
+  int per_cu = 0, dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
+  const int block = bwd_uses_ws<DP, NT>() ? 2 * NT : NT;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, composite_bwd_persistent<DP, uint16_t, NT>, block, 0) !=
+      hipSuccess)
+    return 0;
+  return per_cu * prop.multiProcessorCount;
+}
+
+template <int DP>
+static int bwd_grid_nt(int nt) {
+  return nt == 64 ? bwd_grid<DP, 64>() : nt == 128 ? bwd_grid<DP, 128>() : bwd_grid<DP, 256>();
+}
+
+int composite_bwd_persistent_grid(const fe_config* cfg) {
+  const int nt = cfg->tile_w * cfg->tile_h, D = cfg->feat_dim;
+  return D <= 32 ? bwd_grid_nt<32>(nt) : D <= 64 ? bwd_grid_nt<64>(nt) : bwd_grid_nt<128>(nt);
+}
+
+template <int DP, int NT>
+static void bwd_persistent_launch(const BwdArgs* r, const TileQueue& q, int grid, hipStream_t s) {
+  const int block = bwd_uses_ws<DP, NT>() ? 2 * NT : NT;
+  hipLaunchKernelGGL((composite_bwd_persistent<DP, uint16_t, NT>), dim3(grid), dim3(block), 0, s, r, q);
+}
+
+template <int DP>
+static hipError_t bwd_persistent_nt(int nt, const BwdArgs* r, const TileQueue& q, int grid, hipStream_t s) {
+  switch (nt) {
+    case 64: bwd_persistent_launch<DP, 64>(r, q, grid, s); break;
+    case 128: bwd_persistent_launch<DP, 128>(r, q, grid, s); break;
+    default: bwd_persistent_launch<DP, 256>(r, q, grid, s); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_composite_bwd_persistent(const fe_config* cfg, const void* records, const TileQueue& q,
+                                           int grid, hipStream_t s) {
+  if (grid < 1) return hipErrorInvalidValue;
+  const int nt = cfg->tile_w * cfg->tile_h, D = cfg->feat_dim;
+  const BwdArgs* r = static_cast<const BwdArgs*>(records);
+  return D <= 32 ? bwd_persistent_nt<32>(nt, r, q, grid, s)
+                 : D <= 64 ? bwd_persistent_nt<64>(nt, r, q, grid, s) : bwd_persistent_nt<128>(nt, r, q, grid, s);
 }
 
 hipError_t launch_reduce_rows(const fe_config* cfg, const StateView& v, const uint32_t* rowidx,

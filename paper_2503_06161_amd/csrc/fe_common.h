@@ -115,7 +115,54 @@ hipError_t launch_project_bwd(const CamConst& cc, const fe_config* cfg, const fe
                               const StateView& v, const float* grad2d, const fe_grads* out,
                               hipStream_t s);
 
+// ---- compositing of many frames from one work queue ----
+// Items are (frame, tile) pairs.  The queue builder writes them longest first
+// (by the tile's list length, or by its backward walk length), stores their
+// number and sets the head counter, from which the workgroups of a persistent
+// compositing kernel take items, to zero.
+struct TileQueue {
+  const uint2* items;
+  const uint32_t* count;
+  uint32_t* head;
+};
+struct TileQueueBuild {
+  int32_t frames, tiles;               // tiles per frame
+  const uint2* const* ranges;          // [frames] device pointers to each frame's tile ranges
+  const uint32_t* const* walk;         // [frames] tile walk lengths (backward), or null (forward)
+  uint2* items;                        // [frames * tiles]
+  uint32_t* count;
+  uint32_t* head;
+};
+hipError_t launch_build_tile_queue(const TileQueueBuild& b, hipStream_t s);
+// Frame records are the argument blocks of the per-frame kernels, kept in
+// device memory, one per frame.
+bool composite_persistent_supported(const fe_config* cfg);
+size_t composite_fwd_record_bytes();
+void composite_fwd_record(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g, const StateView& v,
+                          const fe_images* out, void* dst);
+int composite_fwd_persistent_grid(const fe_config* cfg);
+hipError_t launch_composite_fwd_persistent(const fe_config* cfg, const void* records, const TileQueue& q,
+                                           int grid, hipStream_t s);
+size_t composite_bwd_record_bytes();
+void composite_bwd_record(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g, const StateView& v,
+                          const fe_images* fwd, const float* d_rgb, const float* d_feat, const uint32_t* row_base,
+                          float* rows, int64_t row_cap, uint32_t* rowidx, void* dst);
+int composite_bwd_persistent_grid(const fe_config* cfg);
+hipError_t launch_composite_bwd_persistent(const fe_config* cfg, const void* records, const TileQueue& q,
+                                           int grid, hipStream_t s);
+
 // ---- small device helpers ----
+// Per-tile quantities that steer loops containing barriers are read back as
+// scalars: the compiler then treats them as uniform and never lowers such a
+// loop (or an early exit around it) with a per-lane exit mask.
+__device__ __forceinline__ uint2 uniform_u2(uint2 v) {
+  return make_uint2(__builtin_amdgcn_readfirstlane(v.x), __builtin_amdgcn_readfirstlane(v.y));
+}
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
+  const uint64_t u = (uint64_t)v;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u), hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 __device__ __forceinline__ float bf16_bits_to_float(uint16_t b) {
   return __uint_as_float(static_cast<uint32_t>(b) << 16);
 }

@@ -23,6 +23,7 @@
 // Gaussians j and 8 + j produces that layout for both pixel blocks at once.
 #include "fe_common.h"
 
+#include <cstring>
 #include <type_traits>
 
 #pragma clang fp contract(off)
@@ -371,7 +372,7 @@ void composite_fwd_mfma_kernel(MfmaArgs a) {
 // One barrier per batch (the early-termination count); weights and records
 // are double-buffered, feature rows triple-buffered.
 template <int DP, int NT>
-__global__ __launch_bounds__(2 * NT) void composite_fwd_ws_kernel(MfmaArgs a) {
+__device__ __forceinline__ void fwd_ws_tile(const MfmaArgs& a, const int tile) {
   constexpr int CB = DP / 32;
   constexpr int NW = NT / 64;
   constexpr int FROW = DP + 32;
@@ -385,7 +386,6 @@ __global__ __launch_bounds__(2 * NT) void composite_fwd_ws_kernel(MfmaArgs a) {
   __shared__ int s_any[2][NW][2];              // the chunk has a nonzero weight in the k step
   __shared__ int s_maxlast;
 
-  const int tile = blockIdx.x;
   const bool walker = (int)threadIdx.x < NT;
   const int q = walker ? (int)threadIdx.x : (int)threadIdx.x - NT;
   const int lane = q & 63;
@@ -395,7 +395,7 @@ __global__ __launch_bounds__(2 * NT) void composite_fwd_ws_kernel(MfmaArgs a) {
   const int py = (tile / a.tiles_x) * tile_h + q / a.tile_w;
   const bool inside = walker & (px < a.W) & (py < a.H);
   const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
-  const uint2 rg = a.ranges[tile];
+  const uint2 rg = uniform_u2(a.ranges[tile]);
   const int nbatch = (int)((rg.y - rg.x + kNB - 1) / kNB);
   if (threadIdx.x == 0) s_maxlast = 0;
 
@@ -617,6 +617,35 @@ __global__ __launch_bounds__(2 * NT) void composite_fwd_ws_kernel(MfmaArgs a) {
   }
 }
 
+template <int DP, int NT>
+__global__ __launch_bounds__(2 * NT) void composite_fwd_ws_kernel(MfmaArgs a) {
+  fwd_ws_tile<DP, NT>(a, (int)blockIdx.x);
+}
+
+// Persistent form over many frames: each workgroup takes (frame, tile) items
+// from a queue sorted longest first until the queue is empty.
+template <int DP, int NT>
+__global__ __launch_bounds__(2 * NT) void composite_fwd_ws_persistent(const MfmaArgs* __restrict__ args,
+                                                                      TileQueue tq) {
+  __shared__ uint32_t s_item;
+  const uint32_t n_items = __builtin_amdgcn_readfirstlane(*tq.count);
+  // items are fetched at the end of the loop (a divergent fetch at its head
+  // has been lowered into a nested loop with a per-lane exit); the second
+  // barrier keeps thread 0 from overwriting s_item before everyone read it
+  if (threadIdx.x == 0) s_item = atomicAdd(tq.head, 1u);
+  __syncthreads();
+  uint32_t it = __builtin_amdgcn_readfirstlane(s_item);
+  __syncthreads();
+  while (it < n_items) {
+    const uint2 item = tq.items[it];
+    fwd_ws_tile<DP, NT>(args[item.x], (int)item.y);
+    if (threadIdx.x == 0) s_item = atomicAdd(tq.head, 1u);
+    __syncthreads();
+    it = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();
+  }
+}
+
 template <int DP, typename FT>
 hipError_t launch_nt(int nt, const MfmaArgs& a, int tiles, hipStream_t s) {
   // wave-specialized kernel for BF16 features up to 128 channels
@@ -646,9 +675,8 @@ hipError_t dispatch(int D, int nt, const MfmaArgs& a, int tiles, hipStream_t s) 
 
 }  // namespace
 
-hipError_t launch_composite_fwd_mfma(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
-                                     const StateView& v, const fe_images* out, hipStream_t s) {
-  if (v.tiles == 0) return hipSuccess;
+static MfmaArgs make_args(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g, const StateView& v,
+                          const fe_images* out) {
   MfmaArgs a{};
   a.ranges = v.ranges;
   a.gauss = v.gauss_a;
@@ -671,9 +699,69 @@ hipError_t launch_composite_fwd_mfma(const fe_config* cfg, const fe_camera* cam,
   a.D = cfg->feat_dim;
   const size_t esz = cfg->feat_dtype == FE_BF16 ? 2 : 4;
   a.vec = cfg->feat_dim % 4 == 0 && reinterpret_cast<uintptr_t>(g->feat) % (4 * esz) == 0;
+  return a;
+}
+
+hipError_t launch_composite_fwd_mfma(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
+                                     const StateView& v, const fe_images* out, hipStream_t s) {
+  if (v.tiles == 0) return hipSuccess;
+  const MfmaArgs a = make_args(cfg, cam, g, v, out);
   const int nt = cfg->tile_w * cfg->tile_h;
   return cfg->feat_dtype == FE_BF16 ? dispatch<uint16_t>(cfg->feat_dim, nt, a, v.tiles, s)
                                     : dispatch<float>(cfg->feat_dim, nt, a, v.tiles, s);
+}
+
+// ---- persistent multi-frame form (wave-specialized kernels only) ----
+bool composite_persistent_supported(const fe_config* cfg) {
+  return cfg->variant != FE_VARIANT_VALU && cfg->feat_dtype == FE_BF16 && cfg->feat_dim <= 128;
+}
+
+size_t composite_fwd_record_bytes() { return sizeof(MfmaArgs); }
+
+void composite_fwd_record(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g, const StateView& v,
+                          const fe_images* out, void* dst) {
+  const MfmaArgs a = make_args(cfg, cam, g, v, out);
+  std::memcpy(dst, &a, sizeof(a));
+}
+
+template <int DP, int NT>
+static int fwd_grid() {
+  int per_cu = 0, dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, composite_fwd_ws_persistent<DP, NT>, 2 * NT, 0) !=
+      hipSuccess)
+    return 0;
+  return per_cu * prop.multiProcessorCount;
+}
+
+template <int DP>
+static int fwd_grid_nt(int nt) {
+  return nt == 64 ? fwd_grid<DP, 64>() : nt == 128 ? fwd_grid<DP, 128>() : fwd_grid<DP, 256>();
+}
+
+int composite_fwd_persistent_grid(const fe_config* cfg) {
+  const int nt = cfg->tile_w * cfg->tile_h, D = cfg->feat_dim;
+  return D <= 32 ? fwd_grid_nt<32>(nt) : D <= 64 ? fwd_grid_nt<64>(nt) : fwd_grid_nt<128>(nt);
+}
+
+template <int DP>
+static hipError_t fwd_persistent_nt(int nt, const MfmaArgs* r, const TileQueue& q, int grid, hipStream_t s) {
+  switch (nt) {
+    case 64: hipLaunchKernelGGL((composite_fwd_ws_persistent<DP, 64>), dim3(grid), dim3(128), 0, s, r, q); break;
+    case 128: hipLaunchKernelGGL((composite_fwd_ws_persistent<DP, 128>), dim3(grid), dim3(256), 0, s, r, q); break;
+    default: hipLaunchKernelGGL((composite_fwd_ws_persistent<DP, 256>), dim3(grid), dim3(512), 0, s, r, q); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_composite_fwd_persistent(const fe_config* cfg, const void* records, const TileQueue& q,
+                                           int grid, hipStream_t s) {
+  if (grid < 1) return hipErrorInvalidValue;
+  const int nt = cfg->tile_w * cfg->tile_h, D = cfg->feat_dim;
+  const MfmaArgs* r = static_cast<const MfmaArgs*>(records);
+  return D <= 32 ? fwd_persistent_nt<32>(nt, r, q, grid, s)
+                 : D <= 64 ? fwd_persistent_nt<64>(nt, r, q, grid, s) : fwd_persistent_nt<128>(nt, r, q, grid, s);
 }
 
 }  // namespace fe

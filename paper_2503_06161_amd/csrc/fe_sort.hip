@@ -390,6 +390,53 @@ hipError_t radix_pass(RadixArgs a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ---- work queue of (frame, tile) items, longest first ----
+// One workgroup: every item gets the bucket 1 + floor(log2(length)) (0 for
+// an empty tile), buckets are laid out from the longest down, and items are
+// placed in their bucket by LDS counters (the order inside a bucket is
+// arbitrary: every item is processed by exactly one workgroup, so the
+// results do not depend on it).  Backward queues leave out tiles with no
+// walk.  The kernel also sets the count and clears the head counter.
+constexpr int kQueueBuckets = 33;
+
+__device__ __forceinline__ uint32_t queue_item_length(const TileQueueBuild& b, int f, int t) {
+  const uint2 rg = b.ranges[f][t];
+  const uint32_t len = rg.y - rg.x;
+  return b.walk ? min(b.walk[f][t], len) : len;
+}
+
+__device__ __forceinline__ int queue_bucket(uint32_t len) { return len == 0 ? 0 : 32 - __clz(len); }
+
+__global__ __launch_bounds__(1024) void build_tile_queue_kernel(TileQueueBuild b) {
+  __shared__ uint32_t s_n[kQueueBuckets], s_pos[kQueueBuckets];
+  const int total = b.frames * b.tiles;
+  if (threadIdx.x < kQueueBuckets) s_n[threadIdx.x] = 0;
+  __syncthreads();
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    const uint32_t len = queue_item_length(b, e / b.tiles, e % b.tiles);
+    if (b.walk && len == 0) continue;
+    atomicAdd(&s_n[queue_bucket(len)], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t o = 0;
+    for (int k = kQueueBuckets - 1; k >= 0; --k) {
+      s_pos[k] = o;
+      o += s_n[k];
+    }
+    *b.count = o;
+    *b.head = 0u;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    const int f = e / b.tiles, t = e % b.tiles;
+    const uint32_t len = queue_item_length(b, f, t);
+    if (b.walk && len == 0) continue;
+    const uint32_t pos = atomicAdd(&s_pos[queue_bucket(len)], 1u);
+    b.items[pos] = make_uint2((uint32_t)f, (uint32_t)t);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, uint32_t* sums, int64_t n, hipStream_t s) {
@@ -464,6 +511,12 @@ hipError_t launch_sort_and_bin(const fe_config* cfg, const StateView& v, hipStre
   const unsigned rb = (unsigned)((v.cap + 255) / 256);
   if (rb) hipLaunchKernelGGL(ranges_kernel, dim3(rb), dim3(256), 0, s, (const uint32_t*)v.tile_a,
                              (const unsigned long long*)total, v.cap, v.ranges, (uint32_t)v.tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_tile_queue(const TileQueueBuild& b, hipStream_t s) {
+  if (b.frames < 1 || b.tiles < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(build_tile_queue_kernel, dim3(1), dim3(1024), 0, s, b);
   return hipGetLastError();
 }
 

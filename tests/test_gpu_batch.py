@@ -40,11 +40,17 @@ def _frames(n_frames=4, pool=20_000, w=160, h=128):
     return sc, fr, frames, cams
 
 
-@pytest.mark.parametrize("variant", [rast.FE_VARIANT_VALU, rast.FE_VARIANT_MFMA])
-def test_batched_graph_equals_per_frame(variant):
-    say("batched 4 frames, variant", variant)
+# VALU: per-frame kernels in the graph.  MFMA: one persistent compositing
+# launch per direction over a longest-first (frame, tile) queue; 16x16 tiles
+# at D = 64 use the single-role backward tile, 8x8 and 16x8 the
+# wave-specialized one.
+@pytest.mark.parametrize("variant,tile", [(rast.FE_VARIANT_VALU, (16, 16)), (rast.FE_VARIANT_MFMA, (16, 16)),
+                                          (rast.FE_VARIANT_MFMA, (8, 8)), (rast.FE_VARIANT_MFMA, (16, 8))])
+def test_batched_graph_equals_per_frame(variant, tile):
+    say("batched 4 frames, variant", variant, "tile", tile)
     sc, fr, frames, cams = _frames()
-    st = rast.Settings(sh_degree=3, feat_dim=64, sh_dtype="bf16", feat_dtype="bf16", variant=variant)
+    st = rast.Settings(sh_degree=3, feat_dim=64, sh_dtype="bf16", feat_dtype="bf16", variant=variant,
+                       tile_w=tile[0], tile_h=tile[1])
     rng = np.random.default_rng(1)
     H, W = cams[0].height, cams[0].width
     d_rgb = [torch.from_numpy(rng.normal(0, 1e-3, (3, H, W)).astype(np.float32)).cuda() for _ in frames]
@@ -66,6 +72,45 @@ def test_batched_graph_equals_per_frame(variant):
             assert torch.equal(br.out[k]["final_T"], ref.final_T)
             assert torch.equal(br.out[k]["n_contrib"], ref.n_contrib)
             torch.testing.assert_close(br.out[k]["feat"], ref.feat, rtol=0, atol=1e-6)
+            g = rast.render_backward(ref, f["means"], f["scales"], f["quats"], f["opacity"], f["sh"], f["feat"],
+                                     d_rgb[k], d_feat[k], st)
+            for name in ("means", "scales", "quats", "opacity", "sh", "feat"):
+                a, b = br.grads[k][name].double(), g[name].double()
+                err = float((a - b).norm() / max(float(b.norm()), 1e-30))
+                assert err < 1e-5, (rep, k, name, err)
+    br.close()
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8)])
+def test_batched_with_an_empty_frame(tile):
+    """A frame with no Gaussians inside a batch: its tiles are all empty (the
+    forward writes the background, the backward queue leaves them out) and
+    the other frames are unaffected."""
+    say("batched frames with an empty one, tile", tile)
+    sc, fr, frames, cams = _frames(n_frames=3, pool=12_000)
+    empty = {k: v[:0].contiguous() for k, v in frames[1].items()}
+    frames = [frames[0], empty, frames[2]]
+    st = rast.Settings(sh_degree=3, feat_dim=64, sh_dtype="bf16", feat_dtype="bf16", tile_w=tile[0],
+                       tile_h=tile[1])
+    rng = np.random.default_rng(2)
+    H, W = cams[0].height, cams[0].width
+    d_rgb = [torch.from_numpy(rng.normal(0, 1e-3, (3, H, W)).astype(np.float32)).cuda() for _ in frames]
+    d_feat = [torch.from_numpy(rng.normal(0, 1e-3, (64, H, W)).astype(np.float32)).cuda() for _ in frames]
+    br = BatchRenderer(frames, cams, st, rast.FE_MODE_FORWARD_BACKWARD, d_rgb, d_feat)
+    for rep in range(2):
+        br.launch()
+        torch.cuda.synchronize()
+        for k, f in enumerate(frames):
+            assert br.report(k)["status"] == 0
+            ref = rast.render_forward(f["means"], f["scales"], f["quats"], f["opacity"], f["sh"], f["feat"],
+                                      cams[k], st)
+            assert torch.equal(br.out[k]["rgb"], ref.rgb)
+            assert torch.equal(br.out[k]["final_T"], ref.final_T)
+            assert torch.equal(br.out[k]["n_contrib"], ref.n_contrib)
+            torch.testing.assert_close(br.out[k]["feat"], ref.feat, rtol=0, atol=1e-6)
+            if k == 1:
+                assert bool((br.out[k]["final_T"] == 1).all()) and int(br.out[k]["n_contrib"].max()) == 0
+                continue
             g = rast.render_backward(ref, f["means"], f["scales"], f["quats"], f["opacity"], f["sh"], f["feat"],
                                      d_rgb[k], d_feat[k], st)
             for name in ("means", "scales", "quats", "opacity", "sh", "feat"):
