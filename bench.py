@@ -185,6 +185,9 @@ def run_batched(steps, warmup):
     d_rgb = [t(rng.normal(0, 1e-3, (3, H, W)).astype(np.float32)) for _ in fr]
     d_feat = [t(rng.normal(0, 1e-3, (64, H, W)).astype(np.float32)) for _ in fr]
     st = rast.Settings(sh_degree=3, feat_dim=64, sh_dtype="bf16", feat_dtype="bf16")
+    # tile shape and variant from the batch autotuner (untimed; whole replays)
+    from paper_2503_06161_amd import autotune
+    st = autotune.autotune_batch(frames, cams, st, d_rgb, d_feat)
     br = BatchRenderer(frames, cams, st, rast.FE_MODE_FORWARD_BACKWARD, d_rgb, d_feat)
     for _ in range(warmup):
         br.launch()
@@ -198,7 +201,8 @@ def run_batched(steps, warmup):
     br.close()
     ms = 1e3 * (t1 - t0) / steps
     return dict(frames=len(fr), gaussians_per_frame=[f["n"] for f in fr], ms_per_replay=round(ms, 4),
-                frames_per_s=round(len(fr) * 1e3 / ms, 2), status_errors=bad)
+                frames_per_s=round(len(fr) * 1e3 / ms, 2), status_errors=bad,
+                tile=f"{st.tile_w}x{st.tile_h}", variant="valu" if st.variant == rast.FE_VARIANT_VALU else "mfma")
 
 
 def cpu_baseline(sc, sample_tiles):

@@ -199,10 +199,10 @@ fe_status fe_state_layout_get(const fe_config* cfg, const fe_camera* cam, int64_
                               fe_state_layout* out);
 
 /* Scratch needed by fe_render_backward (host only).  With the matrix-core
- * variant it holds one partial-gradient row of round_up(D + 9, 4) floats for
- * each (tile, list position) the backward walks; the forward's
- * report.rows_needed gives the exact count for a frame, and row_capacity
- * bounds it. */
+ * variant it holds one partial-gradient row of round_up(D + 9, 32) floats
+ * (whole 128-byte lines) for each (tile, list position) the backward walks;
+ * the forward's report.rows_needed gives the exact count for a frame, and
+ * row_capacity bounds it. */
 size_t    fe_backward_scratch_bytes(const fe_config* cfg, const fe_camera* cam, int64_t n);
 
 /* Forward render of one camera.  `state` (device, state_bytes >=

@@ -98,3 +98,44 @@ def autotune(g: dict, cam, st: rast.Settings, d_rgb=None, d_feat=None, candidate
                           all=[dict(tile_w=a, tile_h=b, variant=c, ms=m) for m, a, b, c in results])
         _store_cache(cache)
     return rast.Settings(**{**st.__dict__, "tile_w": tw, "tile_h": th, "variant": v})
+
+
+def autotune_batch(frames, cams, st: rast.Settings, d_rgb=None, d_feat=None, candidates=None, use_cache=True,
+                   reps: int = 5, verbose=False) -> rast.Settings:
+    """Tile shape and variant for a batch of frames, chosen by timing whole
+    graph replays of the batch (the multi-frame compositing path included).
+    ``frames``/``cams``/``d_rgb``/``d_feat`` are as for ``BatchRenderer``."""
+    from .batch import BatchRenderer
+    mode = rast.FE_MODE_FORWARD_BACKWARD if d_rgb is not None else rast.FE_MODE_FORWARD
+    n = max(int(f["means"].shape[0]) for f in frames)
+    key = cache_key(cams[0], st, n, d_rgb is not None) + f"|batch{len(frames)}"
+    cache = _load_cache() if use_cache else {}
+    if key in cache:
+        c = cache[key]
+        return rast.Settings(**{**st.__dict__, "tile_w": c["tile_w"], "tile_h": c["tile_h"], "variant": c["variant"]})
+    cands = candidates or [(tw, th, v) for (tw, th) in TILE_SHAPES for v in VARIANTS]
+    results = []
+    for tw, th, v in cands:
+        s2 = rast.Settings(**{**st.__dict__, "tile_w": tw, "tile_h": th, "variant": v})
+        br = BatchRenderer(frames, cams, s2, mode, d_rgb, d_feat)
+        br.launch()
+        times = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            br.launch()
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        br.close()
+        times.sort()
+        ms = times[len(times) // 2]
+        results.append((ms, tw, th, v))
+        if verbose:
+            print(f"autotune batch {tw}x{th} variant {v}: {ms:.3f} ms", flush=True)
+    ms, tw, th, v = min(results)
+    if use_cache:
+        cache[key] = dict(tile_w=tw, tile_h=th, variant=v, ms=ms,
+                          all=[dict(tile_w=a, tile_h=b, variant=c, ms=m) for m, a, b, c in results])
+        _store_cache(cache)
+    return rast.Settings(**{**st.__dict__, "tile_w": tw, "tile_h": th, "variant": v})

@@ -1236,7 +1236,11 @@ hipError_t dispatch_bwd(int D, int nt, const BwdArgs& a, int tiles, hipStream_t 
 
 }  // namespace
 
-int backward_row_stride(int D) { return (D + 9 + 3) & ~3; }
+// Rows are padded to whole 128-byte lines: each 32-channel block of dF and
+// the closing block of the row (the nine projected-space sums and zeros) is
+// then one full, aligned line written by one store instruction, instead of
+// partial lines written at different times by different waves.
+int backward_row_stride(int D) { return (D + 9 + 31) & ~31; }
 
 static BwdArgs make_bwd_args(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g, const StateView& v,
                               const fe_images* fwd, const float* d_rgb, const float* d_feat,
