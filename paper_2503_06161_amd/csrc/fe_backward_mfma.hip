@@ -601,12 +601,16 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
   constexpr size_t kGBytes = sizeof(float) * 32 * GROW;
   constexpr size_t kWBytes = sizeof(__bf16) * 2 * NW * 2 * kNB * WROW;
   constexpr size_t kShared = kGBytes > kWBytes ? kGBytes : kWBytes;
-  __shared__ float2 s_xy[2][kNB];
+  __shared__ float2 s_xy[3][kNB];
   __shared__ float4 s_co[3][kNB];
   __shared__ float4 s_rgb[2][kNB];
   __shared__ int4 s_box[2][kNB];
   __shared__ __attribute__((aligned(16))) __bf16 s_f[2][NPF][kNB][FROW];
-  __shared__ float s_red[3][12][kNB];
+  // per walker wave: pixel moments (about the tile centre) and colour sums of
+  // each Gaussian of a batch, and the X values of a 16-Gaussian half
+  __shared__ float s_mom[2][NW][6][kNB];
+  __shared__ float s_col[2][NW][3][kNB];
+  __shared__ float s_xm[NW][16][64];
   __shared__ int s_live[2][NW];
   __shared__ __attribute__((aligned(16))) unsigned char s_raw[kShared];
   float (*s_g)[GROW] = reinterpret_cast<float (*)[GROW]>(s_raw);
@@ -696,7 +700,7 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
     const int b2 = k & 1, b3 = k % 3, nb = bnb(k);
     ep_s = ep_data;
     if (q < kNB) {
-      s_xy[b2][q] = p_xy;
+      s_xy[b3][q] = p_xy;
       s_co[b3][q] = p_co;
       s_rgb[b2][q] = p_rgb;
       s_box[b2][q] = make_int4(p_box.x, p_box.y, p_box.z, p_box.w);
@@ -812,7 +816,6 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
       s_grb[wave][ks][1][lane] = l;
     }
   } else {
-    for (int e = q; e < 3 * 12 * kNB; e += NT) (&s_red[0][0][0])[e] = 0.f;
     stage(0);
     load_data();
     load_ids(2);
@@ -855,97 +858,130 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
             S[8 * (v >> 2) + (v & 3)] = __uint_as_float(r[0]);
             S[8 * (v >> 2) + 4 + (v & 3)] = __uint_as_float(r[1]);
           }
+          // pairs at list positions >= min(last, pos0 + nb) are not walked for this pixel
+          const int lim = min(last, pos0 + nb) - pos0;
           constexpr int GR = WS_GR;
 #pragma unroll
-          for (int gi = kNB / GR - 1; gi >= 0; --gi) {
-            float al[GR], Gv[GR], dxv[GR], dyv[GR];
-            bool ct[GR], unc[GR];
+          for (int h = 1; h >= 0; --h) {
+            float xh[16];   // X = G dL/dalpha of the half's Gaussians at this pixel
 #pragma unroll
-            for (int u = 0; u < GR; ++u) {
-              const int i = gi * GR + u;
-              const float2 m = s_xy[b2][i];
-              const float4 co = s_co[b3][i];
-              const int4 b = s_box[b2][i];
-              const float dx = fpx - m.x, dy = fpy - m.y;
-              const float qq = __builtin_fmaf(co.x * dx, dx, __builtin_fmaf(co.z * dy, dy, 2.0f * co.y * dx * dy));
-              const bool inb = (px >= b.x) & (px <= b.z) & (py >= b.y) & (py <= b.w);
-              const float G = __expf(-0.5f * qq);
-              const float opG = co.w * G;
-              const float alpha = fminf(kAlphaMax, opG);
-              ct[u] = (i < nb) & (pos0 + i < last) & inb & (qq <= kQMax) & (alpha >= kAlphaMin);
-              unc[u] = opG <= kAlphaMax;
-              al[u] = alpha;
-              Gv[u] = G;
-              dxv[u] = dx;
-              dyv[u] = dy;
-            }
-            float wg[GR], xg[GR];
+            for (int gq = 16 / GR - 1; gq >= 0; --gq) {
+              const int gi = (16 / GR) * h + gq;
+              // alpha, 1 / (1 - alpha) and G of GR pairs, independent of each other;
+              // a pair that is not walked gets alpha 0 (and G 0), which leaves the
+              // chain below unchanged without per-pair selects
+              float al[GR], inv[GR], gx[GR];
 #pragma unroll
-            for (int u = GR - 1; u >= 0; --u) {
-              const int i = gi * GR + u;
-              const float4 c = s_rgb[b2][i];
-              const float sv = S[i] + ((gr0 * c.x + gr1 * c.y) + gr2 * c.z);
-              const float inv_om = __builtin_amdgcn_rcpf(1.0f - al[u]);
-              const float Tn = T * inv_om;
-              const float w = al[u] * Tn;
-              const float da = Tn * sv - acc * inv_om;
-              T = ct[u] ? Tn : T;
-              acc = ct[u] ? __builtin_fmaf(w, sv, acc) : acc;
-              wg[u] = ct[u] ? w : 0.f;
-              xg[u] = (ct[u] & unc[u]) ? Gv[u] * da : 0.f;
-            }
-#pragma unroll
-            for (int u = 0; u < GR; ++u) {
-              __bf16 h, l;
-              split2(wg[u], h, l);
-              s_w[b2][wave][0][gi * GR + u][lane] = h;
-              s_w[b2][wave][1][gi * GR + u][lane] = l;
-            }
-            float red[GR / 2][3];
-            bool anyp[GR / 2];
-#pragma unroll
-            for (int up = 0; up < GR / 2; ++up) {
-              const int u0 = 2 * up;
-              anyp[up] = __ballot(ct[u0] | ct[u0 + 1]) != 0ull;
-              red[up][0] = red[up][1] = red[up][2] = 0.f;
-              if (!anyp[up]) continue;
-              float vals[12];
-#pragma unroll
-              for (int hf = 0; hf < 2; ++hf) {
-                const int u = u0 + hf;
-                const float X = xg[u];
-                const float Xdx = X * dxv[u], Xdy = X * dyv[u];
-                float* v = vals + 6 * hf;
-                v[0] = Xdx;
-                v[1] = Xdy;
-                v[2] = Xdx * dxv[u];
-                v[3] = Xdx * dyv[u];
-                v[4] = Xdy * dyv[u];
-                v[5] = X;
+              for (int u = 0; u < GR; ++u) {
+                const int i = gi * GR + u;
+                const float2 m = s_xy[b3][i];
+                const float4 co = s_co[b3][i];
+                const int4 b = s_box[b2][i];
+                const float dx = fpx - m.x, dy = fpy - m.y;
+                const float qq = __builtin_fmaf(co.x * dx, dx, __builtin_fmaf(co.z * dy, dy, 2.0f * co.y * dx * dy));
+                const bool inb = (px >= b.x) & (px <= b.z) & (py >= b.y) & (py <= b.w);
+                const float G = __expf(-0.5f * qq);
+                const float opG = co.w * G;
+                const float alpha = fminf(kAlphaMax, opG);
+                const bool ct = (i < lim) & inb & (qq <= kQMax) & (alpha >= kAlphaMin);
+                al[u] = ct ? alpha : 0.f;
+                inv[u] = __builtin_amdgcn_rcpf(1.0f - al[u]);
+                gx[u] = (ct & (opG <= kAlphaMax)) ? G : 0.f;
               }
-              float h6[6];
+              // back-to-front recovery of T and the running colour/feature sum
+              float wg[GR];
 #pragma unroll
-              for (int k = 0; k < 6; ++k) {
-                const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(vals[k]), __float_as_uint(vals[k + 6]),
-                                                                false, false);
-                h6[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+              for (int u = GR - 1; u >= 0; --u) {
+                const int i = gi * GR + u;
+                const float4 c = s_rgb[b2][i];
+                const float sv = S[i] + ((gr0 * c.x + gr1 * c.y) + gr2 * c.z);
+                const float Tn = T * inv[u];
+                const float w = al[u] * Tn;
+                const float da = Tn * sv - acc * inv[u];
+                T = Tn;
+                acc = __builtin_fmaf(w, sv, acc);
+                wg[u] = w;
+                xh[gq * GR + u] = gx[u] * da;
               }
 #pragma unroll
-              for (int k = 0; k < 3; ++k) {
-                const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(h6[k]), __float_as_uint(h6[k + 3]),
-                                                                false, false);
-                red[up][k] = row_sum16(__uint_as_float(r[0]) + __uint_as_float(r[1]));
+              for (int u = 0; u < GR; ++u) {
+                __bf16 wh, wl;
+                split2(wg[u], wh, wl);
+                s_w[b2][wave][0][gi * GR + u][lane] = wh;
+                s_w[b2][wave][1][gi * GR + u][lane] = wl;
               }
             }
-            if ((lane & 15) == 15) {
-              const int base = 3 * ((lane >> 4) & 1);
+            // six pixel moments of X per Gaussian of the half: lane l sums 16
+            // pixels (quarter l / 16 of the wave) of Gaussian l % 16 from LDS
 #pragma unroll
-              for (int up = 0; up < GR / 2; ++up)
-                if (anyp[up])
+            for (int g = 0; g < 16; ++g) s_xm[wave][g][lane] = xh[g];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int qr = lane >> 4;
+            const float* xr = &s_xm[wave][lane & 15][16 * qr];
+            float xv[16];
 #pragma unroll
-                  for (int k = 0; k < 3; ++k)
-                    atomicAdd(&s_red[b3][base + k][gi * GR + 2 * up + (lane >> 5)], red[up][k]);
+            for (int j4 = 0; j4 < 4; ++j4) {
+              const float4 v4 = *reinterpret_cast<const float4*>(xr + 4 * j4);
+              xv[4 * j4] = v4.x;
+              xv[4 * j4 + 1] = v4.y;
+              xv[4 * j4 + 2] = v4.z;
+              xv[4 * j4 + 3] = v4.w;
             }
+            // runs of 8 pixels: sums of X, j X, j^2 X (j = 0..7 along the run)
+            float r0[2], r1[2], r2[2];
+#pragma unroll
+            for (int rr = 0; rr < 2; ++rr) {
+              r0[rr] = r1[rr] = r2[rr] = 0.f;
+#pragma unroll
+              for (int j = 0; j < 8; ++j) {
+                const float x = xv[8 * rr + j];
+                r0[rr] += x;
+                r1[rr] = __builtin_fmaf((float)j, x, r1[rr]);
+                r2[rr] = __builtin_fmaf((float)(j * j), x, r2[rr]);
+              }
+            }
+            // pixel coordinates relative to the tile centre: the quarter starts at
+            // tile pixel p0; with tiles at least 16 wide it is part of one row,
+            // 8-wide tiles put its two runs on two rows
+            const int p0 = 64 * wave + 16 * qr;
+            const float hx = 0.5f - 0.5f * (float)a.tile_w, hy = 0.5f - 0.5f * (float)tile_h;
+            float mom[6];   // X, X lx, X ly, X lx^2, X lx ly, X ly^2
+            if (a.tile_w >= 16) {
+              const float x0 = (float)(p0 % a.tile_w) + hx, y0 = (float)(p0 / a.tile_w) + hy;
+              const float s0 = r0[0] + r0[1];
+              const float s1 = r1[0] + __builtin_fmaf(8.0f, r0[1], r1[1]);
+              const float s2 = r2[0] + __builtin_fmaf(16.0f, r1[1], __builtin_fmaf(64.0f, r0[1], r2[1]));
+              const float m10 = __builtin_fmaf(x0, s0, s1);
+              mom[0] = s0;
+              mom[1] = m10;
+              mom[2] = y0 * s0;
+              mom[3] = __builtin_fmaf(x0, __builtin_fmaf(x0, s0, 2.0f * s1), s2);
+              mom[4] = y0 * m10;
+              mom[5] = y0 * y0 * s0;
+            } else {
+              const float x0 = hx, ya = (float)(p0 / a.tile_w) + hy, yb = ya + 1.0f;
+              const float ma = __builtin_fmaf(x0, r0[0], r1[0]), mb = __builtin_fmaf(x0, r0[1], r1[1]);
+              mom[0] = r0[0] + r0[1];
+              mom[1] = ma + mb;
+              mom[2] = __builtin_fmaf(ya, r0[0], yb * r0[1]);
+              mom[3] = __builtin_fmaf(x0, __builtin_fmaf(x0, mom[0], 2.0f * (r1[0] + r1[1])), r2[0] + r2[1]);
+              mom[4] = __builtin_fmaf(ya, ma, yb * mb);
+              mom[5] = __builtin_fmaf(ya * ya, r0[0], yb * yb * r0[1]);
+            }
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+              mom[k] += __shfl_xor(mom[k], 16, 64);
+              mom[k] += __shfl_xor(mom[k], 32, 64);
+            }
+            if (lane < 16)
+#pragma unroll
+              for (int k = 0; k < 6; ++k) s_mom[b2][wave][k][16 * h + lane] = mom[k];
+            // s_xm is rewritten by the next half only after every lane has read it
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
           }
           // colour sums of the wave's pixels on the matrix cores
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -967,8 +1003,7 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
             }
             if ((lane & 15) < 3) {
 #pragma unroll
-              for (int v = 0; v < 4; ++v)
-                atomicAdd(&s_red[b3][6 + (lane & 15)][16 * mb + 4 * (lane >> 4) + v], cs[v]);
+              for (int v = 0; v < 4; ++v) s_col[b2][wave][lane & 15][16 * mb + 4 * (lane >> 4) + v] = cs[v];
             }
           }
         }
@@ -1009,46 +1044,56 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
             d[0] = d[1] = f32x16{};
           }
         }
-        // rest of the rows: the six walk sums turned into projected-space
-        // gradients with the Gaussian's conic and opacity, the colour sums
-        const int cstart = a.D & ~3;
-        const int nq = (a.RS - cstart) >> 2;
-        for (int t = q; t < nb * nq; t += NT) {
-          const int i = t / nq;
-          const int c0 = cstart + 4 * (t - i * nq);
+        // rest of the rows (one lane per Gaussian of the batch): the walker waves'
+        // pixel moments and colour sums are added up, moved from the tile centre
+        // to the Gaussian's centre and turned into projected-space gradients with
+        // its conic and opacity; the row is closed with zeros up to its stride
+        if (q < nb) {
+          const int i = q;
+          float P[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, Cc[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+          for (int w = 0; w < NW; ++w) {
+            if (!s_live[b2][w]) continue;
+#pragma unroll
+            for (int k2 = 0; k2 < 6; ++k2) P[k2] += s_mom[b2][w][k2][i];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Cc[c] += s_col[b2][w][c][i];
+          }
+          const float2 m = s_xy[b3][i];
           const float4 co = s_co[b3][i];
-          float v[4];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
+          // Gaussian centre relative to the tile centre; dx = lx - ux per pixel
+          const float ux = m.x - ((float)tx0 + 0.5f * (float)a.tile_w);
+          const float uy = m.y - ((float)ty0 + 0.5f * (float)tile_h);
+          const float S0 = __builtin_fmaf(-ux, P[0], P[1]);                          // sum X dx
+          const float S1 = __builtin_fmaf(-uy, P[0], P[2]);                          // sum X dy
+          const float S2 = __builtin_fmaf(-ux, __builtin_fmaf(-ux, P[0], 2.0f * P[1]), P[3]);   // X dx^2
+          const float S3 = __builtin_fmaf(-ux, __builtin_fmaf(-uy, P[0], P[2]), __builtin_fmaf(-uy, P[1], P[4]));
+          const float S4 = __builtin_fmaf(-uy, __builtin_fmaf(-uy, P[0], 2.0f * P[2]), P[5]);   // X dy^2
+          float v9[9];
+          v9[0] = co.w * (co.x * S0 + co.y * S1);
+          v9[1] = co.w * (co.y * S0 + co.z * S1);
+          v9[2] = -0.5f * co.w * S2;
+          v9[3] = -co.w * S3;
+          v9[4] = -0.5f * co.w * S4;
+          v9[5] = P[0];
+          v9[6] = Cc[0];
+          v9[7] = Cc[1];
+          v9[8] = Cc[2];
+          auto pick = [&](int t) {
             float x = 0.f;
-            switch (c0 + j - a.D) {
-              case 0: x = co.w * (co.x * s_red[b3][0][i] + co.y * s_red[b3][1][i]); break;
-              case 1: x = co.w * (co.y * s_red[b3][0][i] + co.z * s_red[b3][1][i]); break;
-              case 2: x = -0.5f * co.w * s_red[b3][2][i]; break;
-              case 3: x = -co.w * s_red[b3][3][i]; break;
-              case 4: x = -0.5f * co.w * s_red[b3][4][i]; break;
-              case 5: x = s_red[b3][5][i]; break;
-              case 6: x = s_red[b3][6][i]; break;
-              case 7: x = s_red[b3][7][i]; break;
-              case 8: x = s_red[b3][8][i]; break;
-              default: break;
-            }
-            v[j] = x;
-          }
-          float* dst = &a.rows[(row0 + pos0 + i) * a.RS + c0];
-          if (c0 >= a.D) {
-            *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
-          } else {
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-              if (c0 + j >= a.D) dst[j] = v[j];
-          }
+            for (int k2 = 0; k2 < 9; ++k2) x = t == k2 ? v9[k2] : x;
+            return x;
+          };
+          float* row = &a.rows[(row0 + pos0 + i) * a.RS];
+          int c = a.D;
+          for (; (c & 3) != 0 && c < a.RS; ++c) row[c] = pick(c - a.D);
+          for (; c < a.RS; c += 4)
+            *reinterpret_cast<float4*>(row + c) =
+                make_float4(pick(c - a.D), pick(c + 1 - a.D), pick(c + 2 - a.D), pick(c + 3 - a.D));
         }
         if (q < nb) a.rowidx[ep_w] = (uint32_t)(row0 + pos0 + q + 1);
       }
-      // the sums of batch it-2 were read in the previous step: clear them for batch it+1
-      if (it >= 2)
-        for (int e = q; e < 12 * kNB; e += NT) (&s_red[(it - 2) % 3][0][0])[e] = 0.f;
       ep_w = ep_s;
       if (it + 1 < nbatch) {
         stage(it + 1);
