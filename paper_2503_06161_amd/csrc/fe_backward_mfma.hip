@@ -633,7 +633,7 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
   const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
   const int64_t HW = (int64_t)a.W * a.H;
   // walkers: the upstream feature gradient of their pixel, all slices issued first
-  constexpr int GS = CB < (F32 ? 2 : 4) ? CB : (F32 ? 2 : 4);
+  constexpr int GS = CB < 2 ? CB : 2;
   float gv[GS][32];
   auto load_g = [&](int cb, float* dst) {
 #pragma unroll
@@ -863,7 +863,6 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
           constexpr int GR = WS_GR;
 #pragma unroll
           for (int h = 1; h >= 0; --h) {
-            float xh[16];   // X = G dL/dalpha of the half's Gaussians at this pixel
 #pragma unroll
             for (int gq = 16 / GR - 1; gq >= 0; --gq) {
               const int gi = (16 / GR) * h + gq;
@@ -901,7 +900,7 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
                 T = Tn;
                 acc = __builtin_fmaf(w, sv, acc);
                 wg[u] = w;
-                xh[gq * GR + u] = gx[u] * da;
+                s_xm[wave][gq * GR + u][lane] = gx[u] * da;   // X = G dL/dalpha at this pixel
               }
 #pragma unroll
               for (int u = 0; u < GR; ++u) {
@@ -913,8 +912,6 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
             }
             // six pixel moments of X per Gaussian of the half: lane l sums 16
             // pixels (quarter l / 16 of the wave) of Gaussian l % 16 from LDS
-#pragma unroll
-            for (int g = 0; g < 16; ++g) s_xm[wave][g][lane] = xh[g];
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1019,7 +1016,9 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
         const int k = it - 1;
         const int b2 = k & 1, b3 = k % 3;
         const int pos0 = bpos0(k), nb = bnb(k);
-        f32x16 d[2] = {f32x16{}, f32x16{}};
+        // one accumulator (a dependent MFMA chain) keeps registers for the
+        // upstream-gradient operand, which holds 128 VGPRs at D = 128
+        f32x16 d = f32x16{};
 #pragma unroll
         for (int u = 0; u < CB; ++u) {
           const int chunk = unit_chunk(u);
@@ -1029,9 +1028,9 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
               const int kp = 16 * s + 8 * (lane >> 5);
               const bf16x8 wh = *reinterpret_cast<const bf16x8*>(&s_w[b2][chunk][0][lane & 31][kp]);
               const bf16x8 wl = *reinterpret_cast<const bf16x8*>(&s_w[b2][chunk][1][lane & 31][kp]);
-              d[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh, g2(u, s, 0), d[0], 0, 0, 0);
-              d[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh, g2(u, s, 1), d[1], 0, 0, 0);
-              d[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wl, g2(u, s, 0), d[0], 0, 0, 0);
+              d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh, g2(u, s, 0), d, 0, 0, 0);
+              d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh, g2(u, s, 1), d, 0, 0, 0);
+              d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wl, g2(u, s, 0), d, 0, 0, 0);
             }
           }
           if (u % NW == NW - 1) {   // the channel block is complete
@@ -1039,9 +1038,9 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
               const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-              if (i < nb && c < a.D) a.rows[(row0 + pos0 + i) * a.RS + c] = d[0][v] + d[1][v];
+              if (i < nb && c < a.D) a.rows[(row0 + pos0 + i) * a.RS + c] = d[v];
             }
-            d[0] = d[1] = f32x16{};
+            d = f32x16{};
           }
         }
         // rest of the rows (one lane per Gaussian of the batch): the walker waves'
