@@ -160,11 +160,40 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(RadixArgs a) {
   if (base >= n) return;   // chunks past the item count are never read
   for (int b = threadIdx.x; b < BINS; b += kSortThreads) h[b] = 0;
   __syncthreads();
+  // each thread counts kSortItems consecutive keys and adds runs of equal
+  // digits with one LDS atomic each: emitted tile ids come in runs (a
+  // Gaussian's tiles, neighbouring Gaussians), and one atomic per key would
+  // make the lanes of a wave collide on the same bin
+  const int64_t i0 = base + (int64_t)threadIdx.x * kSortItems;
+  uint32_t kv[kSortItems];
+  if (i0 + kSortItems <= n) {
+    const uint4* p4 = reinterpret_cast<const uint4*>(a.keys_in + i0);
+#pragma unroll
+    for (int k = 0; k < kSortItems / 4; ++k) {
+      const uint4 v = p4[k];
+      kv[4 * k] = v.x;
+      kv[4 * k + 1] = v.y;
+      kv[4 * k + 2] = v.z;
+      kv[4 * k + 3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) kv[k] = i0 + k < n ? a.keys_in[i0 + k] : 0u;
+  }
+  const int valid = (int)max((int64_t)0, min((int64_t)kSortItems, n - i0));
+  uint32_t prev = 0u, run = 0u;
 #pragma unroll
   for (int k = 0; k < kSortItems; ++k) {
-    const int64_t i = base + (int64_t)k * kSortThreads + threadIdx.x;
-    if (i < n) atomicAdd(&h[(a.keys_in[i] >> a.shift) & (BINS - 1)], 1u);
+    if (k >= valid) break;
+    const uint32_t d = (kv[k] >> a.shift) & (BINS - 1);
+    if (run != 0u && d != prev) {
+      atomicAdd(&h[prev], run);
+      run = 0u;
+    }
+    prev = d;
+    ++run;
   }
+  if (run != 0u) atomicAdd(&h[prev], run);
   __syncthreads();
   for (int b = threadIdx.x; b < BINS; b += kSortThreads) {
     const uint32_t c = h[b];
