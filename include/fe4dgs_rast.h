@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define FE4DGS_ABI_VERSION 1
+#define FE4DGS_ABI_VERSION 2
 
 typedef enum fe_status {
   FE_OK = 0,
@@ -108,7 +108,7 @@ typedef struct fe_config {
 
 /* Stages recorded by fe_config.stage_events. */
 #define FE_STAGE_PROJECT 0          /* projection forward                         */
-#define FE_STAGE_SORT 1             /* depth sort, emit, tile sort, ranges        */
+#define FE_STAGE_SORT 1             /* tile binning and per-tile depth sort       */
 #define FE_STAGE_COMPOSITE 2        /* per-tile blending forward                  */
 #define FE_STAGE_COMPOSITE_BWD 3    /* per-tile blending backward                 */
 #define FE_STAGE_REDUCE 4           /* per-Gaussian reduction of tile partials    */
@@ -167,20 +167,19 @@ typedef struct fe_report {
 } fe_report;
 
 /* Byte offsets of the regions of a forward state buffer (for tests and
- * tools; every offset is 256-byte aligned).  Sorted arrays hold
- * report.keys_needed valid entries (at most key_capacity). */
+ * tools; every offset is 256-byte aligned).  The sorted array holds
+ * report.keys_needed valid entries (at most key_capacity): the lists of the
+ * tiles one after another, tile t at [ranges[t].x, ranges[t].y), each in
+ * ascending (float32 depth bits, Gaussian index) order. */
 typedef struct fe_state_layout {
   size_t total;
   size_t xy;                     /* float2 [n]    pixel position (u, v)         */
   size_t conic_opacity;          /* float4 [n]    conic (A, B, C), opacity      */
   size_t rgb;                    /* float4 [n]    colour (r, g, b, 0)           */
   size_t box;                    /* int16x4 [n]   pixel box (i0, j0, i1, j1)    */
-  size_t depth_key;              /* uint32 [n]    float32 depth bits in ascending
-                                                  order (culled: 0xFFFFFFFF)    */
-  size_t depth_order;            /* uint32 [n]    Gaussian indices in that order
-                                                  (stable: ties by index)       */
+  size_t depth_key;              /* uint32 [n]    float32 depth bits of each
+                                                  Gaussian (culled: 0xFFFFFFFF) */
   size_t tile_count;             /* uint32 [n]    tiles touched                 */
-  size_t sorted_tile;            /* uint32 [cap]  tile id of each sorted key    */
   size_t sorted_gauss;           /* uint32 [cap]  Gaussian index of each key    */
   size_t ranges;                 /* uint32x2 [tiles] [start, end) per tile      */
   size_t report;                 /* device report words                         */

@@ -20,44 +20,29 @@ bool compute_layout(const fe_config* cfg, const fe_camera* cam, int64_t n, Layou
   L->tiles_x = ceil_div(cam->width, cfg->tile_w);
   L->tiles_y = ceil_div(cam->height, cfg->tile_h);
   L->tiles = L->tiles_x * L->tiles_y;
-  L->nchunks_n = ceil_div(n, kSortChunk);
-  L->nchunks_k = ceil_div(L->cap, kSortChunk);
-  L->nscan_blocks = ceil_div(n, kScanChunk);
-  int bits = 0;
-  while ((1ll << bits) < (int64_t)L->tiles) ++bits;
-  // 8-bit passes on the tile id: with 256 bins a chunk of 2048 keys scatters
-  // into runs long enough to write whole cache lines, and its histogram row
-  // stays small (an 11-bit digit was measured slower: its 2048-bin rows are
-  // as large as the chunks and every write is an isolated 4 bytes)
-  L->tile_passes = (bits + 7) / 8;
-  L->tile_bits = 8;
+  L->nblk = ceil_div(n, kBinChunk);
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;
     o = align256(o + bytes);
     return at;
   };
-  // zeroed at the start of every forward: report, radix totals, ranges
+  // zeroed at the start of every forward: report, tile counts, ranges
   L->report = take(sizeof(unsigned long long) * 2 * kRepWords);
-  L->totals = take(sizeof(uint32_t) * kRadixBinsMax * (3 + L->tile_passes));
+  L->tile_cnt = take(sizeof(uint32_t) * (size_t)L->tiles);
   L->ranges = take(sizeof(uint2) * (size_t)L->tiles);
   L->xy = take(sizeof(float2) * n);
   L->conic_o = take(sizeof(float4) * n);
   L->rgb = take(sizeof(float4) * n);
   L->box = take(sizeof(short4) * n);
-  L->dkey_a = take(4 * n);
-  L->dkey_b = take(4 * n);
-  L->didx_a = take(4 * n);
-  L->didx_b = take(4 * n);
+  L->dkey = take(4 * n);
   L->count = take(4 * n);
-  L->offsets = take(4 * n);
-  L->scan_sums = take(4 * (size_t)(L->nscan_blocks + 1));
-  L->hist_n = take(4 * (size_t)kRadixBinsMax * L->nchunks_n);
-  L->tile_a = take(4 * (size_t)L->cap);
-  L->gauss_a = take(4 * (size_t)L->cap);
-  L->tile_b = take(4 * (size_t)L->cap);
-  L->gauss_b = take(4 * (size_t)L->cap);
-  L->hist_k = take(4 * (size_t)(1 << L->tile_bits) * L->nchunks_k);
+  L->rel = take(L->tiles <= kBinLdsTiles ? 4 * (size_t)L->nblk * (size_t)L->tiles : 0);
+  L->blk_sum = take(4 * (size_t)L->nblk);
+  L->blk_off = take(4 * (size_t)L->nblk);
+  L->keys = take(8 * (size_t)L->cap);
+  L->keys_b = take(8 * (size_t)L->cap);
+  L->gauss = take(4 * (size_t)L->cap);
   L->tile_maxlast = take(4 * (size_t)L->tiles);
   L->gofe = take(4 * (size_t)L->cap);
   L->epos = take(4 * (size_t)L->cap);
@@ -73,20 +58,15 @@ StateView make_view(const Layout& L, void* base) {
   v.conic_o = reinterpret_cast<float4*>(b + L.conic_o);
   v.rgb = reinterpret_cast<float4*>(b + L.rgb);
   v.box = reinterpret_cast<short4*>(b + L.box);
-  v.dkey_a = reinterpret_cast<uint32_t*>(b + L.dkey_a);
-  v.dkey_b = reinterpret_cast<uint32_t*>(b + L.dkey_b);
-  v.didx_a = reinterpret_cast<uint32_t*>(b + L.didx_a);
-  v.didx_b = reinterpret_cast<uint32_t*>(b + L.didx_b);
+  v.dkey = reinterpret_cast<uint32_t*>(b + L.dkey);
   v.count = reinterpret_cast<uint32_t*>(b + L.count);
-  v.offsets = reinterpret_cast<uint32_t*>(b + L.offsets);
-  v.scan_sums = reinterpret_cast<uint32_t*>(b + L.scan_sums);
-  v.hist_n = reinterpret_cast<uint32_t*>(b + L.hist_n);
-  v.tile_a = reinterpret_cast<uint32_t*>(b + L.tile_a);
-  v.gauss_a = reinterpret_cast<uint32_t*>(b + L.gauss_a);
-  v.tile_b = reinterpret_cast<uint32_t*>(b + L.tile_b);
-  v.gauss_b = reinterpret_cast<uint32_t*>(b + L.gauss_b);
-  v.hist_k = reinterpret_cast<uint32_t*>(b + L.hist_k);
-  v.totals = reinterpret_cast<uint32_t*>(b + L.totals);
+  v.tile_cnt = reinterpret_cast<uint32_t*>(b + L.tile_cnt);
+  v.rel = reinterpret_cast<uint32_t*>(b + L.rel);
+  v.blk_sum = reinterpret_cast<uint32_t*>(b + L.blk_sum);
+  v.blk_off = reinterpret_cast<uint32_t*>(b + L.blk_off);
+  v.keys = reinterpret_cast<unsigned long long*>(b + L.keys);
+  v.keys_b = reinterpret_cast<unsigned long long*>(b + L.keys_b);
+  v.gauss = reinterpret_cast<uint32_t*>(b + L.gauss);
   v.ranges = reinterpret_cast<uint2*>(b + L.ranges);
   v.report = reinterpret_cast<unsigned long long*>(b + L.report);
   v.tile_maxlast = reinterpret_cast<uint32_t*>(b + L.tile_maxlast);
@@ -98,11 +78,7 @@ StateView make_view(const Layout& L, void* base) {
   v.tiles_x = L.tiles_x;
   v.tiles_y = L.tiles_y;
   v.tiles = L.tiles;
-  v.nchunks_n = L.nchunks_n;
-  v.nchunks_k = L.nchunks_k;
-  v.nscan_blocks = L.nscan_blocks;
-  v.tile_passes = L.tile_passes;
-  v.tile_bits = L.tile_bits;
+  v.nblk = L.nblk;
   return v;
 }
 
@@ -348,11 +324,9 @@ fe_status fe_state_layout_get(const fe_config* cfg, const fe_camera* cam, int64_
   out->conic_opacity = L.conic_o;
   out->rgb = L.rgb;
   out->box = L.box;
-  out->depth_key = L.dkey_b;
-  out->depth_order = L.didx_b;
+  out->depth_key = L.dkey;
   out->tile_count = L.count;
-  out->sorted_tile = L.tile_a;
-  out->sorted_gauss = L.gauss_a;
+  out->sorted_gauss = L.gauss;
   out->ranges = L.ranges;
   out->report = L.report;
   return FE_OK;

@@ -53,7 +53,7 @@ struct BwdArgs {
   float* rows;
   int64_t row_cap;
   uint32_t* rowidx;          // [cap] 1 + row of each walked pair, by emit position (0: not walked)
-  const uint32_t* epos;      // [cap] emit position of each sorted pair (NULL: identity)
+  const uint32_t* epos;      // [cap] emit position of each sorted pair
   unsigned long long* report;
   float bg[3];
   int32_t W, H, tile_w, tiles_x, D, RS;
@@ -185,7 +185,7 @@ __device__ __forceinline__ void bwd_mfma_tile(const BwdArgs& a, const int tile) 
     const int r0 = r1 > kNB ? r1 - kNB : 0;
     const bool ok = r0 + si < r1;
     id_n = ok ? a.gauss[rg.x + r0 + si] : 0xFFFFFFFFu;
-    ep_n = (ok && (int)threadIdx.x < kNB) ? (a.epos ? a.epos[rg.x + r0 + si] : rg.x + r0 + si) : 0u;
+    ep_n = (ok && (int)threadIdx.x < kNB) ? a.epos[rg.x + r0 + si] : 0u;
   };
   auto load_data = [&]() {
 #pragma unroll
@@ -678,7 +678,7 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
     const int r0 = bpos0(k), r1 = r0 + bnb(k);
     const bool ok = k < nbatch && r0 + si < r1;
     id_n = ok ? a.gauss[rg.x + r0 + si] : 0xFFFFFFFFu;
-    ep_n = (ok && q < kNB) ? (a.epos ? a.epos[rg.x + r0 + si] : rg.x + r0 + si) : 0u;
+    ep_n = (ok && q < kNB) ? a.epos[rg.x + r0 + si] : 0u;
   };
   auto load_data = [&]() {
 #pragma unroll
@@ -1291,7 +1291,7 @@ static BwdArgs make_bwd_args(const fe_config* cfg, const fe_camera* cam, const f
                               const uint32_t* row_base, float* rows, int64_t row_cap, uint32_t* rowidx) {
   BwdArgs a{};
   a.ranges = v.ranges;
-  a.gauss = v.gauss_a;
+  a.gauss = v.gauss;
   a.xy = v.xy;
   a.conic_o = v.conic_o;
   a.rgb = v.rgb;
@@ -1306,7 +1306,7 @@ static BwdArgs make_bwd_args(const fe_config* cfg, const fe_camera* cam, const f
   a.rows = rows;
   a.row_cap = row_cap;
   a.rowidx = rowidx;
-  a.epos = v.tile_passes > 0 ? v.epos : nullptr;
+  a.epos = v.epos;
   a.report = v.report;
   for (int k = 0; k < 3; ++k) a.bg[k] = cfg->bg_rgb[k];
   a.W = cam->width;

@@ -16,11 +16,14 @@ constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kTStop = 1e-4f;
 constexpr float kQMax = 9.0f;
 
-// Radix passes: 8- or 11-bit digits, 256 threads x 8 items per chunk.
-constexpr int kRadixBinsMax = 2048;
-constexpr int kSortThreads = 256;
-constexpr int kSortItems = 8;
-constexpr int kSortChunk = kSortThreads * kSortItems;   // 2048
+// Binning: 256 threads x 8 Gaussians per workgroup; per-tile counters in
+// LDS up to kBinLdsTiles tiles; one workgroup of kBinOffThreads for the
+// offsets.
+constexpr int kBinThreads = 256;
+constexpr int kBinItems = 8;
+constexpr int kBinChunk = kBinThreads * kBinItems;      // 2048
+constexpr int kBinLdsTiles = 12288;
+constexpr int kBinOffThreads = 1024;
 
 // Exclusive scan: 256 threads x 8 items per block.
 constexpr int kScanThreads = 256;
@@ -37,23 +40,18 @@ struct StateView {
   float4* conic_o;
   float4* rgb;
   short4* box;
-  uint32_t* dkey_a;
-  uint32_t* dkey_b;
-  uint32_t* didx_a;
-  uint32_t* didx_b;
-  uint32_t* count;
-  uint32_t* offsets;
-  uint32_t* scan_sums;
-  uint32_t* hist_n;
-  uint32_t* tile_a;
-  uint32_t* gauss_a;
-  uint32_t* tile_b;
-  uint32_t* gauss_b;
-  uint32_t* hist_k;
-  uint32_t* totals;     // [kRadixBinsMax * (3 + tile_passes)]
+  uint32_t* dkey;           // [n] float32 depth bits (culled: all ones)
+  uint32_t* count;          // [n] tiles touched
+  uint32_t* tile_cnt;       // [tiles] pairs per tile, then placement cursors
+  uint32_t* rel;            // [nblk][tiles] (LDS binning only)
+  uint32_t* blk_sum;        // [nblk]
+  uint32_t* blk_off;        // [nblk]
+  unsigned long long* keys;     // [cap] depth bits << 32 | emit position
+  unsigned long long* keys_b;   // [cap] merge buffer of the per-tile sort
+  uint32_t* gauss;          // [cap] Gaussian index of each sorted pair
   uint2* ranges;
   uint32_t* tile_maxlast;   // [tiles] largest n_contrib per tile (compositing walk length)
-  uint32_t* gofe;           // [cap] Gaussian of each emitted pair (emit order)
+  uint32_t* gofe;           // [cap] Gaussian of each emit position
   uint32_t* epos;           // [cap] emit position of each sorted pair
   uint32_t* eoff;           // [n] first emit position of each Gaussian
   unsigned long long* report;
@@ -61,17 +59,15 @@ struct StateView {
   int64_t n;
   int64_t cap;
   int32_t tiles_x, tiles_y, tiles;
-  int32_t nchunks_n, nchunks_k, nscan_blocks;
-  int32_t tile_passes;
-  int32_t tile_bits;    // digit width of the tile passes (8 or 11)
+  int32_t nblk;             // binning workgroups (kBinChunk Gaussians each)
 };
 
 struct Layout {
   size_t total;
-  size_t xy, conic_o, rgb, box, dkey_a, dkey_b, didx_a, didx_b, count, offsets, scan_sums, hist_n;
-  size_t tile_a, gauss_a, tile_b, gauss_b, hist_k, totals, ranges, report, tile_maxlast, gofe, epos, eoff;
+  size_t report, tile_cnt, ranges, xy, conic_o, rgb, box, dkey, count, rel, blk_sum, blk_off;
+  size_t keys, keys_b, gauss, tile_maxlast, gofe, epos, eoff;
   int64_t n, cap;
-  int32_t tiles_x, tiles_y, tiles, nchunks_n, nchunks_k, nscan_blocks, tile_passes, tile_bits;
+  int32_t tiles_x, tiles_y, tiles, nblk;
 };
 
 // Host helpers (fe_api.cpp).

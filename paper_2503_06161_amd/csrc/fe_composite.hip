@@ -321,7 +321,7 @@ hipError_t dispatch_d(int D, int nt, const CompArgs& a, int tiles, hipStream_t s
 CompArgs make_args(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g, const StateView& v) {
   CompArgs a{};
   a.ranges = v.ranges;
-  a.gauss = v.gauss_a;
+  a.gauss = v.gauss;
   a.xy = v.xy;
   a.conic_o = v.conic_o;
   a.rgb = v.rgb;

@@ -679,7 +679,7 @@ static MfmaArgs make_args(const fe_config* cfg, const fe_camera* cam, const fe_g
                           const fe_images* out) {
   MfmaArgs a{};
   a.ranges = v.ranges;
-  a.gauss = v.gauss_a;
+  a.gauss = v.gauss;
   a.xy = v.xy;
   a.conic_o = v.conic_o;
   a.rgb = v.rgb;

@@ -318,7 +318,7 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(ProjArgs a) {
     a.v.conic_o[i] = co;
     a.v.rgb[i] = rgb;
     a.v.box[i] = box;
-    a.v.dkey_a[i] = dkey;
+    a.v.dkey[i] = dkey;
     a.v.count[i] = count;
   }
   // wave-aggregated report counters

@@ -68,7 +68,7 @@ class fe_report(C.Structure):
 
 class fe_state_layout(C.Structure):
     _fields_ = [(k, C.c_size_t) for k in ("total", "xy", "conic_opacity", "rgb", "box", "depth_key",
-                                          "depth_order", "tile_count", "sorted_tile", "sorted_gauss", "ranges", "report")]
+                                          "tile_count", "sorted_gauss", "ranges", "report")]
 
 
 EXPORTS = {
@@ -111,7 +111,7 @@ def load_library(path: str = LIB_PATH):
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
-    if lib.fe_abi_version() != 1:
+    if lib.fe_abi_version() != 2:
         raise ImportError("libfe4dgs_rast.so ABI version mismatch")
     _lib = lib
     return lib

@@ -1,7 +1,7 @@
 """Edge cases of the HIP path through the C ABI: empty and culled inputs,
 non-finite parameters, key and row capacity overflow (reported, never
-silently truncated), images smaller than a tile, a single tile (no tile-sort
-pass), and ragged sizes; each is compared with the FP64 oracle."""
+silently truncated), images smaller than a tile, a single tile, and ragged
+sizes; each is compared with the FP64 oracle."""
 import numpy as np
 import pytest
 import torch
@@ -92,7 +92,7 @@ def test_row_overflow_is_reported():
 @pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("wh", [(5, 3), (16, 16), (21, 9), (70, 33)])
 def test_ragged_and_tiny_images(wh, variant):
-    # images smaller than one tile, exactly one tile (no tile-sort pass), and ragged tails
+    # images smaller than one tile, exactly one tile, and ragged tails
     w, h = wh
     say("image", wh, "variant", variant)
     sc = _small(n=400, seed=11, grads=True)
