@@ -16,12 +16,12 @@ constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kTStop = 1e-4f;
 constexpr float kQMax = 9.0f;
 
-// Binning: 256 threads x 8 Gaussians per workgroup; per-tile counters in
+// Binning: 256 threads x 4 Gaussians per workgroup; per-tile counters in
 // LDS up to kBinLdsTiles tiles; one workgroup of kBinOffThreads for the
 // offsets.
 constexpr int kBinThreads = 256;
-constexpr int kBinItems = 8;
-constexpr int kBinChunk = kBinThreads * kBinItems;      // 2048
+constexpr int kBinItems = 4;
+constexpr int kBinChunk = kBinThreads * kBinItems;      // 1024
 constexpr int kBinLdsTiles = 12288;
 constexpr int kBinOffThreads = 1024;
 

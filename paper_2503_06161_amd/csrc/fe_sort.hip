@@ -3,7 +3,7 @@
 // touches, and a tile blends its list front to back).
 //
 // Order of work (integer only):
-//   1. count: a workgroup takes 2048 consecutive Gaussians, counts the pairs
+//   1. count: a workgroup takes 1024 consecutive Gaussians, counts the pairs
 //      it adds to every tile in LDS and reserves its share of each tile it
 //      touches with one global atomic; it also sums its Gaussians' pair
 //      counts;
@@ -15,8 +15,10 @@
 //      position (the exclusive prefix of the pair counts in index order)
 //      plus t's row-major place in g's tile rectangle; the key goes to a free
 //      slot of t's segment and gofe[e] = g;
-//   4. sort: one workgroup per tile merge-sorts its segment and writes the
-//      Gaussian index and the emit position of every sorted pair.
+//   4. sort: one workgroup per tile sorts its segment (a counting sort on
+//      depth buckets and each key's rank inside its bucket, or a merge sort
+//      when buckets are crowded or the list is long) and writes the Gaussian
+//      index and the emit position of every sorted pair.
 // A tile holds at most one pair per Gaussian and emit positions increase
 // with the Gaussian index, so ascending keys are ascending (depth bits,
 // index): the order of the keys (tile, depth, index) within each tile.  The
@@ -134,44 +136,115 @@ struct BinArgs {
   int32_t tiles, tiles_x, tile_w, tile_h, nblk;
 };
 
+// The Gaussians of a binning workgroup in LDS: exclusive prefix of their
+// pair counts (entry kBinChunk holds the total) and their tile rectangles
+// (x0 | x1 << 16, y0 | y1 << 16).  Returns the workgroup's pair total.
+__device__ __forceinline__ uint32_t bin_stage(const BinArgs& a, uint32_t* s_off, uint32_t* s_rx, uint32_t* s_ry,
+                                              uint32_t* s_warp, uint32_t (&c)[kBinItems], int chunk) {
+  const int64_t g0 = (int64_t)chunk * kBinChunk + (int64_t)threadIdx.x * kBinItems;
+  uint32_t pre[kBinItems], sum = 0;
+#pragma unroll
+  for (int k = 0; k < kBinItems; ++k) {
+    c[k] = g0 + k < a.n ? a.count[g0 + k] : 0u;
+    pre[k] = sum;
+    sum += c[k];
+  }
+  uint32_t total;
+  const uint32_t off = block_exclusive_scan<kBinThreads / 64>(sum, s_warp, total);
+  const int j0 = (int)threadIdx.x * kBinItems;
+#pragma unroll
+  for (int k = 0; k < kBinItems; ++k) {
+    s_off[j0 + k] = off + pre[k];
+    uint32_t rx = 0u, ry = 0u;
+    if (c[k]) {
+      const short4 b = a.box[g0 + k];
+      rx = (uint32_t)(b.x / a.tile_w) | ((uint32_t)(b.z / a.tile_w) << 16);
+      ry = (uint32_t)(b.y / a.tile_h) | ((uint32_t)(b.w / a.tile_h) << 16);
+    }
+    s_rx[j0 + k] = rx;
+    s_ry[j0 + k] = ry;
+  }
+  if (threadIdx.x == 0) s_off[kBinChunk] = total;
+  __syncthreads();
+  return total;
+}
+
+// Every lane takes an equal run of the workgroup's pairs (in emit order) and
+// calls f(Gaussian slot, tile, pair index) for each, so that large and small
+// Gaussians cost the same per pair.
+template <class F>
+__device__ __forceinline__ void bin_walk(const uint32_t* s_off, const uint32_t* s_rx, const uint32_t* s_ry,
+                                         uint32_t total, int tiles_x, F&& f) {
+  const uint32_t q0 = (uint32_t)(((uint64_t)total * threadIdx.x) / kBinThreads);
+  const uint32_t q1 = (uint32_t)(((uint64_t)total * (threadIdx.x + 1)) / kBinThreads);
+  if (q0 >= q1) return;
+  // the last Gaussian whose prefix is <= q0 holds pair q0 (one without pairs
+  // shares its prefix with the next)
+  int lo = 0, hi = kBinChunk;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (s_off[mid] <= q0) lo = mid; else hi = mid;
+  }
+  int j = lo;
+  const uint32_t li = q0 - s_off[j];
+  uint32_t rx = s_rx[j], ry = s_ry[j];
+  int tx0 = (int)(rx & 0xFFFFu), tx1 = (int)(rx >> 16), ty1 = (int)(ry >> 16);
+  const int w = tx1 - tx0 + 1;
+  int ty = (int)(ry & 0xFFFFu) + (int)(li / (uint32_t)w);
+  int tx = tx0 + (int)(li % (uint32_t)w);
+  for (uint32_t q = q0; q < q1; ++q) {
+    f(j, ty * tiles_x + tx, q);
+    if (++tx > tx1) {
+      ++ty;
+      if (ty > ty1 && q + 1 < q1) {
+        do { ++j; } while (s_off[j + 1] == s_off[j]);
+        rx = s_rx[j];
+        ry = s_ry[j];
+        tx0 = (int)(rx & 0xFFFFu);
+        tx1 = (int)(rx >> 16);
+        ty = (int)(ry & 0xFFFFu);
+        ty1 = (int)(ry >> 16);
+      }
+      tx = tx0;
+    }
+  }
+}
+
 // Step 1.  kLds: per-tile counters in LDS (dynamic, 4 bytes per tile) and one
 // global atomic per touched tile; otherwise one global atomic per pair.
 template <bool kLds>
 __global__ __launch_bounds__(kBinThreads) void bin_count_kernel(BinArgs a) {
   extern __shared__ uint32_t s_tile[];
+  __shared__ uint32_t s_off[kBinChunk + 1], s_rx[kBinChunk], s_ry[kBinChunk];
   __shared__ uint32_t s_warp[kBinThreads / 64];
-  if constexpr (kLds) {
+  if constexpr (kLds)
     for (int t = threadIdx.x; t < a.tiles; t += kBinThreads) s_tile[t] = 0u;
-    __syncthreads();
-  }
-  const int64_t g0 = (int64_t)blockIdx.x * kBinChunk + (int64_t)threadIdx.x * kBinItems;
-  uint32_t sum = 0;
-  for (int k = 0; k < kBinItems; ++k) {
-    const int64_t g = g0 + k;
-    if (g >= a.n) break;
-    const uint32_t c = a.count[g];
-    if (c == 0u) continue;
-    sum += c;
-    const short4 b = a.box[g];
-    const int tx0 = b.x / a.tile_w, tx1 = b.z / a.tile_w;
-    const int ty0 = b.y / a.tile_h, ty1 = b.w / a.tile_h;
-    for (int ty = ty0; ty <= ty1; ++ty)
-      for (int tx = tx0; tx <= tx1; ++tx) {
-        const int t = ty * a.tiles_x + tx;
-        if constexpr (kLds)
-          atomicAdd(&s_tile[t], 1u);
-        else
-          atomicAdd(&a.tile_cnt[t], 1u);
-      }
-  }
-  uint32_t total;
-  block_exclusive_scan<kBinThreads / 64>(sum, s_warp, total);   // its barriers also order the LDS counts
+  uint32_t c[kBinItems];
+  const uint32_t total = bin_stage(a, s_off, s_rx, s_ry, s_warp, c, (int)blockIdx.x);   // its barriers order the zeroing
   if (threadIdx.x == 0) a.blk_sum[blockIdx.x] = total;
+  bin_walk(s_off, s_rx, s_ry, total, a.tiles_x, [&](int, int t, uint32_t) {
+    if constexpr (kLds)
+      atomicAdd(&s_tile[t], 1u);
+    else
+      atomicAdd(&a.tile_cnt[t], 1u);
+  });
   if constexpr (kLds) {
+    // eight reservations in flight per lane: each returns only after a trip
+    // to the device-wide atomic unit
+    __syncthreads();
     uint32_t* rel = a.rel + (size_t)blockIdx.x * a.tiles;
-    for (int t = threadIdx.x; t < a.tiles; t += kBinThreads) {
-      const uint32_t c = s_tile[t];
-      if (c) rel[t] = atomicAdd(&a.tile_cnt[t], c);
+    constexpr int kF = 8;
+    for (int base = 0; base < a.tiles; base += kBinThreads * kF) {
+      uint32_t cnt[kF], r[kF];
+#pragma unroll
+      for (int k = 0; k < kF; ++k) {
+        const int t = base + k * kBinThreads + (int)threadIdx.x;
+        cnt[k] = t < a.tiles ? s_tile[t] : 0u;
+        r[k] = cnt[k] ? atomicAdd(&a.tile_cnt[t], cnt[k]) : 0u;
+      }
+#pragma unroll
+      for (int k = 0; k < kF; ++k)
+        if (cnt[k]) rel[base + k * kBinThreads + (int)threadIdx.x] = r[k];
     }
   }
 }
@@ -245,6 +318,7 @@ __global__ __launch_bounds__(kBinOffThreads) void bin_offsets_kernel(BinArgs a) 
 template <bool kLds>
 __global__ __launch_bounds__(kBinThreads) void bin_place_kernel(BinArgs a) {
   extern __shared__ uint32_t s_next[];          // [tiles] next free slot of this workgroup (kLds)
+  __shared__ uint32_t s_off[kBinChunk + 1], s_rx[kBinChunk], s_ry[kBinChunk], s_dk[kBinChunk];
   __shared__ uint32_t s_warp[kBinThreads / 64];
   if (a.report[kRepKeys] > (unsigned long long)a.cap) return;
   if constexpr (kLds) {
@@ -253,39 +327,29 @@ __global__ __launch_bounds__(kBinThreads) void bin_place_kernel(BinArgs a) {
     const uint32_t* rel = a.rel + (size_t)blockIdx.x * a.tiles;
     for (int t = threadIdx.x; t < a.tiles; t += kBinThreads) s_next[t] = a.tile_cnt[t] + rel[t];
   }
-  const int64_t g0 = (int64_t)blockIdx.x * kBinChunk + (int64_t)threadIdx.x * kBinItems;
-  uint32_t c[kBinItems], sum = 0;
+  const int64_t gb = (int64_t)blockIdx.x * kBinChunk;
+  const int j0 = (int)threadIdx.x * kBinItems;
 #pragma unroll
-  for (int k = 0; k < kBinItems; ++k) {
-    c[k] = g0 + k < a.n ? a.count[g0 + k] : 0u;
-    sum += c[k];
-  }
-  uint32_t total;
-  uint32_t e = a.blk_off[blockIdx.x] + block_exclusive_scan<kBinThreads / 64>(sum, s_warp, total);
+  for (int k = 0; k < kBinItems; ++k) s_dk[j0 + k] = gb + j0 + k < a.n ? a.dkey[gb + j0 + k] : 0u;
+  uint32_t c[kBinItems];
+  const uint32_t total = bin_stage(a, s_off, s_rx, s_ry, s_warp, c, (int)blockIdx.x);
+  const uint32_t e0 = a.blk_off[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kBinItems; ++k)
+    if (c[k]) a.eoff[gb + j0 + k] = e0 + s_off[j0 + k];
   const uint32_t cap = (uint32_t)a.cap;
-  for (int k = 0; k < kBinItems; ++k) {
-    if (c[k] == 0u) continue;
-    const int64_t g = g0 + k;
-    a.eoff[g] = e;
-    const unsigned long long hi = (unsigned long long)a.dkey[g] << 32;
-    const short4 b = a.box[g];
-    const int tx0 = b.x / a.tile_w, tx1 = b.z / a.tile_w;
-    const int ty0 = b.y / a.tile_h, ty1 = b.w / a.tile_h;
-    for (int ty = ty0; ty <= ty1; ++ty)
-      for (int tx = tx0; tx <= tx1; ++tx) {
-        const int t = ty * a.tiles_x + tx;
-        uint32_t slot;
-        if constexpr (kLds)
-          slot = atomicAdd(&s_next[t], 1u);
-        else
-          slot = atomicAdd(&a.tile_cnt[t], 1u);
-        if (slot < cap && e < cap) {   // always true for consistent counts
-          a.keys[slot] = hi | e;
-          a.gofe[e] = (uint32_t)g;
-        }
-        ++e;
-      }
-  }
+  bin_walk(s_off, s_rx, s_ry, total, a.tiles_x, [&](int j, int t, uint32_t q) {
+    uint32_t slot;
+    if constexpr (kLds)
+      slot = atomicAdd(&s_next[t], 1u);
+    else
+      slot = atomicAdd(&a.tile_cnt[t], 1u);
+    const uint32_t e = e0 + q;
+    if (slot < cap && e < cap) {   // always true for consistent counts
+      a.keys[slot] = ((unsigned long long)s_dk[j] << 32) | e;
+      a.gofe[e] = (uint32_t)(gb + j);
+    }
+  });
 }
 
 // ---- step 4: per-tile merge sort ----
@@ -388,14 +452,122 @@ struct TileSortArgs {
   int64_t cap;
 };
 
+// Counting sort on depth buckets, then each key's exact place inside its
+// bucket by counting the smaller keys there.  The bucket of a key is
+// (depth bits - smallest depth bits) >> sh, with sh chosen so that the
+// tile's span of depth bits fills at most np/4 buckets: a bucket is a
+// contiguous range of keys, so the result is the sorted order for any
+// bucket sizes; a few keys per bucket keep the counting short.  Returns false
+// (the same in every lane, nothing written) when a bucket holds more than
+// kTsMaxBucket keys, e.g. when many depths are equal.  THREADS lanes hold
+// PER_LANE keys each in registers; s_k holds THREADS * PER_LANE keys.
+constexpr int kTsMaxBucket = 64;
+
+__device__ __forceinline__ int pow2_at_least(int m);
+
+template <int THREADS, int PER_LANE>
+__device__ __forceinline__ bool bucket_rank_sort(const TileSortArgs& a, uint32_t start, int n, unsigned long long* s_k,
+                                                 uint32_t* s_b, uint32_t* s_red) {
+  constexpr int NW = THREADS / 64;
+  constexpr int BPL = PER_LANE / 4;              // bucket counters per lane (np/4 <= THREADS * BPL)
+  const int t = threadIdx.x;
+  unsigned long long v[PER_LANE];
+  uint32_t dmin = 0xFFFFFFFFu, dmax = 0u;
+#pragma unroll
+  for (int j = 0; j < PER_LANE; ++j) {
+    const int p = t + j * THREADS;
+    v[j] = p < n ? a.keys[start + p] : 0ull;
+    if (p < n) {
+      const uint32_t d = (uint32_t)(v[j] >> 32);
+      dmin = min(dmin, d);
+      dmax = max(dmax, d);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    dmin = min(dmin, (uint32_t)__shfl_xor((int)dmin, o, 64));
+    dmax = max(dmax, (uint32_t)__shfl_xor((int)dmax, o, 64));
+  }
+  const int wave = t >> 6;
+  if ((t & 63) == 0) {
+    s_red[wave] = dmin;
+    s_red[NW + wave] = dmax;
+  }
+  const int np = pow2_at_least(n);
+  const int nb = np >> 2;                       // buckets (a power of two, >= 4)
+  for (int b = t; b < nb; b += THREADS) s_b[b] = 0u;
+  __syncthreads();
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    dmin = min(dmin, s_red[w]);
+    dmax = max(dmax, s_red[NW + w]);
+  }
+  dmin = __builtin_amdgcn_readfirstlane(dmin);
+  dmax = __builtin_amdgcn_readfirstlane(dmax);
+  const int span_bits = 32 - __clz((int)(dmax - dmin));
+  const int sh = max(span_bits - (31 - __clz(nb)), 0);
+#pragma unroll
+  for (int j = 0; j < PER_LANE; ++j)
+    if (t + j * THREADS < n) atomicAdd(&s_b[((uint32_t)(v[j] >> 32) - dmin) >> sh], 1u);
+  __syncthreads();
+  // bucket starts and the largest bucket
+  const int b0 = t * BPL;
+  uint32_t c[BPL], sum = 0, big = 0;
+#pragma unroll
+  for (int k = 0; k < BPL; ++k) {
+    c[k] = b0 + k < nb ? s_b[b0 + k] : 0u;
+    big = max(big, c[k]);
+  }
+  for (int o = 32; o > 0; o >>= 1) big = max(big, (uint32_t)__shfl_xor((int)big, o, 64));
+  if ((t & 63) == 0) s_red[2 * NW + wave] = big;
+#pragma unroll
+  for (int k = 0; k < BPL; ++k) sum += c[k];
+  uint32_t tot;
+  uint32_t off = block_exclusive_scan<NW>(sum, s_red + 3 * NW, tot);   // its barriers publish the maxima
+#pragma unroll
+  for (int w = 0; w < NW; ++w) big = max(big, s_red[2 * NW + w]);
+  if (__builtin_amdgcn_readfirstlane(big) > (uint32_t)kTsMaxBucket) return false;
+#pragma unroll
+  for (int k = 0; k < BPL; ++k) {
+    if (b0 + k < nb) s_b[b0 + k] = off;
+    off += c[k];
+  }
+  __syncthreads();
+  // counting-sort placement; afterwards s_b[b] is the end of bucket b
+#pragma unroll
+  for (int j = 0; j < PER_LANE; ++j)
+    if (t + j * THREADS < n) s_k[atomicAdd(&s_b[((uint32_t)(v[j] >> 32) - dmin) >> sh], 1u)] = v[j];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < PER_LANE; ++j) {
+    const int p = t + j * THREADS;
+    if (p < n) {
+      const unsigned long long key = s_k[p];
+      const uint32_t b = ((uint32_t)(key >> 32) - dmin) >> sh;
+      const uint32_t lo = b ? s_b[b - 1] : 0u, hi = s_b[b];
+      uint32_t r = lo;
+      for (uint32_t q = lo; q < hi; ++q) r += s_k[q] < key ? 1u : 0u;
+      const uint32_t e = (uint32_t)key;
+      a.gauss[start + r] = a.gofe[e];
+      a.epos[start + r] = e;
+    }
+  }
+  return true;
+}
+
 __device__ __forceinline__ int pow2_at_least(int m) {
   int p = kTsItems;
   while (p < m) p <<= 1;
   return p;
 }
 
-__global__ __launch_bounds__(kTsThreads) void tile_sort_kernel(TileSortArgs a) {
+// One workgroup per tile: the bucket sort for lists of up to kTsCap keys
+// whose buckets stay small; otherwise the merge sort, in LDS up to kTsCap
+// keys, and for longer lists as sorted chunks of kTsCap keys merged through
+// global memory.
+__global__ __launch_bounds__(kTsThreads, 4) void tile_sort_kernel(TileSortArgs a) {
   __shared__ unsigned long long s_k[kTsCap + kTsCap / 16];
+  __shared__ uint32_t s_b[kTsCap / 4];
+  __shared__ uint32_t s_red[4 * (kTsThreads / 64)];
   if (a.report[kRepKeys] > (unsigned long long)a.cap) return;
   const uint2 rg = uniform_u2(a.ranges[blockIdx.x]);
   const int n = (int)(rg.y - rg.x);
@@ -404,6 +576,7 @@ __global__ __launch_bounds__(kTsThreads) void tile_sort_kernel(TileSortArgs a) {
   unsigned long long v[kTsItems];
   const int o = (int)threadIdx.x * kTsItems;
   if (n <= kTsCap) {
+    if (bucket_rank_sort<kTsThreads, kTsCap / kTsThreads>(a, rg.x, n, s_k, s_b, s_red)) return;
     block_sort(seg, n, __builtin_amdgcn_readfirstlane(pow2_at_least(n)), s_k, v);
 #pragma unroll
     for (int k = 0; k < kTsItems; ++k)
