@@ -1165,23 +1165,19 @@ struct ReduceArgs {
 // four rows are loaded before they are summed, so that several row reads are
 // in flight per lane.
 template <int LPG, int GPL>
-__global__ __launch_bounds__(256) void reduce_rows_kernel(ReduceArgs a) {
+__device__ __forceinline__ void reduce_one(const ReduceArgs& a, int64_t g, uint32_t cnt, uint32_t e0, uint32_t ri0) {
   const int sub = threadIdx.x & (LPG - 1);
   const int gbase = (int)(threadIdx.x & 63) & ~(LPG - 1);      // first lane of the group in the wave
-  const int64_t g = ((int64_t)blockIdx.x * 256 + threadIdx.x) / LPG;
   const bool live = g < a.n;
   float4 acc[GPL];
 #pragma unroll
   for (int k = 0; k < GPL; ++k) acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
   float acc9 = 0.f;
-  const bool ok = a.report[kRepStatus] == 0ull;
-  const uint32_t cnt = (live && ok) ? a.count[g] : 0u;
-  const uint32_t e0 = cnt ? a.eoff[g] : 0u;
   uint32_t cmax = cnt;
   for (int o = 32; o >= LPG; o >>= 1) cmax = max(cmax, (uint32_t)__shfl_xor((int)cmax, o, 64));
   const int D4 = a.D >> 2;                  // whole 4-channel groups
   for (uint32_t base = 0; base < cmax; base += LPG) {
-    const uint32_t ri = base + sub < cnt ? a.rowidx[e0 + base + sub] : 0u;
+    const uint32_t ri = base == 0 ? ri0 : (base + sub < cnt ? a.rowidx[e0 + base + sub] : 0u);
     const unsigned long long m = __ballot(ri != 0u);
     unsigned long long mine = LPG == 64 ? m : (m >> gbase) & ((1ull << (LPG & 63)) - 1ull);
     int most = __popcll(mine);
@@ -1250,6 +1246,29 @@ __global__ __launch_bounds__(256) void reduce_rows_kernel(ReduceArgs a) {
   const int k9 = c - a.D;
   if (k9 >= 0 && k9 < 9) a.grad2d[g * 12 + k9] = acc9;
   if (sub < 3) a.grad2d[g * 12 + 9 + sub] = 0.f;
+}
+
+// Each group of LPG lanes sums the rows of NG consecutive Gaussians; their
+// counts, first emit positions and first row indices are loaded together, so
+// a group waits on one chain of dependent loads for all NG instead of NG
+// chains.
+template <int LPG, int GPL, int NG>
+__global__ __launch_bounds__(256) void reduce_rows_kernel(ReduceArgs a) {
+  const int sub = threadIdx.x & (LPG - 1);
+  const int64_t g0 = (((int64_t)blockIdx.x * 256 + threadIdx.x) / LPG) * NG;
+  const bool ok = a.report[kRepStatus] == 0ull;
+  uint32_t cnt[NG], e0[NG], ri0[NG];
+#pragma unroll
+  for (int k = 0; k < NG; ++k) {
+    const int64_t g = g0 + k;
+    const bool live = g < a.n;
+    cnt[k] = (live && ok) ? a.count[g] : 0u;
+    e0[k] = live ? a.eoff[g] : 0u;        // read whether or not used: it does not wait on the count
+  }
+#pragma unroll
+  for (int k = 0; k < NG; ++k) ri0[k] = (uint32_t)sub < cnt[k] ? a.rowidx[e0[k] + sub] : 0u;
+#pragma unroll
+  for (int k = 0; k < NG; ++k) reduce_one<LPG, GPL>(a, g0 + k, cnt[k], e0[k], ri0[k]);
 }
 
 template <int DP, typename FT, int NT>
@@ -1407,15 +1426,16 @@ hipError_t launch_reduce_rows(const fe_config* cfg, const StateView& v, const ui
   const int D = cfg->feat_dim;
   // lanes per Gaussian: enough 4-channel groups per lane for the row, and at
   // least 16 lanes so that the leftover channels and the 9 sums have a lane
+  constexpr int NG = 4;   // Gaussians per lane group
   if (D <= 64) {
-    const unsigned blocks = (unsigned)((v.n + 15) / 16);
-    hipLaunchKernelGGL((reduce_rows_kernel<16, 1>), dim3(blocks), dim3(256), 0, s, a);
+    const unsigned blocks = (unsigned)((v.n + 16 * NG - 1) / (16 * NG));
+    hipLaunchKernelGGL((reduce_rows_kernel<16, 1, NG>), dim3(blocks), dim3(256), 0, s, a);
   } else if (D <= 128) {
-    const unsigned blocks = (unsigned)((v.n + 7) / 8);
-    hipLaunchKernelGGL((reduce_rows_kernel<32, 1>), dim3(blocks), dim3(256), 0, s, a);
+    const unsigned blocks = (unsigned)((v.n + 8 * NG - 1) / (8 * NG));
+    hipLaunchKernelGGL((reduce_rows_kernel<32, 1, NG>), dim3(blocks), dim3(256), 0, s, a);
   } else {
-    const unsigned blocks = (unsigned)((v.n + 3) / 4);
-    hipLaunchKernelGGL((reduce_rows_kernel<64, 1>), dim3(blocks), dim3(256), 0, s, a);
+    const unsigned blocks = (unsigned)((v.n + 4 * NG - 1) / (4 * NG));
+    hipLaunchKernelGGL((reduce_rows_kernel<64, 1, NG>), dim3(blocks), dim3(256), 0, s, a);
   }
   return hipGetLastError();
 }
