@@ -60,18 +60,6 @@ struct BwdArgs {
   bool vec;                  // feature rows allow aligned 4-channel vector loads
 };
 
-__device__ __forceinline__ bool pair_alpha(float fpx, float fpy, int px, int py, float2 m, float4 co,
-                                           int4 b, float& dx, float& dy, float& G, float& alpha) {
-  dx = fpx - m.x;
-  dy = fpy - m.y;
-  const float q = __builtin_fmaf(co.x * dx, dx, __builtin_fmaf(co.z * dy, dy, 2.0f * co.y * dx * dy));
-  const bool inb = (px >= b.x) & (px <= b.z) & (py >= b.y) & (py <= b.w);
-  if (!(inb && q <= kQMax)) return false;
-  G = __expf(-0.5f * q);
-  alpha = fminf(kAlphaMax, co.w * G);
-  return alpha >= kAlphaMin;
-}
-
 __device__ __forceinline__ void split2(float x, __bf16& hi, __bf16& lo) {
   hi = (__bf16)x;
   lo = (__bf16)(x - (float)hi);
@@ -365,12 +353,12 @@ __device__ __forceinline__ void bwd_mfma_tile(const BwdArgs& a, const int tile) 
           const float4 co = s_co[i];
           const int4 b = s_box[i];
           const float dx = fpx - m.x, dy = fpy - m.y;
-          const float q = __builtin_fmaf(co.x * dx, dx, __builtin_fmaf(co.z * dy, dy, 2.0f * co.y * dx * dy));
+          const float qs = scaled_q(scale_conic(co), dx, dy);
           const bool inb = (px >= b.x) & (px <= b.z) & (py >= b.y) & (py <= b.w);
-          const float G = __expf(-0.5f * q);
+          const float G = __builtin_amdgcn_exp2f(qs);
           const float opG = co.w * G;
           const float alpha = fminf(kAlphaMax, opG);
-          ct[u] = (i < nb) & (pos0 + i < last) & inb & (q <= kQMax) & (alpha >= kAlphaMin);
+          ct[u] = (i < nb) & (pos0 + i < last) & inb & (qs >= kQsMin) & (alpha >= kAlphaMin);
           unc[u] = opG <= kAlphaMax;   // alpha not clamped: it depends on opacity and q
           al[u] = alpha;
           Gv[u] = G;
@@ -603,6 +591,7 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
   constexpr size_t kShared = kGBytes > kWBytes ? kGBytes : kWBytes;
   __shared__ float2 s_xy[3][kNB];
   __shared__ float4 s_co[3][kNB];
+  __shared__ float4 s_cs[3][kNB];             // scaled conic for the walkers
   __shared__ float4 s_rgb[2][kNB];
   __shared__ int4 s_box[2][kNB];
   __shared__ __attribute__((aligned(16))) __bf16 s_f[2][NPF][kNB][FROW];
@@ -702,6 +691,7 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
     if (q < kNB) {
       s_xy[b3][q] = p_xy;
       s_co[b3][q] = p_co;
+      s_cs[b3][q] = scale_conic(p_co);
       s_rgb[b2][q] = p_rgb;
       s_box[b2][q] = make_int4(p_box.x, p_box.y, p_box.z, p_box.w);
     }
@@ -874,15 +864,15 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
               for (int u = 0; u < GR; ++u) {
                 const int i = gi * GR + u;
                 const float2 m = s_xy[b3][i];
-                const float4 co = s_co[b3][i];
+                const float4 co = s_cs[b3][i];
                 const int4 b = s_box[b2][i];
                 const float dx = fpx - m.x, dy = fpy - m.y;
-                const float qq = __builtin_fmaf(co.x * dx, dx, __builtin_fmaf(co.z * dy, dy, 2.0f * co.y * dx * dy));
+                const float qs = scaled_q(co, dx, dy);
                 const bool inb = (px >= b.x) & (px <= b.z) & (py >= b.y) & (py <= b.w);
-                const float G = __expf(-0.5f * qq);
+                const float G = __builtin_amdgcn_exp2f(qs);
                 const float opG = co.w * G;
                 const float alpha = fminf(kAlphaMax, opG);
-                const bool ct = (i < lim) & inb & (qq <= kQMax) & (alpha >= kAlphaMin);
+                const bool ct = (i < lim) & inb & (qs >= kQsMin) & (alpha >= kAlphaMin);
                 al[u] = ct ? alpha : 0.f;
                 inv[u] = __builtin_amdgcn_rcpf(1.0f - al[u]);
                 gx[u] = (ct & (opG <= kAlphaMax)) ? G : 0.f;

@@ -16,6 +16,20 @@ constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kTStop = 1e-4f;
 constexpr float kQMax = 9.0f;
 
+// The matrix-core kernels evaluate the falloff G = exp(-q/2) of eq. (1) as
+// exp2(qs) with qs = -log2(e)/2 * q, from the conic scaled once per Gaussian
+// (kQScale A, 2 kQScale B, kQScale C); the cut q <= 9 becomes qs >= kQsMin.
+// Forward and backward use the same expression, so they take the same blend
+// decisions.
+constexpr float kQScale = -0.72134752044448170368f;   // -log2(e) / 2
+constexpr float kQsMin = kQMax * kQScale;
+__device__ __forceinline__ float4 scale_conic(float4 co) {
+  return make_float4(kQScale * co.x, (2.0f * kQScale) * co.y, kQScale * co.z, co.w);
+}
+__device__ __forceinline__ float scaled_q(float4 cs, float dx, float dy) {
+  return __builtin_fmaf(cs.x * dx, dx, __builtin_fmaf(cs.z * dy, dy, cs.y * dx * dy));
+}
+
 // Binning: 256 threads x 4 Gaussians per workgroup; per-tile counters in
 // LDS up to kBinLdsTiles tiles; one workgroup of kBinOffThreads for the
 // offsets.

@@ -49,10 +49,12 @@ __device__ __forceinline__ bool pair_alpha(float fpx, float fpy, int px, int py,
                                            int4 b, float& dx, float& dy, float& G, float& alpha) {
   dx = fpx - m.x;
   dy = fpy - m.y;
-  const float q = __builtin_fmaf(co.x * dx, dx, __builtin_fmaf(co.z * dy, dy, 2.0f * co.y * dx * dy));
+  // the same expression as the matrix-core kernels, so every variant gives
+  // bit-identical images
+  const float qs = scaled_q(scale_conic(co), dx, dy);
   const bool inb = (px >= b.x) & (px <= b.z) & (py >= b.y) & (py <= b.w);
-  if (!(inb && q <= kQMax)) return false;
-  G = __expf(-0.5f * q);
+  if (!(inb && qs >= kQsMin)) return false;
+  G = __builtin_amdgcn_exp2f(qs);
   alpha = fminf(kAlphaMax, co.w * G);
   return alpha >= kAlphaMin;
 }

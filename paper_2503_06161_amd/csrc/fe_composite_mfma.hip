@@ -59,18 +59,6 @@ struct MfmaArgs {
   bool vec;                      // feature rows allow aligned 4-channel vector loads
 };
 
-__device__ __forceinline__ bool pair_alpha(float fpx, float fpy, int px, int py, float2 m, float4 co,
-                                           int4 b, float& G, float& alpha) {
-  const float dx = fpx - m.x;
-  const float dy = fpy - m.y;
-  const float q = __builtin_fmaf(co.x * dx, dx, __builtin_fmaf(co.z * dy, dy, 2.0f * co.y * dx * dy));
-  const bool inb = (px >= b.x) & (px <= b.z) & (py >= b.y) & (py <= b.w);
-  if (!(inb && q <= kQMax)) return false;
-  G = __expf(-0.5f * q);
-  alpha = fminf(kAlphaMax, co.w * G);
-  return alpha >= kAlphaMin;
-}
-
 __device__ __forceinline__ float bf16_to_f32(__bf16 h) { return (float)h; }
 
 // float32 -> three bf16 parts, hi + mid + lo == x exactly
@@ -211,7 +199,7 @@ void composite_fwd_mfma_kernel(MfmaArgs a) {
     // ---- stage the batch from registers ----
     if ((int)threadIdx.x < kNB) {
       s_xy[threadIdx.x] = p_xy;
-      s_co[threadIdx.x] = p_co;
+      s_co[threadIdx.x] = scale_conic(p_co);
       s_rgb[threadIdx.x] = p_rgb;
       s_box[threadIdx.x] = make_int4(p_box.x, p_box.y, p_box.z, p_box.w);
     }
@@ -258,13 +246,13 @@ void composite_fwd_mfma_kernel(MfmaArgs a) {
         for (int u = 0; u < GR; ++u) {
           const int i = 16 * s + gi * GR + u;
           const float2 m = s_xy[i];
-          const float4 co = s_co[i];
+          const float4 co = s_co[i];                // scaled conic, opacity
           const int4 b = s_box[i];
           const float dx = fpx - m.x, dy = fpy - m.y;
-          const float q = __builtin_fmaf(co.x * dx, dx, __builtin_fmaf(co.z * dy, dy, 2.0f * co.y * dx * dy));
+          const float qs = scaled_q(co, dx, dy);
           const bool inb = (px >= b.x) & (px <= b.z) & (py >= b.y) & (py <= b.w);
-          const float alpha = fminf(kAlphaMax, co.w * __expf(-0.5f * q));
-          act[u] = (i < nb) & inb & (q <= kQMax) & (alpha >= kAlphaMin);
+          const float alpha = fminf(kAlphaMax, co.w * __builtin_amdgcn_exp2f(qs));
+          act[u] = (i < nb) & inb & (qs >= kQsMin) & (alpha >= kAlphaMin);
           al[u] = alpha;
         }
 #pragma unroll
@@ -437,7 +425,8 @@ __device__ __forceinline__ void fwd_ws_tile(const MfmaArgs& a, const int tile) {
     if (q < kNB) {
       // conic as (a, 2 b, c, opacity); padding entries get opacity 0
       s_xy[b2][q] = p_xy;
-      s_co[b2][q] = make_float4(p_co.x, 2.0f * p_co.y, p_co.z, q < nb ? p_co.w : 0.f);
+      const float4 cs = scale_conic(p_co);
+      s_co[b2][q] = make_float4(cs.x, cs.y, cs.z, q < nb ? p_co.w : 0.f);
       s_rgb[b2][q] = p_rgb;
       s_box[b2][q] = make_int4(p_box.x, p_box.y, p_box.z, p_box.w);
     }
@@ -484,13 +473,13 @@ __device__ __forceinline__ void fwd_ws_tile(const MfmaArgs& a, const int tile) {
           for (int u = 0; u < 16; ++u) {
             const int i = 16 * s + u;
             const float2 m = s_xy[b2][i];
-            const float4 co = s_co[b2][i];            // (a, 2 b, c, opacity)
+            const float4 co = s_co[b2][i];            // scaled conic, opacity
             const int4 b = s_box[b2][i];
             const float dx = fpx - m.x, dy = fpy - m.y;
-            const float qq = __builtin_fmaf(co.x * dx, dx, __builtin_fmaf(co.z * dy, dy, co.y * dx * dy));
+            const float qs = scaled_q(co, dx, dy);
             const bool inb = (px >= b.x) & (px <= b.z) & (py >= b.y) & (py <= b.w);
-            const float alpha = fminf(kAlphaMax, co.w * __expf(-0.5f * qq));
-            al[u] = (inb & (qq <= kQMax) & (alpha >= kAlphaMin)) ? alpha : 0.f;
+            const float alpha = fminf(kAlphaMax, co.w * __builtin_amdgcn_exp2f(qs));
+            al[u] = (inb & (qs >= kQsMin) & (alpha >= kAlphaMin)) ? alpha : 0.f;
             om[u] = 1.0f - al[u];
           }
           // front-to-back transmittance chain
