@@ -60,7 +60,9 @@ extern "C" {
 typedef enum fe_status {
   FE_OK = 0,
   FE_ERR_INVALID_ARG = 1,        /* NULL pointer, bad size, bad enum value      */
-  FE_ERR_UNSUPPORTED = 2,        /* feat_dim > 256, sh_degree > 3, W/H > 32767  */
+  FE_ERR_UNSUPPORTED = 2,        /* feat_dim > 256, sh_degree > 3, W/H > 32767,
+                                    n > 2^23 Gaussians, tile shapes other than
+                                    8/16/32 wide with 64/128/256 pixels        */
   FE_ERR_WORKSPACE_TOO_SMALL = 3,/* state / scratch / workspace below *_bytes() */
   FE_ERR_KEY_OVERFLOW = 4,       /* device: more (tile, Gaussian) keys than
                                     key_capacity; outputs are invalid and

@@ -110,9 +110,9 @@ CamConst make_cam_const(const fe_camera* cam, const fe_config* cfg) {
 
 static fe_status hip_status(hipError_t e) { return e == hipSuccess ? FE_OK : FE_ERR_HIP; }
 
-// backward scratch: grad2d [n][12] | row_base [tiles] | scan sums | rows [row_cap][RS]
+// backward scratch: grad2d [n][12] | row_base [tiles] | rowidx [cap] | rows [row_cap][RS]
 struct BwdScratch {
-  size_t grad2d, row_base, sums, rowidx, rows, total;
+  size_t grad2d, row_base, rowidx, rows, total;
   int64_t row_cap;
 };
 
@@ -127,11 +127,10 @@ static bool bwd_scratch_layout(const fe_config* cfg, const fe_camera* cam, int64
   };
   b->grad2d = take(sizeof(float) * 12 * (size_t)(n > 0 ? n : 1));
   b->row_cap = 0;
-  b->row_base = b->sums = b->rowidx = b->rows = o;
+  b->row_base = b->rowidx = b->rows = o;
   if (cfg->variant != FE_VARIANT_VALU) {
     b->row_cap = cfg->row_capacity > 0 ? cfg->row_capacity : cfg->key_capacity;
     b->row_base = take(sizeof(uint32_t) * ((size_t)L.tiles + 1));
-    b->sums = take(sizeof(uint32_t) * ((size_t)((L.tiles + kScanChunk - 1) / kScanChunk) + 1));
     b->rowidx = take(sizeof(uint32_t) * (size_t)L.cap);
     b->rows = take(sizeof(float) * (size_t)backward_row_stride(cfg->feat_dim) * (size_t)b->row_cap);
   }
@@ -192,7 +191,6 @@ static fe_status forward_impl(const fe_config* cfg, const fe_camera* cam, const 
 struct BwdBuffers {
   float* grad2d;
   uint32_t* row_base;
-  uint32_t* sums;
   uint32_t* rowidx;
   float* rows;
   int64_t row_cap;
@@ -205,7 +203,6 @@ static BwdBuffers bwd_buffers(const fe_config* cfg, const fe_camera* cam, int64_
   BwdBuffers b;
   b.grad2d = reinterpret_cast<float*>(sb + bs.grad2d);
   b.row_base = reinterpret_cast<uint32_t*>(sb + bs.row_base);
-  b.sums = reinterpret_cast<uint32_t*>(sb + bs.sums);
   b.rowidx = reinterpret_cast<uint32_t*>(sb + bs.rowidx);
   b.rows = reinterpret_cast<float*>(sb + bs.rows);
   b.row_cap = bs.row_cap;
@@ -214,7 +211,7 @@ static BwdBuffers bwd_buffers(const fe_config* cfg, const fe_camera* cam, int64_
 
 static fe_status backward_pre(const Layout& L, const void* state, const BwdBuffers& b, hipStream_t s) {
   StateView v = make_view(L, const_cast<void*>(state));
-  if (launch_scan_u32(v.tile_maxlast, b.row_base, b.sums, v.tiles, s) != hipSuccess) return FE_ERR_HIP;
+  if (launch_scan_u32(v.tile_maxlast, b.row_base, v.tiles, s) != hipSuccess) return FE_ERR_HIP;
   return hip_status(launch_zero_u32(b.rowidx, (size_t)L.cap, s));
 }
 
@@ -301,7 +298,7 @@ fe_status fe_validate(const fe_config* cfg, const fe_camera* cam, int64_t n) {
       (cfg->feat_dtype != FE_F32 && cfg->feat_dtype != FE_BF16))
     return FE_ERR_INVALID_ARG;
   if (cfg->key_capacity < 0 || cfg->key_capacity > 0x7FFFFFFFll) return FE_ERR_INVALID_ARG;
-  if (n > (int64_t)kScanChunk * kScanTopMax) return FE_ERR_UNSUPPORTED;
+  if (n > kMaxGaussians) return FE_ERR_UNSUPPORTED;
   if (cfg->variant != FE_VARIANT_AUTO && cfg->variant != FE_VARIANT_VALU && cfg->variant != FE_VARIANT_MFMA)
     return FE_ERR_UNSUPPORTED;
   return FE_OK;

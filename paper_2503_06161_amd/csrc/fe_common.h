@@ -39,11 +39,8 @@ constexpr int kBinChunk = kBinThreads * kBinItems;      // 1024
 constexpr int kBinLdsTiles = 12288;
 constexpr int kBinOffThreads = 1024;
 
-// Exclusive scan: 256 threads x 8 items per block.
-constexpr int kScanThreads = 256;
-constexpr int kScanItems = 8;
-constexpr int kScanChunk = kScanThreads * kScanItems;   // 2048
-constexpr int kScanTopMax = kScanThreads * 16;          // block sums scanned by one block
+// Largest supported Gaussian count.
+constexpr int64_t kMaxGaussians = int64_t(1) << 23;
 
 // Report words (unsigned long long) at StateView::report.
 enum ReportWord { kRepStatus = 0, kRepKeys = 1, kRepVisible = 2, kRepNonFinite = 3, kRepRows = 4, kRepWords = 8 };
@@ -113,7 +110,7 @@ hipError_t launch_composite_fwd_mfma(const fe_config* cfg, const fe_camera* cam,
 hipError_t launch_composite_bwd(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
                                 const StateView& v, const fe_images* fwd, const float* d_rgb,
                                 const float* d_feat, float* grad2d, float* grad_feat, hipStream_t s);
-hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, uint32_t* sums, int64_t n, hipStream_t s);
+hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s);
 int backward_row_stride(int D);
 hipError_t launch_composite_bwd_mfma(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
                                      const StateView& v, const fe_images* fwd, const float* d_rgb,

@@ -59,62 +59,30 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
   return wave_off + x - v;
 }
 
-// ---- exclusive scan of u32 values ----
-struct ScanArgs {
-  const uint32_t* in;       // values
-  uint32_t* out;            // exclusive prefix
-  uint32_t* block_sums;     // [nblocks]
-  int64_t n;
-};
+// ---- exclusive scan of u32 values (one workgroup; sizes here are per-tile
+// arrays, a few thousand entries) ----
+constexpr int kScanWg = 1024;
 
-__global__ __launch_bounds__(kScanThreads) void scan_local_kernel(ScanArgs a) {
-  __shared__ uint32_t s_warp[kScanThreads / 64];
-  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
-  uint32_t v[kScanItems];
-  uint32_t sum = 0;
+__global__ __launch_bounds__(kScanWg) void scan_small_kernel(const uint32_t* in, uint32_t* out, int64_t n) {
+  __shared__ uint32_t s_warp[kScanWg / 64];
+  constexpr int per = 4;
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < n; base += kScanWg * per) {
+    const int64_t i0 = base + (int64_t)threadIdx.x * per;
+    uint32_t c[per], sum = 0;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    const int64_t i = base + k;
-    const uint32_t x = i < a.n ? a.in[i] : 0u;
-    v[k] = sum;
-    sum += x;
-  }
-  uint32_t total;
-  const uint32_t off = block_exclusive_scan<kScanThreads / 64>(sum, s_warp, total);
+    for (int k = 0; k < per; ++k) {
+      c[k] = i0 + k < n ? in[i0 + k] : 0u;
+      sum += c[k];
+    }
+    uint32_t step;
+    uint32_t o = carry + block_exclusive_scan<kScanWg / 64>(sum, s_warp, step);
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    const int64_t i = base + k;
-    if (i < a.n) a.out[i] = off + v[k];
-  }
-  if (threadIdx.x == 0) a.block_sums[blockIdx.x] = total;
-}
-
-__global__ __launch_bounds__(kScanThreads) void scan_top_kernel(uint32_t* sums, int nblocks) {
-  __shared__ uint32_t s_warp[kScanThreads / 64];
-  constexpr int per = kScanTopMax / kScanThreads;   // 16
-  uint32_t v[per];
-  uint32_t sum = 0;
-  for (int k = 0; k < per; ++k) {
-    const int i = threadIdx.x * per + k;
-    const uint32_t x = i < nblocks ? sums[i] : 0u;
-    v[k] = sum;
-    sum += x;
-  }
-  uint32_t total;
-  const uint32_t off = block_exclusive_scan<kScanThreads / 64>(sum, s_warp, total);
-  for (int k = 0; k < per; ++k) {
-    const int i = threadIdx.x * per + k;
-    if (i < nblocks) sums[i] = off + v[k];
-  }
-}
-
-__global__ __launch_bounds__(kScanThreads) void scan_add_kernel(uint32_t* out, const uint32_t* sums, int64_t n) {
-  const uint32_t add = sums[blockIdx.x];
-  if (add == 0) return;
-  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
-  for (int k = threadIdx.x; k < kScanChunk; k += kScanThreads) {
-    const int64_t i = base + k;
-    if (i < n) out[i] += add;
+    for (int k = 0; k < per; ++k) {
+      if (i0 + k < n) out[i0 + k] = o;
+      o += c[k];
+    }
+    carry += step;
   }
 }
 
@@ -630,16 +598,6 @@ __global__ __launch_bounds__(kTsThreads, 4) void tile_sort_kernel(TileSortArgs a
       }
 }
 
-hipError_t scan_u32(const uint32_t* in, uint32_t* out, uint32_t* sums, int64_t n, hipStream_t s) {
-  ScanArgs a{in, out, sums, n};
-  const int nb = (int)((n + kScanChunk - 1) / kScanChunk);
-  if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(scan_local_kernel, dim3(nb), dim3(kScanThreads), 0, s, a);
-  hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(kScanThreads), 0, s, sums, nb);
-  hipLaunchKernelGGL(scan_add_kernel, dim3(nb), dim3(kScanThreads), 0, s, out, (const uint32_t*)sums, n);
-  return hipGetLastError();
-}
-
 // ---- work queue of (frame, tile) items, longest first ----
 // One workgroup: every item gets the bucket 1 + floor(log2(length)) (0 for
 // an empty tile), buckets are laid out from the longest down, and items are
@@ -689,8 +647,10 @@ __global__ __launch_bounds__(1024) void build_tile_queue_kernel(TileQueueBuild b
 
 }  // namespace
 
-hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, uint32_t* sums, int64_t n, hipStream_t s) {
-  return scan_u32(in, out, sums, n, s);
+hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scan_small_kernel, dim3(1), dim3(kScanWg), 0, s, in, out, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_zero_u32(uint32_t* p, size_t count, hipStream_t s) {
