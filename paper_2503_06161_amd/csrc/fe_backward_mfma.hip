@@ -693,7 +693,8 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
       s_co[b3][q] = p_co;
       s_cs[b3][q] = scale_conic(p_co);
       s_rgb[b2][q] = p_rgb;
-      s_box[b2][q] = make_int4(p_box.x, p_box.y, p_box.z, p_box.w);
+      // (x0, y0, x1 - x0, y1 - y0): one unsigned compare per axis in the walk
+      s_box[b2][q] = make_int4(p_box.x, p_box.y, p_box.z - p_box.x, p_box.w - p_box.y);
     }
 #pragma unroll
     for (int k2 = 0; k2 < FI; ++k2) {
@@ -868,7 +869,7 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
                 const int4 b = s_box[b2][i];
                 const float dx = fpx - m.x, dy = fpy - m.y;
                 const float qs = scaled_q(co, dx, dy);
-                const bool inb = (px >= b.x) & (px <= b.z) & (py >= b.y) & (py <= b.w);
+                const bool inb = ((uint32_t)(px - b.x) <= (uint32_t)b.z) & ((uint32_t)(py - b.y) <= (uint32_t)b.w);
                 const float G = __builtin_amdgcn_exp2f(qs);
                 const float opG = co.w * G;
                 const float alpha = fminf(kAlphaMax, opG);

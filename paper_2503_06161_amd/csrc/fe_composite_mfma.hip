@@ -428,7 +428,8 @@ __device__ __forceinline__ void fwd_ws_tile(const MfmaArgs& a, const int tile) {
       const float4 cs = scale_conic(p_co);
       s_co[b2][q] = make_float4(cs.x, cs.y, cs.z, q < nb ? p_co.w : 0.f);
       s_rgb[b2][q] = p_rgb;
-      s_box[b2][q] = make_int4(p_box.x, p_box.y, p_box.z, p_box.w);
+      // (x0, y0, x1 - x0, y1 - y0): one unsigned compare per axis in the walk
+      s_box[b2][q] = make_int4(p_box.x, p_box.y, p_box.z - p_box.x, p_box.w - p_box.y);
     }
 #pragma unroll
     for (int j = 0; j < FI; ++j) {
@@ -477,7 +478,7 @@ __device__ __forceinline__ void fwd_ws_tile(const MfmaArgs& a, const int tile) {
             const int4 b = s_box[b2][i];
             const float dx = fpx - m.x, dy = fpy - m.y;
             const float qs = scaled_q(co, dx, dy);
-            const bool inb = (px >= b.x) & (px <= b.z) & (py >= b.y) & (py <= b.w);
+            const bool inb = ((uint32_t)(px - b.x) <= (uint32_t)b.z) & ((uint32_t)(py - b.y) <= (uint32_t)b.w);
             const float alpha = fminf(kAlphaMax, co.w * __builtin_amdgcn_exp2f(qs));
             al[u] = (inb & (qs >= kQsMin) & (alpha >= kAlphaMin)) ? alpha : 0.f;
             om[u] = 1.0f - al[u];
