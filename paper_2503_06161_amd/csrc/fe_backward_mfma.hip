@@ -99,6 +99,7 @@ __device__ __forceinline__ void bwd_mfma_tile(const BwdArgs& a, const int tile) 
   constexpr size_t kShared = kGBytes > kWBytes + kDFBytes ? kGBytes : kWBytes + kDFBytes;
   __shared__ float2 s_xy[kNB];
   __shared__ float4 s_co[kNB];
+  __shared__ float s_tg[kNB];
   __shared__ float4 s_rgb[kNB];
   __shared__ int4 s_box[kNB];
   __shared__ __attribute__((aligned(16))) __bf16 s_f[NPF][kNB][FROW];
@@ -284,6 +285,7 @@ __device__ __forceinline__ void bwd_mfma_tile(const BwdArgs& a, const int tile) 
     if ((int)threadIdx.x < kNB) {
       s_xy[threadIdx.x] = p_xy;
       s_co[threadIdx.x] = p_co;
+      s_tg[threadIdx.x] = blend_cut(p_co.w);
       s_rgb[threadIdx.x] = p_rgb;
       s_box[threadIdx.x] = make_int4(p_box.x, p_box.y, p_box.z, p_box.w);
     }
@@ -358,7 +360,7 @@ __device__ __forceinline__ void bwd_mfma_tile(const BwdArgs& a, const int tile) 
           const float G = __builtin_amdgcn_exp2f(qs);
           const float opG = co.w * G;
           const float alpha = fminf(kAlphaMax, opG);
-          ct[u] = (i < nb) & (pos0 + i < last) & inb & (qs >= kQsMin) & (alpha >= kAlphaMin);
+          ct[u] = (i < nb) & (pos0 + i < last) & inb & (qs >= s_tg[i]);
           unc[u] = opG <= kAlphaMax;   // alpha not clamped: it depends on opacity and q
           al[u] = alpha;
           Gv[u] = G;
@@ -592,6 +594,7 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
   __shared__ float2 s_xy[3][kNB];
   __shared__ float4 s_co[3][kNB];
   __shared__ float4 s_cs[3][kNB];             // scaled conic for the walkers
+  __shared__ float s_tg[3][kNB];              // blend cut on qs
   __shared__ float4 s_rgb[2][kNB];
   __shared__ int4 s_box[2][kNB];
   __shared__ __attribute__((aligned(16))) __bf16 s_f[2][NPF][kNB][FROW];
@@ -692,6 +695,7 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
       s_xy[b3][q] = p_xy;
       s_co[b3][q] = p_co;
       s_cs[b3][q] = scale_conic(p_co);
+      s_tg[b3][q] = blend_cut(p_co.w);
       s_rgb[b2][q] = p_rgb;
       // (x0, y0, x1 - x0, y1 - y0): one unsigned compare per axis in the walk
       s_box[b2][q] = make_int4(p_box.x, p_box.y, p_box.z - p_box.x, p_box.w - p_box.y);
@@ -873,7 +877,7 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
                 const float G = __builtin_amdgcn_exp2f(qs);
                 const float opG = co.w * G;
                 const float alpha = fminf(kAlphaMax, opG);
-                const bool ct = (i < lim) & inb & (qs >= kQsMin) & (alpha >= kAlphaMin);
+                const bool ct = (i < lim) & inb & (qs >= s_tg[b3][i]);
                 al[u] = ct ? alpha : 0.f;
                 inv[u] = __builtin_amdgcn_rcpf(1.0f - al[u]);
                 gx[u] = (ct & (opG <= kAlphaMax)) ? G : 0.f;

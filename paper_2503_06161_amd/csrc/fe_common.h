@@ -29,6 +29,10 @@ __device__ __forceinline__ float4 scale_conic(float4 co) {
 __device__ __forceinline__ float scaled_q(float4 cs, float dx, float dy) {
   return __builtin_fmaf(cs.x * dx, dx, __builtin_fmaf(cs.z * dy, dy, cs.y * dx * dy));
 }
+// Both cuts of a pair, q <= 9 and alpha = min(0.99, o G) >= 1/255, as one
+// bound on qs, staged per Gaussian: o 2^qs >= 1/255 <=> qs >= -log2(255 o).
+// Opacity 0 (padding) gives +inf: never blended.
+__device__ __forceinline__ float blend_cut(float o) { return fmaxf(kQsMin, -__log2f(255.0f * o)); }
 
 // Binning: 256 threads x 4 Gaussians per workgroup; per-tile counters in
 // LDS up to kBinLdsTiles tiles; one workgroup of kBinOffThreads for the

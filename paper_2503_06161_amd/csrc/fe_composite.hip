@@ -45,7 +45,7 @@ struct CompArgs {
 
 // Alpha of one (pixel, Gaussian) pair; returns false when the pair is
 // skipped (outside the box, q > 9, alpha < 1/255).
-__device__ __forceinline__ bool pair_alpha(float fpx, float fpy, int px, int py, float2 m, float4 co,
+__device__ __forceinline__ bool pair_alpha(float fpx, float fpy, int px, int py, float2 m, float4 co, float tg,
                                            int4 b, float& dx, float& dy, float& G, float& alpha) {
   dx = fpx - m.x;
   dy = fpy - m.y;
@@ -53,10 +53,10 @@ __device__ __forceinline__ bool pair_alpha(float fpx, float fpy, int px, int py,
   // bit-identical images
   const float qs = scaled_q(scale_conic(co), dx, dy);
   const bool inb = (px >= b.x) & (px <= b.z) & (py >= b.y) & (py <= b.w);
-  if (!(inb && qs >= kQsMin)) return false;
+  if (!(inb && qs >= tg)) return false;
   G = __builtin_amdgcn_exp2f(qs);
   alpha = fminf(kAlphaMax, co.w * G);
-  return alpha >= kAlphaMin;
+  return true;
 }
 
 template <typename FT>
@@ -65,13 +65,15 @@ __device__ __forceinline__ float feat_at(const void* p, int64_t i) {
 }
 
 template <int D, typename FT, int NT, int NB>
-__device__ __forceinline__ void stage_batch(const CompArgs& a, uint32_t b0, int nb, float2* s_xy, float4* s_co,
+__device__ __forceinline__ void stage_batch(const CompArgs& a, uint32_t b0, int nb, float2* s_xy, float4* s_co, float* s_tg,
                                             float4* s_rgb, int4* s_box, uint32_t* s_gid, float* s_f) {
   for (int t = threadIdx.x; t < nb; t += NT) {
     const uint32_t g = a.gauss[b0 + t];
     s_gid[t] = g;
     s_xy[t] = a.xy[g];
-    s_co[t] = a.conic_o[g];
+    const float4 co = a.conic_o[g];
+    s_co[t] = co;
+    s_tg[t] = blend_cut(co.w);
     s_rgb[t] = a.rgb[g];
     const short4 b = a.box[g];
     s_box[t] = make_int4(b.x, b.y, b.z, b.w);
@@ -98,6 +100,7 @@ __global__ __launch_bounds__(NT) void composite_fwd_kernel(CompArgs a) {
   constexpr int NB = batch_size<D>();
   __shared__ float2 s_xy[NB];
   __shared__ float4 s_co[NB];
+  __shared__ float s_tg[NB];
   __shared__ float4 s_rgb[NB];
   __shared__ int4 s_box[NB];
   __shared__ uint32_t s_gid[NB];
@@ -119,12 +122,12 @@ __global__ __launch_bounds__(NT) void composite_fwd_kernel(CompArgs a) {
   for (uint32_t b0 = rg.x; b0 < rg.y; b0 += NB) {
     const int nb = (int)min((uint32_t)NB, rg.y - b0);
     if (__syncthreads_count(!done) == 0) break;
-    stage_batch<D, FT, NT, NB>(a, b0, nb, s_xy, s_co, s_rgb, s_box, s_gid, s_f);
+    stage_batch<D, FT, NT, NB>(a, b0, nb, s_xy, s_co, s_tg, s_rgb, s_box, s_gid, s_f);
     __syncthreads();
     if (!done) {
       for (int j = 0; j < nb; ++j) {
         float dx, dy, G, alpha;
-        if (!pair_alpha(fpx, fpy, px, py, s_xy[j], s_co[j], s_box[j], dx, dy, G, alpha)) continue;
+        if (!pair_alpha(fpx, fpy, px, py, s_xy[j], s_co[j], s_tg[j], s_box[j], dx, dy, G, alpha)) continue;
         const float Tn = T * (1.0f - alpha);
         if (Tn < kTStop) {
           done = true;
@@ -183,6 +186,7 @@ __global__ __launch_bounds__(NT) void composite_bwd_kernel(CompArgs a) {
   constexpr int NB = batch_size<D>();
   __shared__ float2 s_xy[NB];
   __shared__ float4 s_co[NB];
+  __shared__ float s_tg[NB];
   __shared__ float4 s_rgb[NB];
   __shared__ int4 s_box[NB];
   __shared__ uint32_t s_gid[NB];
@@ -225,13 +229,13 @@ __global__ __launch_bounds__(NT) void composite_bwd_kernel(CompArgs a) {
     const uint32_t b0 = b1 - rg.x > (uint32_t)NB ? b1 - NB : rg.x;
     const int nb = (int)(b1 - b0);
     __syncthreads();
-    stage_batch<D, FT, NT, NB>(a, b0, nb, s_xy, s_co, s_rgb, s_box, s_gid, s_f);
+    stage_batch<D, FT, NT, NB>(a, b0, nb, s_xy, s_co, s_tg, s_rgb, s_box, s_gid, s_f);
     __syncthreads();
     for (int j = nb - 1; j >= 0; --j) {
       const int pos = (int)(b0 - rg.x) + j;
       float dx = 0.f, dy = 0.f, G = 0.f, alpha = 0.f;
       bool contrib = false;
-      if (inside && pos < last) contrib = pair_alpha(fpx, fpy, px, py, s_xy[j], s_co[j], s_box[j], dx, dy, G, alpha);
+      if (inside && pos < last) contrib = pair_alpha(fpx, fpy, px, py, s_xy[j], s_co[j], s_tg[j], s_box[j], dx, dy, G, alpha);
       if (__ballot(contrib) == 0ull) continue;
       float v[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       float w = 0.f;

@@ -128,6 +128,7 @@ void composite_fwd_mfma_kernel(MfmaArgs a) {
   constexpr int FROW = DP + 32;
   __shared__ float2 s_xy[kNB];
   __shared__ float4 s_co[kNB];
+  __shared__ float s_tg[kNB];
   __shared__ float4 s_rgb[kNB];
   __shared__ int4 s_box[kNB];
   __shared__ __attribute__((aligned(16))) __bf16 s_f[NPL][kNB][FROW];
@@ -200,6 +201,7 @@ void composite_fwd_mfma_kernel(MfmaArgs a) {
     if ((int)threadIdx.x < kNB) {
       s_xy[threadIdx.x] = p_xy;
       s_co[threadIdx.x] = scale_conic(p_co);
+      s_tg[threadIdx.x] = blend_cut(p_co.w);
       s_rgb[threadIdx.x] = p_rgb;
       s_box[threadIdx.x] = make_int4(p_box.x, p_box.y, p_box.z, p_box.w);
     }
@@ -252,7 +254,7 @@ void composite_fwd_mfma_kernel(MfmaArgs a) {
           const float qs = scaled_q(co, dx, dy);
           const bool inb = (px >= b.x) & (px <= b.z) & (py >= b.y) & (py <= b.w);
           const float alpha = fminf(kAlphaMax, co.w * __builtin_amdgcn_exp2f(qs));
-          act[u] = (i < nb) & inb & (qs >= kQsMin) & (alpha >= kAlphaMin);
+          act[u] = (i < nb) & inb & (qs >= s_tg[i]);
           al[u] = alpha;
         }
 #pragma unroll
@@ -367,6 +369,7 @@ __device__ __forceinline__ void fwd_ws_tile(const MfmaArgs& a, const int tile) {
   constexpr int WROW = kNB + 4;                // float32 weight row of a pixel (bank spread)
   __shared__ float2 s_xy[2][kNB];
   __shared__ float4 s_co[2][kNB];
+  __shared__ float s_tg[2][kNB];
   __shared__ float4 s_rgb[2][kNB];
   __shared__ int4 s_box[2][kNB];
   __shared__ __attribute__((aligned(16))) __bf16 s_f[3][kNB][FROW];
@@ -427,6 +430,7 @@ __device__ __forceinline__ void fwd_ws_tile(const MfmaArgs& a, const int tile) {
       s_xy[b2][q] = p_xy;
       const float4 cs = scale_conic(p_co);
       s_co[b2][q] = make_float4(cs.x, cs.y, cs.z, q < nb ? p_co.w : 0.f);
+      s_tg[b2][q] = blend_cut(q < nb ? p_co.w : 0.f);
       s_rgb[b2][q] = p_rgb;
       // (x0, y0, x1 - x0, y1 - y0): one unsigned compare per axis in the walk
       s_box[b2][q] = make_int4(p_box.x, p_box.y, p_box.z - p_box.x, p_box.w - p_box.y);
@@ -480,7 +484,7 @@ __device__ __forceinline__ void fwd_ws_tile(const MfmaArgs& a, const int tile) {
             const float qs = scaled_q(co, dx, dy);
             const bool inb = ((uint32_t)(px - b.x) <= (uint32_t)b.z) & ((uint32_t)(py - b.y) <= (uint32_t)b.w);
             const float alpha = fminf(kAlphaMax, co.w * __builtin_amdgcn_exp2f(qs));
-            al[u] = (inb & (qs >= kQsMin) & (alpha >= kAlphaMin)) ? alpha : 0.f;
+            al[u] = (inb & (qs >= s_tg[b2][i])) ? alpha : 0.f;
             om[u] = 1.0f - al[u];
           }
           // front-to-back transmittance chain
