@@ -596,7 +596,7 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
   __shared__ float4 s_cs[3][kNB];             // scaled conic for the walkers
   __shared__ float s_tg[3][kNB];              // blend cut on qs
   __shared__ float4 s_rgb[2][kNB];
-  __shared__ int4 s_box[2][kNB];
+  __shared__ uint2 s_box[2][kNB];             // packed (origin, extent)
   __shared__ __attribute__((aligned(16))) __bf16 s_f[2][NPF][kNB][FROW];
   // per walker wave: pixel moments (about the tile centre) and colour sums of
   // each Gaussian of a batch, and the X values of a 16-Gaussian half
@@ -623,6 +623,7 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
   const int py = ty0 + q / a.tile_w;
   const bool inside = (px < a.W) & (py < a.H);
   const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+  const u16x2 pp = {(unsigned short)px, (unsigned short)py};
   const int64_t HW = (int64_t)a.W * a.H;
   // walkers: the upstream feature gradient of their pixel, all slices issued first
   constexpr int GS = CB < 2 ? CB : 2;
@@ -697,8 +698,7 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
       s_cs[b3][q] = scale_conic(p_co);
       s_tg[b3][q] = blend_cut(p_co.w);
       s_rgb[b2][q] = p_rgb;
-      // (x0, y0, x1 - x0, y1 - y0): one unsigned compare per axis in the walk
-      s_box[b2][q] = make_int4(p_box.x, p_box.y, p_box.z - p_box.x, p_box.w - p_box.y);
+      s_box[b2][q] = pack_box(p_box);
     }
 #pragma unroll
     for (int k2 = 0; k2 < FI; ++k2) {
@@ -870,10 +870,9 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
                 const int i = gi * GR + u;
                 const float2 m = s_xy[b3][i];
                 const float4 co = s_cs[b3][i];
-                const int4 b = s_box[b2][i];
                 const float dx = fpx - m.x, dy = fpy - m.y;
                 const float qs = scaled_q(co, dx, dy);
-                const bool inb = ((uint32_t)(px - b.x) <= (uint32_t)b.z) & ((uint32_t)(py - b.y) <= (uint32_t)b.w);
+                const bool inb = in_box(pp, s_box[b2][i]);
                 const float G = __builtin_amdgcn_exp2f(qs);
                 const float opG = co.w * G;
                 const float alpha = fminf(kAlphaMax, opG);

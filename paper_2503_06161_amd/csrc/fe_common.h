@@ -34,6 +34,20 @@ __device__ __forceinline__ float scaled_q(float4 cs, float dx, float dy) {
 // Opacity 0 (padding) gives +inf: never blended.
 __device__ __forceinline__ float blend_cut(float o) { return fmaxf(kQsMin, -__log2f(255.0f * o)); }
 
+// Pixel box test on packed 16-bit coordinates: box = (x0 | y0 << 16,
+// (x1 - x0) | (y1 - y0) << 16), p = px | py << 16.  p - origin wraps below
+// the origin; the saturating subtraction of the extent is 0 on an axis iff
+// the offset is within the extent.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint2 pack_box(short4 b) {
+  return make_uint2((uint32_t)(uint16_t)b.x | ((uint32_t)(uint16_t)b.y << 16),
+                    (uint32_t)(uint16_t)(b.z - b.x) | ((uint32_t)(uint16_t)(b.w - b.y) << 16));
+}
+__device__ __forceinline__ bool in_box(u16x2 p, uint2 box) {
+  const u16x2 d = p - __builtin_bit_cast(u16x2, box.x);
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_sub_sat(d, __builtin_bit_cast(u16x2, box.y))) == 0u;
+}
+
 // Binning: 256 threads x 4 Gaussians per workgroup; per-tile counters in
 // LDS up to kBinLdsTiles tiles; one workgroup of kBinOffThreads for the
 // offsets.

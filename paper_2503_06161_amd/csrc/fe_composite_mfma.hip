@@ -371,7 +371,7 @@ __device__ __forceinline__ void fwd_ws_tile(const MfmaArgs& a, const int tile) {
   __shared__ float4 s_co[2][kNB];
   __shared__ float s_tg[2][kNB];
   __shared__ float4 s_rgb[2][kNB];
-  __shared__ int4 s_box[2][kNB];
+  __shared__ uint2 s_box[2][kNB];             // packed (origin, extent)
   __shared__ __attribute__((aligned(16))) __bf16 s_f[3][kNB][FROW];
   __shared__ __attribute__((aligned(16))) float s_w[2][NT][WROW];
   __shared__ int s_any[2][NW][2];              // the chunk has a nonzero weight in the k step
@@ -386,6 +386,7 @@ __device__ __forceinline__ void fwd_ws_tile(const MfmaArgs& a, const int tile) {
   const int py = (tile / a.tiles_x) * tile_h + q / a.tile_w;
   const bool inside = walker & (px < a.W) & (py < a.H);
   const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+  const u16x2 pp = {(unsigned short)px, (unsigned short)py};
   const uint2 rg = uniform_u2(a.ranges[tile]);
   const int nbatch = (int)((rg.y - rg.x + kNB - 1) / kNB);
   if (threadIdx.x == 0) s_maxlast = 0;
@@ -432,8 +433,7 @@ __device__ __forceinline__ void fwd_ws_tile(const MfmaArgs& a, const int tile) {
       s_co[b2][q] = make_float4(cs.x, cs.y, cs.z, q < nb ? p_co.w : 0.f);
       s_tg[b2][q] = blend_cut(q < nb ? p_co.w : 0.f);
       s_rgb[b2][q] = p_rgb;
-      // (x0, y0, x1 - x0, y1 - y0): one unsigned compare per axis in the walk
-      s_box[b2][q] = make_int4(p_box.x, p_box.y, p_box.z - p_box.x, p_box.w - p_box.y);
+      s_box[b2][q] = pack_box(p_box);
     }
 #pragma unroll
     for (int j = 0; j < FI; ++j) {
@@ -479,10 +479,9 @@ __device__ __forceinline__ void fwd_ws_tile(const MfmaArgs& a, const int tile) {
             const int i = 16 * s + u;
             const float2 m = s_xy[b2][i];
             const float4 co = s_co[b2][i];            // scaled conic, opacity
-            const int4 b = s_box[b2][i];
             const float dx = fpx - m.x, dy = fpy - m.y;
             const float qs = scaled_q(co, dx, dy);
-            const bool inb = ((uint32_t)(px - b.x) <= (uint32_t)b.z) & ((uint32_t)(py - b.y) <= (uint32_t)b.w);
+            const bool inb = in_box(pp, s_box[b2][i]);
             const float alpha = fminf(kAlphaMax, co.w * __builtin_amdgcn_exp2f(qs));
             al[u] = (inb & (qs >= s_tg[b2][i])) ? alpha : 0.f;
             om[u] = 1.0f - al[u];
