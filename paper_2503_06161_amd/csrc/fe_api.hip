@@ -686,21 +686,21 @@ fe_status fe_batch_launch(fe_batch_plan* p, void* stream) {
     hipStream_t cs;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return FE_ERR_HIP;
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-      hipStreamDestroy(cs);
+      (void)hipStreamDestroy(cs);
       return FE_ERR_HIP;
     }
     const fe_status st = batch_enqueue(p, cs, br);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(cs, &graph);
-    hipStreamDestroy(cs);
+    (void)hipStreamDestroy(cs);
     if (st != FE_OK) {
-      if (graph) hipGraphDestroy(graph);
+      if (graph) (void)hipGraphDestroy(graph);
       return st;
     }
     if (e != hipSuccess || !graph) return FE_ERR_HIP;
     hipGraphExec_t exec = nullptr;
     if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-      hipGraphDestroy(graph);
+      (void)hipGraphDestroy(graph);
       return FE_ERR_HIP;
     }
     p->graph = graph;
@@ -717,8 +717,8 @@ fe_status fe_batch_read_report(fe_batch_plan* p, int32_t f, fe_report* out, void
 
 void fe_batch_plan_destroy(fe_batch_plan* p) {
   if (!p) return;
-  if (p->exec) hipGraphExecDestroy(p->exec);
-  if (p->graph) hipGraphDestroy(p->graph);
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
   delete p;
 }
 

@@ -493,7 +493,7 @@ __device__ __forceinline__ bool bucket_rank_sort(const TileSortArgs& a, uint32_t
   uint32_t off = block_exclusive_scan<NW>(sum, s_red + 3 * NW, tot);   // its barriers publish the maxima
 #pragma unroll
   for (int w = 0; w < NW; ++w) big = max(big, s_red[2 * NW + w]);
-  if (__builtin_amdgcn_readfirstlane(big) > (uint32_t)kTsMaxBucket) return false;
+  if ((uint32_t)__builtin_amdgcn_readfirstlane(big) > (uint32_t)kTsMaxBucket) return false;
 #pragma unroll
   for (int k = 0; k < BPL; ++k) {
     if (b0 + k < nb) s_b[b0 + k] = off;
