@@ -80,7 +80,10 @@ def _algorithmic_bytes(stage, n, k, pairs, H, W, D, L, eb):
     if stage == "project_bwd":
         return n * (12 + 12 + 16 + K3 * eb + 36) + n * (12 + 12 + 16 + 4 + K3 * 4)
     if stage == "sort":
-        return 4 * n * 16 + k * 8 + 2 * k * 16 + k * 4
+        # per Gaussian: tile count, pixel box, depth key; per key: placed and read
+        # (8 + 8), sorted Gaussian id and emit position written (8), emit-order
+        # Gaussian id written and gathered (4 + 4)
+        return n * 16 + k * 32
     return 0
 
 
