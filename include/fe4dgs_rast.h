@@ -206,17 +206,19 @@ fe_status fe_state_layout_get(const fe_config* cfg, const fe_camera* cam, int64_
  * row_capacity bounds it. */
 size_t    fe_backward_scratch_bytes(const fe_config* cfg, const fe_camera* cam, int64_t n);
 
-/* Forward render of one camera.  `state` (device, state_bytes >=
- * fe_state_bytes) receives the projected record, the sorted key lists and the
- * report, and must be passed unchanged to fe_render_backward. */
+/* Forward render of one camera.  `state` (device, 256-byte aligned,
+ * state_bytes >= fe_state_bytes) receives the projected record, the sorted key
+ * lists and the report, and must be passed unchanged to fe_render_backward.
+ * A misaligned state returns FE_ERR_INVALID_ARG. */
 fe_status fe_render_forward(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
                             const fe_images* out, void* state, size_t state_bytes, void* stream);
 
 /* Backward of fe_render_forward for upstream gradients d_rgb [3][H][W] and
  * d_feat [D][H][W] (device float32; none flows into final_T / n_contrib).
  * `fwd` must be the images that forward wrote (final_T and n_contrib are
- * read).  `scratch` (device, >= fe_backward_scratch_bytes) holds per-Gaussian
- * screen-space gradients. */
+ * read).  `scratch` (device, 256-byte aligned, >= fe_backward_scratch_bytes)
+ * holds per-Gaussian screen-space gradients; a misaligned scratch returns
+ * FE_ERR_INVALID_ARG. */
 fe_status fe_render_backward(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
                              const fe_images* fwd, const void* state, size_t state_bytes,
                              const float* d_rgb, const float* d_feat, const fe_grads* out,
@@ -261,8 +263,9 @@ size_t fe_batch_workspace_bytes(const fe_config* cfg, const fe_camera* cams, int
  * grads (d_rgb / d_feat / grads may be NULL for FE_MODE_FORWARD; the gradient
  * pointers of a frame with n == 0 may be NULL).  Returns FE_ERR_HIP when the
  * device cannot be queried for the persistent launch size.  The plan
- * owns host memory and HIP graph handles only; `workspace` stays the
- * caller's.  The first fe_batch_launch captures the graph. */
+ * owns host memory and HIP graph handles only; `workspace` (256-byte
+ * aligned, else FE_ERR_INVALID_ARG) stays the caller's.  The first
+ * fe_batch_launch captures the graph. */
 fe_status fe_batch_plan_create(const fe_config* cfg, const fe_camera* cams, int32_t frames,
                                const fe_gaussians* g, const fe_images* out,
                                const float* const* d_rgb, const float* const* d_feat,

@@ -131,7 +131,7 @@ static bool bwd_scratch_layout(const fe_config* cfg, const fe_camera* cam, int64
   if (cfg->variant != FE_VARIANT_VALU) {
     b->row_cap = cfg->row_capacity > 0 ? cfg->row_capacity : cfg->key_capacity;
     b->row_base = take(sizeof(uint32_t) * ((size_t)L.tiles + 1));
-    b->rowidx = take(sizeof(uint32_t) * (size_t)L.cap);
+    b->rowidx = take(sizeof(uint32_t) * (((size_t)L.cap + 3) & ~(size_t)3));   // whole 16-byte groups
     b->rows = take(sizeof(float) * (size_t)backward_row_stride(cfg->feat_dim) * (size_t)b->row_cap);
   }
   b->total = o;
@@ -212,7 +212,7 @@ static BwdBuffers bwd_buffers(const fe_config* cfg, const fe_camera* cam, int64_
 static fe_status backward_pre(const Layout& L, const void* state, const BwdBuffers& b, hipStream_t s) {
   StateView v = make_view(L, const_cast<void*>(state));
   if (launch_scan_u32(v.tile_maxlast, b.row_base, v.tiles, s) != hipSuccess) return FE_ERR_HIP;
-  return hip_status(launch_zero_u32(b.rowidx, (size_t)L.cap, s));
+  return hip_status(launch_zero_keys(b.rowidx, v.report, L.cap, s));
 }
 
 static fe_status backward_post(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g, const Layout& L,
@@ -341,6 +341,7 @@ fe_status fe_render_forward(const fe_config* cfg, const fe_camera* cam, const fe
   if (st != FE_OK) return st;
   if ((st = check_gaussians(cfg, g)) != FE_OK) return st;
   if (!out || !out->rgb || !out->feat || !out->final_T || !out->n_contrib || !state) return FE_ERR_INVALID_ARG;
+  if (reinterpret_cast<uintptr_t>(state) % 256 != 0) return FE_ERR_INVALID_ARG;   // regions are 256-byte aligned
   Layout L;
   compute_layout(cfg, cam, g->n, &L);
   if (state_bytes < L.total) return FE_ERR_WORKSPACE_TOO_SMALL;
@@ -354,7 +355,8 @@ fe_status fe_render_backward(const fe_config* cfg, const fe_camera* cam, const f
   fe_status st = fe_validate(cfg, cam, g ? g->n : -1);
   if (st != FE_OK) return st;
   if ((st = check_gaussians(cfg, g)) != FE_OK) return st;
-  if (!fwd || !fwd->final_T || !fwd->n_contrib || !state || !d_rgb || !d_feat || !out || !scratch)
+  if (!fwd || !fwd->final_T || !fwd->n_contrib || !state || !d_rgb || !d_feat || !out || !scratch ||
+      reinterpret_cast<uintptr_t>(state) % 256 != 0 || reinterpret_cast<uintptr_t>(scratch) % 256 != 0)
     return FE_ERR_INVALID_ARG;
   if (!out->means || !out->scales || !out->quats || !out->opacity || !out->sh || !out->feat)
     return FE_ERR_INVALID_ARG;
@@ -478,6 +480,7 @@ fe_status fe_batch_plan_create(const fe_config* cfg, const fe_camera* cams, int3
   if (!plan) return FE_ERR_INVALID_ARG;
   *plan = nullptr;
   if (!cfg || !cams || frames < 1 || !g || !out || !workspace) return FE_ERR_INVALID_ARG;
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return FE_ERR_INVALID_ARG;
   if (mode != FE_MODE_FORWARD && mode != FE_MODE_BACKWARD && mode != FE_MODE_FORWARD_BACKWARD)
     return FE_ERR_INVALID_ARG;
   const bool bwd = (mode & FE_MODE_BACKWARD) != 0;

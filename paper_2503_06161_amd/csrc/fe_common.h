@@ -118,6 +118,8 @@ CamConst make_cam_const(const fe_camera* cam, const fe_config* cfg);
 
 // ---- launchers (each enqueues on `stream`, returns hipError_t) ----
 hipError_t launch_zero_u32(uint32_t* p, size_t count, hipStream_t s);
+// zeroes the first min(report keys, cap) words; p 16-byte aligned, room for cap rounded up to 4 words
+hipError_t launch_zero_keys(uint32_t* p, const unsigned long long* report, int64_t cap, hipStream_t s);
 hipError_t launch_project_fwd(const CamConst& cc, const fe_config* cfg, const fe_gaussians* g,
                               const StateView& v, hipStream_t s);
 hipError_t launch_sort_and_bin(const fe_config* cfg, const StateView& v, hipStream_t s);
