@@ -87,6 +87,16 @@ def test_forward_rejects_bad_arguments_before_any_gpu_work():
     st = lib.fe_render_forward(C.byref(cfg), C.byref(cam), C.byref(g), C.byref(im), None, 0, None)
     assert st == rast.FE_ERR_INVALID_ARG
     assert lib.fe_render_forward(None, C.byref(cam), C.byref(g), C.byref(im), None, 0, None) == rast.FE_ERR_INVALID_ARG
+    # a state buffer that is not 256-byte aligned is refused before anything
+    # is launched (the pointers are never dereferenced on this path)
+    fake = 1 << 20
+    g = rast.fe_gaussians(10, fake, fake, fake, fake, fake, fake)
+    im = rast.fe_images(fake, fake, fake, fake)
+    big = lib.fe_state_bytes(C.byref(cfg), C.byref(cam), 10) + 512
+    assert lib.fe_render_forward(C.byref(cfg), C.byref(cam), C.byref(g), C.byref(im),
+                                 C.c_void_p(fake + 16), big, None) == rast.FE_ERR_INVALID_ARG
+    assert lib.fe_render_forward(C.byref(cfg), C.byref(cam), C.byref(g), C.byref(im),
+                                 C.c_void_p(fake), 16, None) == rast.FE_ERR_WORKSPACE_TOO_SMALL
     rep = rast.fe_report()
     assert lib.fe_read_report(None, 0, C.byref(rep), None) == rast.FE_ERR_INVALID_ARG
     assert lib.fe_status_string(rast.FE_ERR_KEY_OVERFLOW) == b"sort key capacity exceeded"
