@@ -118,8 +118,11 @@ CamConst make_cam_const(const fe_camera* cam, const fe_config* cfg);
 
 // ---- launchers (each enqueues on `stream`, returns hipError_t) ----
 hipError_t launch_zero_u32(uint32_t* p, size_t count, hipStream_t s);
-// zeroes the first min(report keys, cap) words; p 16-byte aligned, room for cap rounded up to 4 words
-hipError_t launch_zero_keys(uint32_t* p, const unsigned long long* report, int64_t cap, hipStream_t s);
+// row offsets per tile (exclusive scan of the walk lengths) and cleared row
+// indices for the frame's keys; rowidx 16-byte aligned with room for cap
+// rounded up to 4 words
+hipError_t launch_backward_prep(const uint32_t* walk, uint32_t* row_base, int64_t tiles, uint32_t* rowidx,
+                                const unsigned long long* report, int64_t cap, hipStream_t s);
 hipError_t launch_project_fwd(const CamConst& cc, const fe_config* cfg, const fe_gaussians* g,
                               const StateView& v, hipStream_t s);
 hipError_t launch_sort_and_bin(const fe_config* cfg, const StateView& v, hipStream_t s);
@@ -130,7 +133,6 @@ hipError_t launch_composite_fwd_mfma(const fe_config* cfg, const fe_camera* cam,
 hipError_t launch_composite_bwd(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
                                 const StateView& v, const fe_images* fwd, const float* d_rgb,
                                 const float* d_feat, float* grad2d, float* grad_feat, hipStream_t s);
-hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s);
 int backward_row_stride(int D);
 hipError_t launch_composite_bwd_mfma(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
                                      const StateView& v, const fe_images* fwd, const float* d_rgb,

@@ -35,18 +35,6 @@ __global__ void zero_u32_kernel(uint32_t* p, size_t count) {
   for (; i < count; i += stride) p[i] = 0u;
 }
 
-// Zeroes the first min(keys, cap) words of a 16-byte aligned array, keys read
-// from the report (the key count is known on the device only), 16 bytes per
-// store.
-__global__ void zero_keys_kernel(uint4* p, const unsigned long long* report, int64_t cap) {
-  const unsigned long long k = report[kRepKeys];
-  const size_t n = k > (unsigned long long)cap ? 0 : (size_t)k;
-  const size_t n4 = (n + 3) / 4;   // whole 16-byte groups covering n (cap is padded to them)
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (; i < n4; i += stride) p[i] = make_uint4(0u, 0u, 0u, 0u);
-}
-
 // ---- block-wide exclusive scan (NW waves of 64 lanes) ----
 template <int NW>
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_warp, uint32_t& total) {
@@ -75,7 +63,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
 // arrays, a few thousand entries) ----
 constexpr int kScanWg = 1024;
 
-__global__ __launch_bounds__(kScanWg) void scan_small_kernel(const uint32_t* in, uint32_t* out, int64_t n) {
+__device__ __forceinline__ void scan_small(const uint32_t* in, uint32_t* out, int64_t n) {
   __shared__ uint32_t s_warp[kScanWg / 64];
   constexpr int per = 4;
   uint32_t carry = 0;
@@ -96,6 +84,24 @@ __global__ __launch_bounds__(kScanWg) void scan_small_kernel(const uint32_t* in,
     }
     carry += step;
   }
+}
+
+// Backward preparation in one launch: workgroup 0 scans the per-tile walk
+// lengths into row offsets; the others clear the row index of every key of
+// the frame (min(report keys, cap) words, 16 bytes per store; nothing reads
+// the words past the key count).
+__global__ __launch_bounds__(kScanWg) void backward_prep_kernel(const uint32_t* walk, uint32_t* row_base, int64_t tiles,
+                                                                uint4* rowidx, const unsigned long long* report,
+                                                                int64_t cap) {
+  if (blockIdx.x == 0) {
+    scan_small(walk, row_base, tiles);
+    return;
+  }
+  const unsigned long long k = report[kRepKeys];
+  const size_t n4 = ((k > (unsigned long long)cap ? 0 : (size_t)k) + 3) / 4;
+  size_t i = (size_t)(blockIdx.x - 1) * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)(gridDim.x - 1) * blockDim.x;
+  for (; i < n4; i += stride) rowidx[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
 // ---- binning ----
@@ -659,18 +665,12 @@ __global__ __launch_bounds__(1024) void build_tile_queue_kernel(TileQueueBuild b
 
 }  // namespace
 
-hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(scan_small_kernel, dim3(1), dim3(kScanWg), 0, s, in, out, n);
-  return hipGetLastError();
-}
-
-hipError_t launch_zero_keys(uint32_t* p, const unsigned long long* report, int64_t cap, hipStream_t s) {
-  if (cap <= 0) return hipSuccess;
-  size_t blocks = ((size_t)cap / 4 + 255) / 256 + 1;
-  if (blocks > 2048) blocks = 2048;
-  hipLaunchKernelGGL(zero_keys_kernel, dim3((unsigned)blocks), dim3(256), 0, s, reinterpret_cast<uint4*>(p), report,
-                     cap);
+hipError_t launch_backward_prep(const uint32_t* walk, uint32_t* row_base, int64_t tiles, uint32_t* rowidx,
+                                const unsigned long long* report, int64_t cap, hipStream_t s) {
+  size_t zb = ((size_t)(cap > 0 ? cap : 0) / 4 + kScanWg - 1) / kScanWg;
+  if (zb > 512) zb = 512;
+  hipLaunchKernelGGL(backward_prep_kernel, dim3((unsigned)(1 + zb)), dim3(kScanWg), 0, s, walk, row_base, tiles,
+                     reinterpret_cast<uint4*>(rowidx), report, cap);
   return hipGetLastError();
 }
 
