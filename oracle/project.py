@@ -216,9 +216,13 @@ def project(means, scales, quats, opacity, sh, cam, cfg: OracleConfig, sh_degree
 
 def round_projected(p: dict, to=torch.float32) -> dict:
     """Round the projected record to float32 once (the precision boundary of
-    the GPU path); gradients pass through the rounding unchanged."""
+    the GPU path); gradients pass through the rounding unchanged.
+
+    The rounding is added as a constant (detached) correction, so its
+    derivative is exactly the identity: a plain dtype cast would also round
+    the incoming gradient to float32 on the way back."""
     out = dict(p)
-    for k in ("xy", "conic", "rgb", "depth"):
-        out[k] = p[k].to(to).to(F64)
-    out["opacity"] = p["opacity"].to(to).to(F64)
+    for k in ("xy", "conic", "rgb", "depth", "opacity"):
+        x = p[k]
+        out[k] = x + (x.detach().to(to).to(F64) - x.detach())
     return out

@@ -211,3 +211,84 @@ def test_ambiguity_variants_cover_both_branches():
     vs = pixel_variants(i, j, out["proj"], g["feat"], out["lists"], out["cam"], out["cfg"], out["near"][tile])
     fe = sorted(v[1][0] for v in vs)
     assert fe[0] == 0.0 and fe[-1] > 0.0
+
+
+def _variants_at(out, g, i, j, tile=8):
+    t = (j // tile) * out["lists"].tiles_x + i // tile
+    vs = pixel_variants(i, j, out["proj"], g["feat"], out["lists"], out["cam"], out["cfg"], out["near"][t])
+    assert vs is not None
+    return sorted(vs, key=lambda v: v[2])      # by final transmittance
+
+
+def test_ambiguity_variants_alpha_branch():
+    # alpha exactly at the 1/255 skip threshold (Gaussian centred on pixel
+    # (4, 4), opacity 1/255): one outcome includes it, the other skips it
+    c = cam(8, 8, f=40.0, cx=4.5, cy=4.5)
+    col, fv = [0.8, 0.5, 0.2], [2.0, -1.0]
+    g = gaussians([[0, 0, 2.0]], [[0.02, 0.02, 0.02]], opacity=1.0 / 255.0, colors=col, feat=[fv])
+    bg = (0.1, 0.2, 0.3)
+    out = render_forward(**g, cam=c, cfg=cfg(tile=8, bg=bg), parity=True, amb_delta=(1e-5, 1e-5, 1e-5))
+    amb = out["ambiguous"].numpy()
+    assert amb[4, 4] and amb.sum() == 1
+    near = out["near"][0][2]
+    assert near["a"].any() and not near["q"].any() and not near["t"].any()
+    vs = _variants_at(out, g, 4, 4)
+    assert len(vs) == 2
+    a = float(np.float32(1.0 / 255.0))
+    # the projected colour (pinned by the SH tests), as the blend sees it
+    col32 = out["proj"]["rgb"][0].numpy()
+    np.testing.assert_allclose(col32, col, rtol=1e-6)
+    bg32 = np.asarray([float(np.float32(b)) for b in bg])
+    (r_in, f_in, T_in, n_in), (r_sk, f_sk, T_sk, n_sk) = vs
+    np.testing.assert_allclose(r_in, a * col32 + (1 - a) * bg32, rtol=1e-12)
+    np.testing.assert_allclose(f_in, a * np.asarray(fv), rtol=1e-12)
+    assert abs(T_in - (1 - a)) < 1e-15 and n_in == 1
+    np.testing.assert_allclose(r_sk, bg32, rtol=1e-15)
+    assert np.all(f_sk == 0) and T_sk == 1.0 and n_sk == 0
+
+
+def test_ambiguity_variants_stop_branch():
+    # two Gaussians centred on pixel (4, 4), both clamped at alpha = 0.99:
+    # the transmittance after the second is 0.01^2, at the 1e-4 stop
+    # threshold; one outcome blends both, the other stops before the second
+    c = cam(8, 8, f=40.0, cx=4.5, cy=4.5)
+    c1, c2 = [0.9, 0.1, 0.4], [0.2, 0.7, 0.6]
+    g = gaussians([[0, 0, 2.0], [0, 0, 2.5]], [[0.05, 0.05, 0.05]], opacity=0.995, colors=[c1, c2],
+                  feat=[[1.0, 0.0], [0.0, 1.0]])
+    out = render_forward(**g, cam=c, cfg=cfg(tile=8), parity=True, amb_delta=(1e-5, 1e-5, 1e-5))
+    amb = out["ambiguous"].numpy()
+    assert amb[4, 4] and amb.sum() == 1
+    near = out["near"][0][2]
+    assert near["t"].any() and not near["a"].any()
+    vs = _variants_at(out, g, 4, 4)
+    assert len(vs) == 2
+    k1, k2 = out["proj"]["rgb"][0].numpy(), out["proj"]["rgb"][1].numpy()
+    np.testing.assert_allclose(k1, c1, rtol=1e-6)
+    np.testing.assert_allclose(k2, c2, rtol=1e-6)
+    a, t1 = 0.99, 1.0 - 0.99
+    (r_both, f_both, T_both, n_both), (r_stop, f_stop, T_stop, n_stop) = vs
+    np.testing.assert_allclose(r_both, a * k1 + t1 * a * k2, rtol=1e-12)
+    np.testing.assert_allclose(f_both, [a, t1 * a], rtol=1e-12)
+    assert abs(T_both - t1 * t1) < 1e-18 and n_both == 2
+    np.testing.assert_allclose(r_stop, a * k1, rtol=1e-12)
+    np.testing.assert_allclose(f_stop, [a, 0.0], rtol=1e-12, atol=0)
+    assert abs(T_stop - t1) < 1e-16 and n_stop == 1
+
+
+def test_round_projected_is_one_float32_rounding_with_identity_gradient():
+    from oracle.project import round_projected
+    rng = np.random.default_rng(3)
+    vals = {k: torch.tensor(rng.normal(0, 50, shape), dtype=torch.float64, requires_grad=True)
+            for k, shape in (("xy", (7, 2)), ("conic", (7, 3)), ("rgb", (7, 3)), ("depth", (7,)), ("opacity", (7,)))}
+    box = torch.tensor(rng.integers(0, 9, (7, 4)))
+    p = dict(vals, box=box, n=7)
+    r = round_projected(p)
+    for k, v in vals.items():
+        # numpy's float64 -> float32 cast rounds to nearest, ties to even
+        np.testing.assert_array_equal(r[k].detach().numpy(), v.detach().numpy().astype(np.float32).astype(np.float64))
+        assert r[k].dtype == torch.float64
+    assert r["box"] is box and r["n"] == 7
+    w = {k: torch.tensor(rng.normal(size=tuple(v.shape)), dtype=torch.float64) for k, v in vals.items()}
+    sum((r[k] * w[k]).sum() for k in vals).backward()
+    for k, v in vals.items():
+        assert torch.equal(v.grad, w[k])        # the rounding passes gradients through unchanged
