@@ -107,7 +107,7 @@ def run_form(sc, form, steps, warmup, variant="mfma"):
         nonlocal fwd, grads, scratch
         st.stage_events = events
         f = rast.render_forward(*args, sc.cam, st, check=False, state=fwd.state, out=out)
-        g = rast.render_backward(f, *args, d_rgb, d_feat, st, grads=grads, scratch=scratch)
+        g = rast.render_backward(f, *args, d_rgb, d_feat, st, grads=grads, scratch=scratch, check=False)
         fwd, grads, scratch = f, g, g["_scratch"]
 
     for _ in range(warmup):

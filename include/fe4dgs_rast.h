@@ -2,7 +2,7 @@
  * fe4dgs_rast.h -- C ABI of the MI355X (gfx950) tile rasterizer for
  * feature-distilled 4D Gaussian splatting (FeatureEndo-4DGS).
  *
- * What the library computes (the paper's Sec. 3.4, "Differentiable Rendering
+ * What the library computes (the paper's Sec. 3.3, "Differentiable Rendering
  * and Loss Functions", and Sec. 3.1):
  *   - each deformed Gaussian G_t (eq. 6) is projected: Sigma = R S S^T R^T
  *     (eq. 2) and Sigma' = J W Sigma W^T J^T (eq. 9), plus a 0.3 px^2
@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define FE4DGS_ABI_VERSION 2
+#define FE4DGS_ABI_VERSION 3
 
 typedef enum fe_status {
   FE_OK = 0,
@@ -159,8 +159,12 @@ typedef struct fe_grads {
 
 /* Device-side report, read back with fe_read_report(). */
 typedef struct fe_report {
-  int32_t status;                /* FE_OK or FE_ERR_KEY_OVERFLOW                */
-  int32_t reserved;
+  int32_t status;                /* the forward's status (FE_OK or
+                                    FE_ERR_KEY_OVERFLOW) if it is not FE_OK,
+                                    else backward_status                       */
+  int32_t backward_status;       /* the last backward of this state: FE_OK or
+                                    FE_ERR_ROW_OVERFLOW (cleared when a
+                                    backward starts, and by a new forward)     */
   int64_t keys_needed;           /* number of (tile, Gaussian) keys the frame has */
   int64_t n_visible;             /* Gaussians that emitted at least one key     */
   int64_t n_culled_nonfinite;    /* Gaussians culled for non-finite parameters  */

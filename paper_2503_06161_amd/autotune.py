@@ -65,7 +65,7 @@ def time_candidate(g: dict, cam, st: rast.Settings, d_rgb=None, d_feat=None, rep
         e0.record()
         f = rast.render_forward(*args, cam, st2, check=False, state=fwd.state, out=out)
         if d_rgb is not None:
-            grads = rast.render_backward(f, *args, d_rgb, d_feat, st2, grads=grads, scratch=scratch)
+            grads = rast.render_backward(f, *args, d_rgb, d_feat, st2, grads=grads, scratch=scratch, check=False)
             scratch = grads["_scratch"]
         e1.record()
         torch.cuda.synchronize()

@@ -373,8 +373,8 @@ fe_status fe_read_report(const void* state, size_t state_bytes, fe_report* out, 
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (hipMemcpyAsync(w, state, sizeof(w), hipMemcpyDeviceToHost, s) != hipSuccess) return FE_ERR_HIP;
   if (hipStreamSynchronize(s) != hipSuccess) return FE_ERR_HIP;
-  out->status = (int32_t)w[kRepStatus];
-  out->reserved = 0;
+  out->status = (int32_t)(w[kRepStatus] != 0 ? w[kRepStatus] : w[kRepBwdStatus]);
+  out->backward_status = (int32_t)w[kRepBwdStatus];
   out->keys_needed = (int64_t)w[kRepKeys];
   out->n_visible = (int64_t)w[kRepVisible];
   out->n_culled_nonfinite = (int64_t)w[kRepNonFinite];

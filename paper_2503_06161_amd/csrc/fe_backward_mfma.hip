@@ -145,7 +145,7 @@ __device__ __forceinline__ void bwd_mfma_tile(const BwdArgs& a, const int tile) 
   const int walk_all = __builtin_amdgcn_readfirstlane((int)min(a.tile_maxlast[tile], rg.y - rg.x));
   const int64_t row0 = uniform_i64(a.row_base[tile]);
   const bool overflow = __builtin_amdgcn_readfirstlane((int)(row0 + walk_all > a.row_cap));
-  if (overflow && threadIdx.x == 0) a.report[kRepStatus] = (unsigned long long)FE_ERR_ROW_OVERFLOW;
+  if (overflow && threadIdx.x == 0) a.report[kRepBwdStatus] = (unsigned long long)FE_ERR_ROW_OVERFLOW;
   // nothing of an overflowing tile can be stored: it is walked as empty.  The
   // per-tile kernel leaves empty tiles at once; inside the persistent loop the
   // tile keeps a single exit (empty tiles are not queued there).
@@ -643,7 +643,7 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
   const int walk_all = __builtin_amdgcn_readfirstlane((int)min(a.tile_maxlast[tile], rg.y - rg.x));
   const int64_t row0 = uniform_i64(a.row_base[tile]);
   const bool overflow = __builtin_amdgcn_readfirstlane((int)(row0 + walk_all > a.row_cap));
-  if (overflow && threadIdx.x == 0) a.report[kRepStatus] = (unsigned long long)FE_ERR_ROW_OVERFLOW;
+  if (overflow && threadIdx.x == 0) a.report[kRepBwdStatus] = (unsigned long long)FE_ERR_ROW_OVERFLOW;
   // nothing of an overflowing tile can be stored: it is walked as empty.  The
   // per-tile kernel leaves empty tiles at once; inside the persistent loop the
   // tile keeps a single exit (empty tiles are not queued there).
@@ -1250,7 +1250,7 @@ template <int LPG, int GPL, int NG>
 __global__ __launch_bounds__(256) void reduce_rows_kernel(ReduceArgs a) {
   const int sub = threadIdx.x & (LPG - 1);
   const int64_t g0 = (((int64_t)blockIdx.x * 256 + threadIdx.x) / LPG) * NG;
-  const bool ok = a.report[kRepStatus] == 0ull;
+  const bool ok = a.report[kRepStatus] == 0ull && a.report[kRepBwdStatus] == 0ull;
   uint32_t cnt[NG], e0[NG], ri0[NG];
 #pragma unroll
   for (int k = 0; k < NG; ++k) {

@@ -10,7 +10,7 @@
 
 namespace fe {
 
-// Blending rules (Sec. 3.4 with the thresholds of the hot-path definition).
+// Blending rules (Sec. 3.3, eqs. 7-8, with the alpha thresholds of this rasterizer).
 constexpr float kAlphaMax = 0.99f;
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kTStop = 1e-4f;
@@ -61,7 +61,11 @@ constexpr int kBinOffThreads = 1024;
 constexpr int64_t kMaxGaussians = int64_t(1) << 23;
 
 // Report words (unsigned long long) at StateView::report.
-enum ReportWord { kRepStatus = 0, kRepKeys = 1, kRepVisible = 2, kRepNonFinite = 3, kRepRows = 4, kRepWords = 8 };
+// kRepStatus is the forward's status (key overflow); kRepBwdStatus the last
+// backward's (row overflow), cleared when a backward starts.
+enum ReportWord {
+  kRepStatus = 0, kRepKeys = 1, kRepVisible = 2, kRepNonFinite = 3, kRepRows = 4, kRepBwdStatus = 5, kRepWords = 8
+};
 
 // Device pointers into one frame's forward state plus its derived sizes.
 struct StateView {
@@ -122,7 +126,7 @@ hipError_t launch_zero_u32(uint32_t* p, size_t count, hipStream_t s);
 // indices for the frame's keys; rowidx 16-byte aligned with room for cap
 // rounded up to 4 words
 hipError_t launch_backward_prep(const uint32_t* walk, uint32_t* row_base, int64_t tiles, uint32_t* rowidx,
-                                const unsigned long long* report, int64_t cap, hipStream_t s);
+                                unsigned long long* report, int64_t cap, hipStream_t s);
 hipError_t launch_project_fwd(const CamConst& cc, const fe_config* cfg, const fe_gaussians* g,
                               const StateView& v, hipStream_t s);
 hipError_t launch_sort_and_bin(const fe_config* cfg, const StateView& v, hipStream_t s);

@@ -1,5 +1,5 @@
 // Binning of projected Gaussians into per-tile lists in depth order
-// (Sec. 3.4: every Gaussian joins the list of each tile its 3-sigma box
+// (Sec. 3.3: every Gaussian joins the list of each tile its 3-sigma box
 // touches, and a tile blends its list front to back).
 //
 // Order of work (integer only):
@@ -86,14 +86,15 @@ __device__ __forceinline__ void scan_small(const uint32_t* in, uint32_t* out, in
   }
 }
 
-// Backward preparation in one launch: workgroup 0 scans the per-tile walk
-// lengths into row offsets; the others clear the row index of every key of
-// the frame (min(report keys, cap) words, 16 bytes per store; nothing reads
-// the words past the key count).
+// Backward preparation in one launch: workgroup 0 clears the backward's
+// status word and scans the per-tile walk lengths into row offsets; the others
+// clear the row index of every key of the frame (min(report keys, cap) words,
+// 16 bytes per store; nothing reads the words past the key count).
 __global__ __launch_bounds__(kScanWg) void backward_prep_kernel(const uint32_t* walk, uint32_t* row_base, int64_t tiles,
-                                                                uint4* rowidx, const unsigned long long* report,
+                                                                uint4* rowidx, unsigned long long* report,
                                                                 int64_t cap) {
   if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) report[kRepBwdStatus] = 0ull;
     scan_small(walk, row_base, tiles);
     return;
   }
@@ -666,8 +667,11 @@ __global__ __launch_bounds__(1024) void build_tile_queue_kernel(TileQueueBuild b
 }  // namespace
 
 hipError_t launch_backward_prep(const uint32_t* walk, uint32_t* row_base, int64_t tiles, uint32_t* rowidx,
-                                const unsigned long long* report, int64_t cap, hipStream_t s) {
-  size_t zb = ((size_t)(cap > 0 ? cap : 0) / 4 + kScanWg - 1) / kScanWg;
+                                unsigned long long* report, int64_t cap, hipStream_t s) {
+  // clearing workgroups: one 16-byte group per thread over ceil(cap / 4)
+  // groups, at least one whenever there is any key slot
+  const size_t groups = ((size_t)(cap > 0 ? cap : 0) + 3) / 4;
+  size_t zb = (groups + kScanWg - 1) / kScanWg;
   if (zb > 512) zb = 512;
   hipLaunchKernelGGL(backward_prep_kernel, dim3((unsigned)(1 + zb)), dim3(kScanWg), 0, s, walk, row_base, tiles,
                      reinterpret_cast<uint4*>(rowidx), report, cap);

@@ -62,7 +62,7 @@ class fe_grads(C.Structure):
 
 
 class fe_report(C.Structure):
-    _fields_ = [("status", C.c_int32), ("reserved", C.c_int32), ("keys_needed", C.c_int64),
+    _fields_ = [("status", C.c_int32), ("backward_status", C.c_int32), ("keys_needed", C.c_int64),
                 ("n_visible", C.c_int64), ("n_culled_nonfinite", C.c_int64), ("rows_needed", C.c_int64)]
 
 
@@ -111,7 +111,7 @@ def load_library(path: str = LIB_PATH):
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
-    if lib.fe_abi_version() != 2:
+    if lib.fe_abi_version() != 3:
         raise ImportError("libfe4dgs_rast.so ABI version mismatch")
     _lib = lib
     return lib
@@ -233,8 +233,8 @@ def read_report(state: torch.Tensor, stream=None) -> dict:
     lib = load_library()
     r = fe_report()
     lib.fe_read_report(C.c_void_p(state.data_ptr()), state.numel(), C.byref(r), C.c_void_p(_stream_handle(stream)))
-    return dict(status=r.status, keys_needed=r.keys_needed, n_visible=r.n_visible,
-                n_culled_nonfinite=r.n_culled_nonfinite, rows_needed=r.rows_needed)
+    return dict(status=r.status, backward_status=r.backward_status, keys_needed=r.keys_needed,
+                n_visible=r.n_visible, n_culled_nonfinite=r.n_culled_nonfinite, rows_needed=r.rows_needed)
 
 
 def state_layout(cam, st: Settings, n: int, cap: int) -> dict:
@@ -289,8 +289,11 @@ def render_forward(means, scales, quats, opacity, sh, feat, cam, st: Settings, c
 
 def render_backward(fwd: ForwardResult, means, scales, quats, opacity, sh, feat, d_rgb, d_feat,
                     st: Settings, stream=None, grads: dict | None = None, scratch: torch.Tensor | None = None,
-                    want_means2d: bool = False) -> dict:
-    """Gradients of <d_rgb, rgb> + <d_feat, feat> for every input (float32)."""
+                    want_means2d: bool = False, check: bool = True) -> dict:
+    """Gradients of <d_rgb, rgb> + <d_feat, feat> for every input (float32).
+    With ``check`` the report is read back (one stream synchronisation) and a
+    backward that ran out of partial rows (a ``row_capacity`` below the
+    frame's need) raises instead of returning invalid gradients."""
     lib = load_library()
     n = means.shape[0]
     dev = means.device
@@ -323,6 +326,12 @@ def render_backward(fwd: ForwardResult, means, scales, quats, opacity, sh, feat,
                                   C.c_void_p(scratch.data_ptr()), scratch.numel(),
                                   C.c_void_p(_stream_handle(stream))), "fe_render_backward")
     grads["_scratch"] = scratch
+    if check:
+        rep = read_report(fwd.state, stream)
+        if rep["backward_status"] == FE_ERR_ROW_OVERFLOW:
+            raise RasterError(FE_ERR_ROW_OVERFLOW, f"fe_render_backward needs {rep['rows_needed']} rows, "
+                                                   f"row_capacity is {cfg.row_capacity}")
+        _check(rep["status"], "fe_render_backward (device)")
     return grads
 
 

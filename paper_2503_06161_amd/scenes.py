@@ -6,8 +6,9 @@ from it.  The activations that the paper leaves to the optimiser (scales are
 stored in log space, opacities as logits) are applied here, because the
 rasterizer consumes linear scales and opacities in (0, 1).
 
-Five workloads are defined (sizes follow the paper: 640x512 frames (Sec. 4.1,
-EndoVis18), 128 semantic channels (Sec. 3.3), 30k-90k initial points and
+Five workloads are defined (sizes follow the paper: 640x512 frames (appendix
+"Dataset Details", EndoVis18), 128 semantic channels (Sec. 3.2, "Semantic
+Feature Extraction"), 30k-90k initial points and
 about 1e5 Gaussians in a trained scene (hyper-parameter table)):
 
 * ``small``   128x128, 2,000 Gaussians, SH degree 0, D=8, forward only.

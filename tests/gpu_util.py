@@ -166,3 +166,31 @@ def normwise(a, b):
     a = np.asarray(a, np.float64).reshape(-1)
     b = np.asarray(b, np.float64).reshape(-1)
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+GRAD_KEYS = ("means", "scales", "quats", "opacity", "sh", "feat")
+
+
+def grad_errors(g, o):
+    """(normwise L2 relative, max |g - o| / max |o|) of one gradient group;
+    a group whose reference is exactly zero must be zero too."""
+    g = np.asarray(g.detach().double().cpu().numpy() if isinstance(g, torch.Tensor) else g, np.float64).reshape(-1)
+    o = np.asarray(o, np.float64).reshape(-1)
+    ref = np.abs(o).max() if o.size else 0.0
+    if ref == 0.0:
+        return (0.0, 0.0) if not np.abs(g).max(initial=0.0) else (np.inf, np.inf)
+    return normwise(g, o), float(np.abs(g - o).max() / ref)
+
+
+def check_grads(gr, ob, keys=GRAD_KEYS, tol=1e-4, tol_inf=1e-4):
+    """Every gradient group against the oracle: normwise L2 relative error
+    below ``tol`` and the largest element error below ``tol_inf`` times the
+    group's largest reference magnitude (a few wrong Gaussians with small
+    gradients cannot hide in the norm)."""
+    errs = {}
+    for k in keys:
+        nw, inf = grad_errors(gr[k], ob[k])
+        errs[k] = (nw, inf)
+        assert nw < tol and inf < tol_inf, (k, nw, inf)
+    print("[grads] normwise / max-element:", {k: (f"{a:.2e}", f"{b:.2e}") for k, (a, b) in errs.items()}, flush=True)
+    return errs

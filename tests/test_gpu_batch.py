@@ -120,25 +120,39 @@ def test_batched_with_an_empty_frame(tile):
     br.close()
 
 
-def test_batched_frame_matches_oracle():
-    say("batched frame vs oracle")
-    sc, fr, frames, cams = _frames(n_frames=2, pool=8_000, w=96, h=80)
-    st = rast.Settings(sh_degree=3, feat_dim=64, sh_dtype="bf16", feat_dtype="bf16")
-    br = BatchRenderer(frames, cams, st, rast.FE_MODE_FORWARD)
-    br.launch()
-    torch.cuda.synchronize()
-    import copy
-    for k, f in enumerate(fr):
-        s2 = copy.copy(sc)
-        n = f["n"]
-        s2.means, s2.scales, s2.quats, s2.opacity = f["means"], sc.scales[:n], sc.quats[:n], sc.opacity[:n]
-        s2.sh, s2.feat, s2.cam = sc.sh[:n], sc.feat[:n], cams[k]
-        orc = U.oracle_forward(s2, st, cam=cams[k])
+@pytest.mark.parametrize("tile", [(16, 16), (16, 8)])
+def test_batched_frames_match_oracle(tile):
+    """Forward images and backward gradients of every frame of one graph
+    replay against the FP64 oracle.  At D = 64, 16x16 tiles use the
+    single-role persistent backward, 16x8 tiles the wave-specialized one."""
+    say("batched frames vs oracle, forward and backward, tile", tile)
+    sc, fr, frames, cams = _frames(n_frames=3, pool=8_000, w=96, h=80)
+    st = rast.Settings(sh_degree=3, feat_dim=64, sh_dtype="bf16", feat_dtype="bf16", tile_w=tile[0],
+                       tile_h=tile[1], variant=rast.FE_VARIANT_MFMA)
+    rng = np.random.default_rng(7)
+    H, W = cams[0].height, cams[0].width
+    d_rgb = [rng.normal(0, 1, (3, H, W)).astype(np.float32) for _ in frames]
+    d_feat = [rng.normal(0, 1, (64, H, W)).astype(np.float32) for _ in frames]
+    br = BatchRenderer(frames, cams, st, rast.FE_MODE_FORWARD_BACKWARD,
+                       [torch.from_numpy(x).cuda() for x in d_rgb], [torch.from_numpy(x).cuda() for x in d_feat])
+    for rep in range(2):
+        br.launch()
+        torch.cuda.synchronize()
+        import copy
+        for k, f in enumerate(fr):
+            assert br.report(k)["status"] == 0
+            s2 = copy.copy(sc)
+            n = f["n"]
+            s2.means, s2.scales, s2.quats, s2.opacity = f["means"], sc.scales[:n], sc.quats[:n], sc.opacity[:n]
+            s2.sh, s2.feat, s2.cam = sc.sh[:n], sc.feat[:n], cams[k]
+            orc = U.oracle_forward(s2, st, cam=cams[k])
 
-        class F:
-            pass
-        fw = F()
-        fw.rgb, fw.feat, fw.final_T, fw.n_contrib = (br.out[k]["rgb"], br.out[k]["feat"], br.out[k]["final_T"],
-                                                     br.out[k]["n_contrib"])
-        say("frame", k, U.compare_images(fw, orc, s2, st))
+            class F:
+                pass
+            fw = F()
+            fw.rgb, fw.feat, fw.final_T, fw.n_contrib = (br.out[k]["rgb"], br.out[k]["feat"], br.out[k]["final_T"],
+                                                         br.out[k]["n_contrib"])
+            say("replay", rep, "frame", k, U.compare_images(fw, orc, s2, st))
+            ob = U.oracle_backward(s2, st, d_rgb[k], d_feat[k], cam=cams[k])
+            U.check_grads(br.grads[k], ob)
     br.close()

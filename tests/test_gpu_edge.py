@@ -79,14 +79,57 @@ def test_key_overflow_is_reported_not_truncated(variant):
 
 def test_row_overflow_is_reported():
     say("row overflow")
-    sc = _small(n=500)
+    sc = _small(n=500, grads=True)
     st = U.settings_for(sc, variant=rast.FE_VARIANT_MFMA, row_capacity=3)
     fwd, d = U.gpu_forward(sc, st)
-    rast.render_backward(fwd, d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["feat"],
-                         torch.ones(3, 128, 128, device="cuda"), torch.ones(sc.feat_dim, 128, 128, device="cuda"),
-                         st)
+    args = (d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["feat"])
+    rng = np.random.default_rng(8)
+    d_rgb = rng.normal(0, 1, (3, 128, 128)).astype(np.float32)
+    d_feat = rng.normal(0, 1, (sc.feat_dim, 128, 128)).astype(np.float32)
+    gd_rgb, gd_feat = torch.from_numpy(d_rgb).cuda(), torch.from_numpy(d_feat).cuda()
+    with pytest.raises(rast.RasterError) as e:
+        rast.render_backward(fwd, *args, gd_rgb, gd_feat, st)
+    assert e.value.status == rast.FE_ERR_ROW_OVERFLOW
     rep = rast.read_report(fwd.state)
-    assert rep["status"] == rast.FE_ERR_ROW_OVERFLOW and rep["rows_needed"] > 3
+    assert rep["backward_status"] == rast.FE_ERR_ROW_OVERFLOW and rep["rows_needed"] > 3
+    # a second backward of the same forward state with enough rows clears the
+    # status and returns the oracle's gradients
+    st.row_capacity = None
+    gr = rast.render_backward(fwd, *args, gd_rgb, gd_feat, st)
+    rep = rast.read_report(fwd.state)
+    assert rep["status"] == 0 and rep["backward_status"] == 0
+    ob = U.oracle_backward(sc, st, d_rgb, d_feat)
+    U.check_grads(gr, ob)
+
+
+@pytest.mark.parametrize("cap_extra", [0, 1, 3])
+def test_tiny_key_capacity_with_dirty_scratch(cap_extra):
+    # key_capacity 1..4 (the frame's exact need plus a little) and a scratch
+    # buffer filled with 0xFF: the backward must clear every row index it reads
+    say("tiny key capacity, dirty scratch, cap_extra", cap_extra)
+    sc = make_scene("small", seed=21, n=1, grads=True)
+    sc.means[0] = (0.0, 0.0, 4.0)
+    sc.scales[0] = (0.06, 0.035, 0.045)          # anisotropic and rotated: every group has a gradient
+    sc.quats[0] = (0.9, 0.2, -0.3, 0.25)
+    cam = crop_camera(sc.cam, 56, 56, 16, 16)        # one tile, the Gaussian in the middle
+    sc.cam = cam
+    st = U.settings_for(sc, variant=rast.FE_VARIANT_MFMA)
+    fwd, d = U.gpu_forward(sc, st, cam=cam)
+    need = int(fwd.report["keys_needed"])
+    assert need == 1
+    st.key_capacity = need + cap_extra
+    fwd, d = U.gpu_forward(sc, st, cam=cam, dev_in=d)
+    rng = np.random.default_rng(9)
+    d_rgb = rng.normal(0, 1, (3, 16, 16)).astype(np.float32)
+    d_feat = rng.normal(0, 1, (sc.feat_dim, 16, 16)).astype(np.float32)
+    cfg = rast.fe_config.from_buffer_copy(fwd.cfg)
+    nbytes = rast.load_library().fe_backward_scratch_bytes(rast.C.byref(cfg), rast.C.byref(fwd.cam), sc.n)
+    scratch = torch.full((nbytes,), 255, dtype=torch.uint8, device="cuda")
+    gr = rast.render_backward(fwd, d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["feat"],
+                              torch.from_numpy(d_rgb).cuda(), torch.from_numpy(d_feat).cuda(), st, scratch=scratch)
+    torch.cuda.synchronize()
+    ob = U.oracle_backward(sc, st, d_rgb, d_feat, cam=cam)
+    U.check_grads(gr, ob)
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
@@ -111,11 +154,7 @@ def test_ragged_and_tiny_images(wh, variant):
                               torch.from_numpy(d_rgb).cuda(), torch.from_numpy(d_feat).cuda(), st)
     torch.cuda.synchronize()
     ob = U.oracle_backward(sc, st, d_rgb, d_feat, cam=cam)
-    for k in ("means", "scales", "quats", "opacity", "sh", "feat"):
-        if np.abs(ob[k]).max() > 0:
-            assert U.normwise(gr[k].cpu().numpy(), ob[k]) < 1e-4, k
-        else:
-            assert float(gr[k].abs().max()) == 0.0, k
+    U.check_grads(gr, ob)
 
 
 def test_invalid_arguments_return_status():

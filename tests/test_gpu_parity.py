@@ -102,15 +102,9 @@ def test_mid_window_forward_backward(dtype, variant):
     torch.cuda.synchronize()
     ob = U.oracle_backward(sw, st, d_rgb, d_feat, cam=cam)
     g2 = gr["_scratch"][: 48 * sc.n].view(torch.float32).reshape(sc.n, 12).cpu().numpy()
-    errs = {
-        "xy2d": U.normwise(g2[:, 0:2], ob["xy"]), "conic2d": U.normwise(g2[:, 2:5], ob["conic"]),
-        "opacity2d": U.normwise(g2[:, 5], ob["opacity2d"]), "rgb2d": U.normwise(g2[:, 6:9], ob["rgb2d"]),
-    }
-    for k in ("means", "scales", "quats", "opacity", "sh", "feat"):
-        errs[k] = U.normwise(gr[k].cpu().numpy(), ob[k])
-    say("bwd normwise", errs)
-    for k, e in errs.items():
-        assert e < 1e-4, (k, e)
+    screen = dict(xy=g2[:, 0:2], conic=g2[:, 2:5], opacity2d=g2[:, 5], rgb2d=g2[:, 6:9])
+    U.check_grads(screen, ob, keys=("xy", "conic", "opacity2d", "rgb2d"))
+    U.check_grads(gr, ob)
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
@@ -135,7 +129,4 @@ def test_metric_window_d128(dtype, variant):
                               torch.from_numpy(d_rgb).cuda(), torch.from_numpy(d_feat).cuda(), st)
     torch.cuda.synchronize()
     ob = U.oracle_backward(sw, st, d_rgb, d_feat, cam=cam)
-    errs = {k: U.normwise(gr[k].cpu().numpy(), ob[k]) for k in ("means", "scales", "quats", "opacity", "sh", "feat")}
-    say("bwd normwise", errs)
-    for k, e in errs.items():
-        assert e < 1e-4, (k, e)
+    U.check_grads(gr, ob)

@@ -292,3 +292,37 @@ def test_round_projected_is_one_float32_rounding_with_identity_gradient():
     sum((r[k] * w[k]).sum() for k in vals).backward()
     for k, v in vals.items():
         assert torch.equal(v.grad, w[k])        # the rounding passes gradients through unchanged
+
+
+def test_equal_depths_blend_in_index_order():
+    # two Gaussians at the same depth (identical sort keys) centred on pixel
+    # (4, 4): the lower index is in front, rgb = a0 c0 + (1 - a0) a1 c1
+    c = cam(8, 8, f=40.0, cx=4.5, cy=4.5)
+    c0, c1 = [0.9, 0.2, 0.1], [0.1, 0.3, 0.8]
+    g = gaussians([[0, 0, 2.0], [0, 0, 2.0]], [[0.03, 0.03, 0.03], [0.05, 0.05, 0.05]], opacity=[0.6, 0.3],
+                  colors=[c0, c1], feat=[[1.0, 0.0], [0.0, 1.0]])
+    out = render_forward(**g, cam=c, cfg=cfg(tile=8), parity=True)
+    L = out["lists"]
+    assert L.gidx.tolist() == [0, 1] and L.depth_bits[0] == L.depth_bits[1]
+    k0, k1 = out["proj"]["rgb"][0].numpy(), out["proj"]["rgb"][1].numpy()
+    a0, a1 = float(np.float32(0.6)), float(np.float32(0.3))
+    np.testing.assert_allclose(out["rgb"][:, 4, 4].numpy(), a0 * k0 + (1 - a0) * a1 * k1, rtol=1e-12)
+    np.testing.assert_allclose(out["feat"][:, 4, 4].numpy(), [a0, (1 - a0) * a1], rtol=1e-12)
+    # the same scene with the two Gaussians listed the other way round
+    gs = {k: v[::-1].copy() for k, v in g.items()}
+    out2 = render_forward(**gs, cam=c, cfg=cfg(tile=8), parity=True)
+    np.testing.assert_allclose(out2["rgb"][:, 4, 4].numpy(), a1 * k1 + (1 - a1) * a0 * k0, rtol=1e-12)
+
+
+def test_negative_colour_is_clamped_to_zero():
+    # a DC coefficient whose colour Y00 k + 1/2 is negative in one channel:
+    # that channel is 0 (colour = max(0, sum k Y + 1/2)), the others unchanged
+    c = cam(8, 8, f=40.0, cx=4.5, cy=4.5)
+    g = gaussians([[0, 0, 2.0]], [[0.05, 0.05, 0.05]], opacity=0.5, colors=[-0.3, 0.4, 0.7], feat=[[1.0, 1.0]])
+    out = render_forward(**g, cam=c, cfg=cfg(tile=8), parity=False)
+    col = out["proj"]["rgb"][0].numpy()
+    assert col[0] == 0.0
+    np.testing.assert_allclose(col[1:], [0.4, 0.7], rtol=1e-6)
+    assert float(out["rgb"][0].abs().max()) == 0.0
+    a = float(np.float32(0.5))
+    np.testing.assert_allclose(out["rgb"][1:, 4, 4].numpy(), a * col[1:], rtol=1e-12)
