@@ -17,8 +17,12 @@ in key order, starting from T = 1, C = 0, Z = 0:
 * T' = T (1 - alpha); if T' < 1e-4 the pixel stops and this Gaussian is
   excluded
 * C += alpha T c, Z += alpha T f (eqs. 7-8, same weights), T = T'
-and rgb = C + T bg, feature = Z (feature background 0), final T = T,
-n_contrib = 1 + list position of the last included Gaussian (0 if none).
+* the depth image takes the same weights on the view-space depth t_z of each
+  Gaussian (colour, depth and features are rendered in one pass, Sec. 3,
+  method overview): Dp += alpha T t_z
+and rgb = C + T bg, feature = Z (feature background 0), depth = Dp (depth
+background 0), final T = T, n_contrib = 1 + list position of the last
+included Gaussian (0 if none).
 """
 from __future__ import annotations
 
@@ -87,9 +91,10 @@ def tile_pixels(tile: int, lists: TileLists, cam: OracleCamera, cfg: OracleConfi
     return pi[keep], pj[keep]
 
 
-def composite_tile(pi, pj, xy, conic, op, rgb, feat, box, bg, amb_delta=None):
+def composite_tile(pi, pj, xy, conic, op, rgb, feat, box, bg, amb_delta=None, depth=None):
     """Blend one tile.  pi, pj: [P] int pixel indices; per-Gaussian tensors
-    [L, ...] in list order.  Differentiable in xy, conic, op, rgb, feat."""
+    [L, ...] in list order (``depth`` [L] view-space depths, optional).
+    Differentiable in xy, conic, op, rgb, feat, depth."""
     P, L = len(pi), xy.shape[0]
     pit = torch.as_tensor(pi, dtype=torch.int64)
     pjt = torch.as_tensor(pj, dtype=torch.int64)
@@ -114,12 +119,13 @@ def composite_tile(pi, pj, xy, conic, op, rgb, feat, box, bg, amb_delta=None):
     w = a_inc * t_before
     C = w @ rgb
     Z = w @ feat
+    Dp = w @ depth if depth is not None else None
     T = t_incl[:, -1] if L > 0 else torch.ones(P, dtype=F64)
     out_rgb = C + T[:, None] * torch.as_tensor(bg, dtype=F64)[None, :]
     pos = torch.arange(1, L + 1, dtype=torch.int64)[None, :]
     ncon = torch.where(incl, pos, torch.zeros_like(pos)).max(dim=1).values if L > 0 else torch.zeros(P, dtype=torch.int64)
     aclamp = incl & ((op[None, :] * g).detach() > ALPHA_MAX)
-    res = dict(rgb=out_rgb, feat=Z, T=T, n_contrib=ncon, w=w, incl=incl, aclamp=aclamp)
+    res = dict(rgb=out_rgb, feat=Z, T=T, n_contrib=ncon, w=w, incl=incl, aclamp=aclamp, depth=Dp)
     if amb_delta is not None:
         dq, da, dt = amb_delta
         stop_hit = active & (t_after < T_STOP)
@@ -144,6 +150,7 @@ def composite(proj: dict, feat: torch.Tensor, lists: TileLists, cam: OracleCamer
     D = feat.shape[1]
     rgb = torch.zeros(3, H, W, dtype=F64)
     Z = torch.zeros(D, H, W, dtype=F64)
+    Dimg = torch.zeros(H, W, dtype=F64)
     T = torch.ones(H, W, dtype=F64)
     ncon = torch.zeros(H, W, dtype=torch.int64)
     amb = torch.zeros(H, W, dtype=torch.bool)
@@ -151,6 +158,7 @@ def composite(proj: dict, feat: torch.Tensor, lists: TileLists, cam: OracleCamer
     weights = {}
     tr = hashlib.sha1() if trace else None
     xy, conic, op, col = proj["xy"].detach(), proj["conic"].detach(), proj["opacity"].detach(), proj["rgb"].detach()
+    dep = proj["depth"].detach()
     box = proj["box"]
     featd = feat.detach()
     it = range(lists.tiles_x * lists.tiles_y) if tiles is None else tiles
@@ -158,9 +166,11 @@ def composite(proj: dict, feat: torch.Tensor, lists: TileLists, cam: OracleCamer
         pi, pj = tile_pixels(t, lists, cam, cfg)
         s, e = lists.ranges[t]
         gi = torch.as_tensor(lists.gidx[s:e])
-        r = composite_tile(pi, pj, xy[gi], conic[gi], op[gi], col[gi], featd[gi], box[gi], cfg.bg, amb_delta)
+        r = composite_tile(pi, pj, xy[gi], conic[gi], op[gi], col[gi], featd[gi], box[gi], cfg.bg, amb_delta,
+                           depth=dep[gi])
         rgb[:, pj, pi] = r["rgb"].T
         Z[:, pj, pi] = r["feat"].T
+        Dimg[pj, pi] = r["depth"]
         T[pj, pi] = r["T"]
         ncon[pj, pi] = r["n_contrib"]
         if amb_delta is not None:
@@ -172,7 +182,7 @@ def composite(proj: dict, feat: torch.Tensor, lists: TileLists, cam: OracleCamer
         if tr is not None:
             tr.update(np.packbits(r["incl"].numpy()).tobytes())
             tr.update(np.packbits(r["aclamp"].numpy()).tobytes())
-    return dict(rgb=rgb, feat=Z, final_T=T, n_contrib=ncon, ambiguous=amb, near=near, weights=weights,
+    return dict(rgb=rgb, feat=Z, depth=Dimg, final_T=T, n_contrib=ncon, ambiguous=amb, near=near, weights=weights,
                 trace=tr.hexdigest() if tr is not None else None)
 
 
@@ -215,12 +225,14 @@ def brute_force_render(proj: dict, feat, cam: OracleCamera, cfg: OracleConfig):
     conic = proj["conic"].detach().numpy()
     op = proj["opacity"].detach().numpy()
     col = proj["rgb"].detach().numpy()
+    dep = proj["depth"].detach().numpy()
     box = proj["box"].numpy()
     vis = proj["visible"].numpy()
     db = depth_bits(proj["depth"])
     bg = np.asarray(cfg.bg, dtype=np.float64)
     rgb = np.zeros((3, H, W))
     Z = np.zeros((D, H, W))
+    Dimg = np.zeros((H, W))
     Tf = np.ones((H, W))
     lists = {}
     cand = np.nonzero(vis)[0]
@@ -231,6 +243,7 @@ def brute_force_render(proj: dict, feat, cam: OracleCamera, cfg: OracleConfig):
             T = 1.0
             C = np.zeros(3)
             z = np.zeros(D)
+            dsum = 0.0
             used, ws = [], []
             for g in order:
                 dx = (i + 0.5) - xy[g, 0]
@@ -247,21 +260,23 @@ def brute_force_render(proj: dict, feat, cam: OracleCamera, cfg: OracleConfig):
                 w = a * T
                 C = C + w * col[g]
                 z = z + w * feat[g]
+                dsum += w * dep[g]
                 used.append(int(g))
                 ws.append(w)
                 T = Tn
             rgb[:, j, i] = C + T * bg
             Z[:, j, i] = z
+            Dimg[j, i] = dsum
             Tf[j, i] = T
             lists[(i, j)] = (used, ws)
-    return dict(rgb=rgb, feat=Z, final_T=Tf, lists=lists)
+    return dict(rgb=rgb, feat=Z, depth=Dimg, final_T=Tf, lists=lists)
 
 
 def pixel_variants(i, j, proj: dict, feat, lists: TileLists, cam: OracleCamera, cfg: OracleConfig,
                    near: dict, max_flips=3):
     """All outcomes of one pixel when each near-threshold decision (from
     ``composite(..., amb_delta)``) may go either way.  Returns a list of
-    (rgb[3], feat[D], T, n_contrib) or None if too many decisions are near."""
+    (rgb[3], feat[D], T, n_contrib, depth) or None if too many decisions are near."""
     tiles_x = lists.tiles_x
     t = (j // cfg.tile_h) * tiles_x + (i // cfg.tile_w)
     pis, pjs, nr = near
@@ -278,13 +293,14 @@ def pixel_variants(i, j, proj: dict, feat, lists: TileLists, cam: OracleCamera, 
     conic = proj["conic"].detach().numpy()
     op = proj["opacity"].detach().numpy()
     col = proj["rgb"].detach().numpy()
+    dep = proj["depth"].detach().numpy()
     box = proj["box"].numpy()
     feat = np.asarray(feat, dtype=np.float64)
     bg = np.asarray(cfg.bg, dtype=np.float64)
     outs = []
     for mask in itertools.product([False, True], repeat=len(cands)):
         flips = {c for c, f in zip(cands, mask) if f}
-        T, C, z, last = 1.0, np.zeros(3), np.zeros(feat.shape[1]), 0
+        T, C, z, last, dsum = 1.0, np.zeros(3), np.zeros(feat.shape[1]), 0, 0.0
         for pos, g in enumerate(gl):
             if not (box[g, 0] <= i <= box[g, 2] and box[g, 1] <= j <= box[g, 3]):
                 continue
@@ -302,7 +318,8 @@ def pixel_variants(i, j, proj: dict, feat, lists: TileLists, cam: OracleCamera, 
             w = a * T
             C = C + w * col[g]
             z = z + w * feat[g]
+            dsum += w * dep[g]
             T = Tn
             last = pos + 1
-        outs.append((C + T * bg, z, T, last))
+        outs.append((C + T * bg, z, T, last, dsum))
     return outs

@@ -144,7 +144,7 @@ def compare_images(fwd, orc, sc, st, tiles=None, tol=1e-5, feat_in=None):
                             orc["near"][t])
         ok = False
         if vs is not None:
-            for (vr, vf, vT, vn) in vs:
+            for (vr, vf, vT, vn, vd) in vs:
                 if (np.abs(vr - g_rgb[:, j, i]).max() <= tol * ref_r and np.abs(vf - g_feat[:, j, i]).max() <= tol * ref_f
                         and abs(vT - g_T[j, i]) <= tol):
                     ok = True

@@ -59,6 +59,34 @@ def test_gradients_through_clamps():
     assert _check(g, c, cf, d_rgb, d_feat) > 40
 
 
+def test_depth_gradients_match_central_differences():
+    # L = <d_depth, depth image> alone: the depth of each Gaussian moves its
+    # weighted contribution (and, through J and (u, v), its footprint)
+    g, c, d_rgb, d_feat = _scene(4)
+    rng = np.random.default_rng(9)
+    d_depth = rng.normal(size=(c.height, c.width))
+    z_rgb, z_feat = np.zeros_like(d_rgb), np.zeros_like(d_feat)
+    cf = cfg(tile=8, sh_degree=2)
+    an = render_backward(**g, cam=c, cfg=cf, d_rgb=z_rgb, d_feat=z_feat, d_depth=d_depth, parity=False)
+    nvalid = 0
+    for name in ("means", "scales", "quats", "opacity"):
+        size = g[name].size
+        idx = list(rng.choice(size, size=min(16, size), replace=False))
+        fd, valid = fd_gradient(g, name, idx, c, cf, z_rgb, z_feat, d_depth=d_depth)
+        a = an[name].reshape(-1)[idx]
+        nvalid += int(valid.sum())
+        assert valid.sum() >= 4, name
+        err = np.linalg.norm((fd - a)[valid]) / max(np.linalg.norm(a[valid]), 1e-12)
+        assert err < 1e-5, (name, err)
+    assert np.abs(an["means"][:, 2]).max() > 0 and np.abs(an["sh"]).max() == 0 and np.abs(an["feat"]).max() == 0
+    # the screen-space depth gradient is sum_p w_i(p) d_depth(p)
+    out = render_forward(**g, cam=c, cfg=cf, parity=False, keep_weights=True)
+    ws = np.zeros(g["means"].shape[0])
+    for t, (pi, pj, gi, w, incl) in out["weights"].items():
+        np.add.at(ws, gi, (w * d_depth[pj, pi][:, None]).sum(0))
+    np.testing.assert_allclose(an["depth2d"], ws, rtol=1e-12, atol=1e-14)
+
+
 def test_feature_gradient_equals_weight_sum():
     g, c, d_rgb, d_feat = _scene(3, n=40)
     cf = cfg(tile=8, sh_degree=2)

@@ -37,6 +37,8 @@ def test_single_isotropic_gaussian_closed_form():
     np.testing.assert_allclose(out["rgb"].numpy(), rgb, atol=1e-12)
     np.testing.assert_allclose(out["feat"].numpy(), a[None] * fv.astype(np.float32)[:, None, None], atol=1e-12)
     np.testing.assert_allclose(out["final_T"].numpy(), 1 - a, atol=1e-15)
+    # depth image: the same weights on the view-space depth, background 0
+    np.testing.assert_allclose(out["depth"].numpy(), a * z, atol=1e-12)
 
 
 def test_rotated_anisotropic_gaussian_closed_form():
@@ -78,6 +80,9 @@ def test_two_gaussians_front_to_back_order():
         fr, bk = (0, 1) if z1 < z2 else (1, 0)
         expect = a[fr] * np.eye(2)[fr] + (1 - a[fr]) * a[bk] * np.eye(2)[bk]
         np.testing.assert_allclose(out["feat"][:, 8, 8].numpy(), expect, rtol=1e-12)
+        zs = (z1, z2)
+        np.testing.assert_allclose(out["depth"][8, 8].item(), a[fr] * zs[fr] + (1 - a[fr]) * a[bk] * zs[bk],
+                                   rtol=1e-12)
 
 
 def test_stop_rule_excludes_the_stopping_gaussian():
@@ -142,6 +147,7 @@ def test_tiled_equals_brute_force(seed):
     assert np.array_equal(out["final_T"].numpy(), bf["final_T"])
     np.testing.assert_allclose(out["rgb"].numpy(), bf["rgb"], atol=1e-14)
     np.testing.assert_allclose(out["feat"].numpy(), bf["feat"], atol=1e-13)
+    np.testing.assert_allclose(out["depth"].numpy(), bf["depth"], atol=1e-13)
 
 
 def test_image_independent_of_tile_shape():
@@ -239,12 +245,13 @@ def test_ambiguity_variants_alpha_branch():
     col32 = out["proj"]["rgb"][0].numpy()
     np.testing.assert_allclose(col32, col, rtol=1e-6)
     bg32 = np.asarray([float(np.float32(b)) for b in bg])
-    (r_in, f_in, T_in, n_in), (r_sk, f_sk, T_sk, n_sk) = vs
+    (r_in, f_in, T_in, n_in, d_in), (r_sk, f_sk, T_sk, n_sk, d_sk) = vs
     np.testing.assert_allclose(r_in, a * col32 + (1 - a) * bg32, rtol=1e-12)
     np.testing.assert_allclose(f_in, a * np.asarray(fv), rtol=1e-12)
     assert abs(T_in - (1 - a)) < 1e-15 and n_in == 1
     np.testing.assert_allclose(r_sk, bg32, rtol=1e-15)
     assert np.all(f_sk == 0) and T_sk == 1.0 and n_sk == 0
+    assert abs(d_in - a * 2.0) < 1e-15 and d_sk == 0.0
 
 
 def test_ambiguity_variants_stop_branch():
@@ -266,13 +273,14 @@ def test_ambiguity_variants_stop_branch():
     np.testing.assert_allclose(k1, c1, rtol=1e-6)
     np.testing.assert_allclose(k2, c2, rtol=1e-6)
     a, t1 = 0.99, 1.0 - 0.99
-    (r_both, f_both, T_both, n_both), (r_stop, f_stop, T_stop, n_stop) = vs
+    (r_both, f_both, T_both, n_both, d_both), (r_stop, f_stop, T_stop, n_stop, d_stop) = vs
     np.testing.assert_allclose(r_both, a * k1 + t1 * a * k2, rtol=1e-12)
     np.testing.assert_allclose(f_both, [a, t1 * a], rtol=1e-12)
     assert abs(T_both - t1 * t1) < 1e-18 and n_both == 2
     np.testing.assert_allclose(r_stop, a * k1, rtol=1e-12)
     np.testing.assert_allclose(f_stop, [a, 0.0], rtol=1e-12, atol=0)
     assert abs(T_stop - t1) < 1e-16 and n_stop == 1
+    np.testing.assert_allclose([d_both, d_stop], [a * 2.0 + t1 * a * 2.5, a * 2.0], rtol=1e-12)
 
 
 def test_round_projected_is_one_float32_rounding_with_identity_gradient():
