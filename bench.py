@@ -6,11 +6,18 @@ Workload: one 640x512 camera, 300,000 Gaussians, SH degree 3, 128 semantic
 channels, 16x16 tiles (the paper's frame size and feature width), seeded
 synthetic scene.  A step is one forward render plus its backward pass for
 one frame, through the C ABI on one HIP stream, with every input already in
-HBM.  Both storage forms are timed: SH and features in BF16 (the reported
-value) and plain FP32, and their speedup is reported beside it.
+HBM.  Three forms are timed: SH and features stored BF16 (the reported
+value), the same kernels with FP32 storage, and the plain-FP32 vector-ALU
+kernels; the speedups are reported beside the accuracy of each form against
+the FP64 oracle (at the stored BF16 values and at the FP32 originals).
+
+Also reported (untimed by the headline): a sweep of the feature width
+(16..256), the 1280x1024 frame with 1M Gaussians, the 100k-Gaussian FP32
+frame, 16 timestamps as one graph replay and as 16 separate calls, and the
+bandwidth of a plain device copy.
 
 Prints one JSON line.  Stage durations come from HIP events that the library
-records on the stream around each stage during the timed steps.
+records on the stream around each stage.
 """
 from __future__ import annotations
 
@@ -29,20 +36,28 @@ HBM_PEAK_GBS = 8000.0
 WORKLOAD = "metric"
 
 
+def _log(*a):
+    """Progress on stderr (the JSON line alone goes to stdout)."""
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
 def _parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-tiles", type=int, default=0,
-                    help="tiles blended by the CPU oracle (0: every tile, i.e. one whole frame)")
-    ap.add_argument("--forms", default="bf16,f32")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the FP64 oracle (CPU baseline and accuracy block)")
+    ap.add_argument("--forms", default="bf16,f32,f32_valu",
+                    help="bf16 / f32 storage with the --variant kernels; f32_valu: plain FP32 vector-ALU kernels")
     ap.add_argument("--variant", default="mfma", choices=["mfma", "valu"],
                     help="compositing kernels: matrix cores (default) or vector ALU")
     ap.add_argument("--no-batched", action="store_true", help="skip the 16-timestamp graph form")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for HBM counters)")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the FP64-oracle accuracy block")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the feature-width sweep")
+    ap.add_argument("--no-configs", action="store_true", help="skip the large and mid frames")
     return ap.parse_args()
 
 
@@ -87,12 +102,14 @@ def _algorithmic_bytes(stage, n, k, pairs, H, W, D, L, eb):
     return 0
 
 
-def run_form(sc, form, steps, warmup, variant="mfma"):
+def run_form(sc, form, steps, warmup, variant="mfma", key_capacity=None, keep=False):
+    """Time `steps` forward+backward steps of scene `sc` (16x16 tiles).  With
+    `keep` the last step's images and gradients are returned on the host."""
     import torch
     from paper_2503_06161_amd import rast
     d, d_rgb, d_feat = _device_inputs(sc, form)
     st = rast.Settings(sh_degree=sc.sh_degree, feat_dim=sc.feat_dim, tile_w=16, tile_h=16,
-                       sh_dtype=form, feat_dtype=form,
+                       sh_dtype=form, feat_dtype=form, key_capacity=key_capacity,
                        variant=rast.FE_VARIANT_VALU if variant == "valu" else rast.FE_VARIANT_MFMA)
     args = (d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["feat"])
     fwd = rast.render_forward(*args, sc.cam, st, check=True)      # sizes the key buffers
@@ -162,8 +179,15 @@ def run_form(sc, form, steps, warmup, variant="mfma"):
     stage_ms.update(stage_times(evs, dom))
     pairs = _processed_pairs(fwd.n_contrib, 16, 16)
     rep2 = rast.read_report(fwd.state)
-    return dict(ms_per_step=1e3 * (t1 - t0) / steps, fps=steps / (t1 - t0), stage_ms=stage_ms, pairs=pairs,
-                keys=int(rep2["keys_needed"]), report=rep, eb=2 if form == "bf16" else 4)
+    res = dict(ms_per_step=1e3 * (t1 - t0) / steps, fps=steps / (t1 - t0), stage_ms=stage_ms, pairs=pairs,
+               keys=int(rep2["keys_needed"]), report=rep2, eb=2 if form == "bf16" else 4)
+    if keep:
+        res["images"] = {k: out[k].double().cpu().numpy() for k in ("rgb", "feat", "final_T")}
+        res["grads"] = {k: grads[k].double().cpu().numpy() for k in ("means", "scales", "quats", "opacity", "sh",
+                                                                        "feat")}
+    del d, d_rgb, d_feat, fwd, grads, scratch, out
+    torch.cuda.empty_cache()
+    return res
 
 
 def run_batched(steps, warmup):
@@ -203,44 +227,167 @@ def run_batched(steps, warmup):
     bad = [k for k in range(len(fr)) if br.report(k)["status"] != 0]
     br.close()
     ms = 1e3 * (t1 - t0) / steps
+    # the same 16 frames as 16 separate forward+backward calls on one stream
+    # (same settings, buffers sized once)
+    per = []
+    for f, cam, gr_, gf_ in zip(frames, cams, d_rgb, d_feat):
+        args = (f["means"], f["scales"], f["quats"], f["opacity"], f["sh"], f["feat"])
+        fw = rast.render_forward(*args, cam, st, check=True)
+        st_f = rast.Settings(**{**st.__dict__, "key_capacity": fw.cfg.key_capacity,
+                                "row_capacity": max(int(fw.report["rows_needed"]), 1)})
+        per.append([args, cam, gr_, gf_, st_f, fw, None, None])
+
+    def calls():
+        for e in per:
+            args, cam, gr_, gf_, st_f, fw, g, scr = e
+            out = dict(rgb=fw.rgb, feat=fw.feat, final_T=fw.final_T, n_contrib=fw.n_contrib)
+            f2 = rast.render_forward(*args, cam, st_f, check=False, state=fw.state, out=out)
+            g2 = rast.render_backward(f2, *args, gr_, gf_, st_f, grads=g, scratch=scr, check=False)
+            e[5], e[6], e[7] = f2, g2, g2["_scratch"]
+
+    for _ in range(warmup):
+        calls()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(steps):
+        calls()
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    ms_calls = 1e3 * (t3 - t2) / steps
     return dict(frames=len(fr), gaussians_per_frame=[f["n"] for f in fr], ms_per_replay=round(ms, 4),
                 frames_per_s=round(len(fr) * 1e3 / ms, 2), status_errors=bad,
-                tile=f"{st.tile_w}x{st.tile_h}", variant="valu" if st.variant == rast.FE_VARIANT_VALU else "mfma")
+                tile=f"{st.tile_w}x{st.tile_h}", threads_per_tile=st.threads_per_tile,
+                variant="valu" if st.variant == rast.FE_VARIANT_VALU else "mfma",
+                separate_calls={"ms_per_16_frames": round(ms_calls, 4),
+                                "frames_per_s": round(len(fr) * 1e3 / ms_calls, 2)},
+                graph_speedup_vs_separate_calls=round(ms_calls / ms, 4))
 
 
-def cpu_baseline(sc, sample_tiles):
-    """The float64 oracle, as it is, forward + backward on the same frame:
-    projection, binning and projection backward of all Gaussians, and the
-    blending forward+backward of every tile (or of `sample_tiles` evenly spaced
-    tiles, with the frame time extrapolated to all tiles)."""
+def _img_errors(g, o, clean):
+    """Errors of one form's images against an oracle render, over pixels
+    without a near-threshold decision (those are counted, not compared)."""
+    import numpy as np
+    out = {}
+    for k in ("rgb", "feat"):
+        ref = max(float(np.abs(o[k]).max()), 1e-30)
+        out[k] = float(np.abs(g[k] - o[k])[:, clean].max() / ref)
+    out["final_T"] = float(np.abs(g["final_T"] - o["final_T"])[clean].max())
+    out["pixels_near_threshold"] = int((~clean).sum())
+    return out
+
+
+def _grad_errors(g, o):
+    import numpy as np
+    nw, mx = {}, {}
+    for k in ("means", "scales", "quats", "opacity", "sh", "feat"):
+        a, b = g[k].reshape(-1), o[k].reshape(-1)
+        nw[k] = float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+        mx[k] = float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
+    return {"normwise": nw, "max_element": mx}
+
+
+def accuracy_and_cpu_baseline(sc, forms):
+    """Error of each timed form against the float64 oracle on the whole metric
+    frame (images and all six gradient groups), the BF16 form both at its
+    stored (BF16-rounded) inputs, where only arithmetic differs, and at the
+    FP32 originals, where the storage rounding shows; and the oracle's own
+    forward+backward time on the host (the CPU baseline)."""
     import numpy as np
     import torch
     import oracle
     from paper_2503_06161_amd.scenes import bf16_round
-    inp = dict(means=sc.means, scales=sc.scales, quats=sc.quats, opacity=sc.opacity, sh=bf16_round(sc.sh),
-               feat=bf16_round(sc.feat))
     cfg = oracle.OracleConfig(tile_w=16, tile_h=16, sh_degree=sc.sh_degree)
-    ntiles = -(-sc.cam.width // 16) * -(-sc.cam.height // 16)
-    oracle.render_backward(**inp, cam=sc.cam, cfg=cfg, d_rgb=sc.d_rgb, d_feat=sc.d_feat, tiles=[0])   # warm-up
-    if sample_tiles <= 0 or sample_tiles >= ntiles:
+    base = dict(means=sc.means, scales=sc.scales, quats=sc.quats, opacity=sc.opacity)
+    refs = {}
+    t_bwd = None
+    for name, sh, feat in (("stored_bf16", bf16_round(sc.sh), bf16_round(sc.feat)), ("f32", sc.sh, sc.feat)):
+        inp = dict(base, sh=sh, feat=feat)
+        of = oracle.render_forward(**inp, cam=sc.cam, cfg=cfg, amb_delta=(2e-6, 2e-6, 1e-5))
         t0 = time.perf_counter()
-        oracle.render_backward(**inp, cam=sc.cam, cfg=cfg, d_rgb=sc.d_rgb, d_feat=sc.d_feat)
-        per_frame = time.perf_counter() - t0
-        what = f"one whole frame ({per_frame:.1f} s of CPU work)"
-    else:
-        sample = list(np.linspace(0, ntiles - 1, sample_tiles).astype(int))
-        t0 = time.perf_counter()
-        oracle.render_backward(**inp, cam=sc.cam, cfg=cfg, d_rgb=sc.d_rgb, d_feat=sc.d_feat, tiles=[])
-        t1 = time.perf_counter()
-        oracle.render_backward(**inp, cam=sc.cam, cfg=cfg, d_rgb=sc.d_rgb, d_feat=sc.d_feat, tiles=sample)
-        t2 = time.perf_counter()
-        per_tile = max((t2 - t1) - (t1 - t0), 0.0) / len(sample)
-        per_frame = (t1 - t0) + per_tile * ntiles
-        what = (f"projection, binning and projection backward of all {sc.n} Gaussians plus {len(sample)} of "
-                f"{ntiles} tiles blended forward+backward ({t2 - t0:.1f} s of CPU work), extrapolated to all tiles")
-    return dict(value=1.0 / per_frame, unit="frames/s", cores=torch.get_num_threads(), kind="oracle",
-                sample=f"float64 oracle fwd+bwd of the {sc.cam.width}x{sc.cam.height}, {sc.n}-Gaussian, "
-                       f"D={sc.feat_dim} frame: {what}")
+        ob = oracle.render_backward(**inp, cam=sc.cam, cfg=cfg, d_rgb=sc.d_rgb, d_feat=sc.d_feat)
+        if name == "stored_bf16":
+            t_bwd = time.perf_counter() - t0
+        refs[name] = ({"rgb": of["rgb"].numpy(), "feat": of["feat"].numpy(), "final_T": of["final_T"].numpy()},
+                      ~of["ambiguous"].numpy(), ob)
+    acc = {}
+    for form, r in forms.items():
+        if "images" not in r:
+            continue
+        against = ["stored_bf16", "f32"] if form == "bf16" else ["f32"]
+        acc[form] = {}
+        for a in against:
+            img, clean, ob = refs[a]
+            label = "vs_oracle_at_stored_bf16" if a == "stored_bf16" else "vs_oracle_at_f32_inputs"
+            acc[form][label] = {"images": _img_errors(r["images"], img, clean), "gradients": _grad_errors(r["grads"], ob)}
+    cpu = dict(value=1.0 / t_bwd, unit="frames/s", cores=torch.get_num_threads(), kind="oracle",
+               sample=f"float64 oracle forward+backward (projection, binning, blending of every tile, "
+                      f"projection backward) of the whole {sc.cam.width}x{sc.cam.height}, {sc.n}-Gaussian, "
+                      f"D={sc.feat_dim} BF16-valued frame: {t_bwd:.1f} s of CPU work")
+    return acc, cpu
+
+
+def feature_width_sweep(steps, warmup, widths=(16, 32, 64, 128, 256)):
+    """The metric frame with D channels (BF16 storage), forward+backward
+    frames/s and both compositing kernels' duration and fraction of the HBM
+    peak (their algorithmic bytes over their event-timed duration)."""
+    from paper_2503_06161_amd.scenes import make_scene
+    out = {}
+    for D in widths:
+        _log("  D =", D)
+        sc = make_scene(WORKLOAD, feat_dim=D)
+        r = run_form(sc, "bf16", steps, warmup)
+        H, W, L = sc.cam.height, sc.cam.width, sc.sh_degree
+        row = {"frames_per_s": round(r["fps"], 2), "ms_per_step": round(r["ms_per_step"], 4)}
+        for stage in ("composite", "composite_bwd"):
+            ms = r["stage_ms"][stage]
+            by = _algorithmic_bytes(stage, sc.n, r["keys"], r["pairs"], H, W, D, L, 2)
+            row[stage] = {"ms": round(ms, 4), "algorithmic_bytes": by,
+                          "hbm_frac": round(by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)}
+        out[str(D)] = row
+    return out
+
+
+def other_configs(steps, warmup):
+    """The 1280x1024 frame with 1M Gaussians (D=128 BF16, sort buffer for 8
+    tile overlaps per Gaussian) and the 640x512 frame with 100k Gaussians
+    (D=32, FP32), forward+backward frames/s and the dominant stage's roofline."""
+    from paper_2503_06161_amd.scenes import make_scene
+    res = {}
+    for name, form, cap, desc in (("large", "bf16", 8, "1280x1024 camera (f=1024), 1M Gaussians, SH 3, D=128 BF16, "
+                                                     "key capacity 8N, 16x16 tiles"),
+                                  ("mid", "f32", None, "640x512 camera (f=512), 100k Gaussians, SH 3, D=32 FP32, "
+                                                       "16x16 tiles")):
+        sc = make_scene(name)
+        r = run_form(sc, form, steps, warmup, key_capacity=cap * sc.n if cap else None)
+        H, W, D, L = sc.cam.height, sc.cam.width, sc.feat_dim, sc.sh_degree
+        stage, ms = max(r["stage_ms"].items(), key=lambda kv: kv[1])
+        by = _algorithmic_bytes(stage, sc.n, r["keys"], r["pairs"], H, W, D, L, r["eb"])
+        res[name] = {"workload": desc, "frames_per_s": round(r["fps"], 2), "ms_per_step": round(r["ms_per_step"], 4),
+                     "status": r["report"]["status"], "keys": r["keys"],
+                     "stage_ms": {k: round(x, 4) for k, x in r["stage_ms"].items()},
+                     "roofline": {"kernel": stage, "bound": "hbm", "achieved": round(by / (ms * 1e-3) / 1e9, 2),
+                                  "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": round(by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)}}
+    return res
+
+
+def copy_bandwidth():
+    """Achievable HBM bandwidth: a plain 256 MiB device-to-device copy
+    (read + write bytes over its event-timed duration, best of 10)."""
+    import torch
+    n = 256 << 20
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    best = None
+    for _ in range(12):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    return {"bytes": 2 * n, "gb_per_s": round(2 * n / (best * 1e-3) / 1e9, 1)}
 
 
 def _kernel_source_hash():
@@ -264,6 +411,16 @@ def _traffic(stage):
     return d.get("bytes_per_launch")
 
 
+FORM_DESC = {
+    "bf16": "SH and features stored BF16; blending and transmittance in FP32 on the vector ALUs; the D-channel "
+            "contractions on the matrix cores from exact bf16 parts (forward: every FP32 product exact; "
+            "backward: products of order <= 1 of two-part splits, about 16 significant bits) with FP32 accumulation",
+    "f32": "SH and features stored FP32, the same matrix-core kernels (three-part feature splits)",
+    "f32_valu": "plain FP32: SH and features stored FP32, blending and both contractions on the vector ALUs in "
+                "FP32, backward reduced with device-wide FP32 atomics",
+}
+
+
 def main():
     args = _parse()
     if args.gpus != 1:
@@ -276,14 +433,20 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     sc = make_scene(WORKLOAD)
+    keep = not (args.no_accuracy or args.no_cpu_baseline)
     res = {}
     for form in args.forms.split(","):
-        res[form] = run_form(sc, form, args.steps, args.warmup, args.variant)
+        _log("form", form)
+        if form == "f32_valu":
+            res[form] = run_form(sc, "f32", max(3, args.steps // 4), 1, "valu", keep=keep)
+        else:
+            res[form] = run_form(sc, form, args.steps, args.warmup, args.variant, keep=keep)
     if args.calibrate_copy:
         a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
+        del a, b
     main_form = "bf16" if "bf16" in res else next(iter(res))
     r = res[main_form]
     H, W, D, L = sc.cam.height, sc.cam.width, sc.feat_dim, sc.sh_degree
@@ -301,13 +464,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16 storage, f32 compute" if main_form == "bf16" else "f32",
+        "dtype": "bf16 storage; f32 blend and accumulation; split-bf16 matrix-core products" if main_form == "bf16"
+                 else "f32",
         "data": "synthetic",
         "config": {"workload": "640x512 camera (f=512), 300k Gaussians, SH degree 3, D=128 features, "
                                "16x16 tiles, one frame forward+backward", "form": main_form,
                    "gaussians": sc.n, "width": W, "height": H, "feat_dim": D, "sh_degree": L,
                    "keys": r["keys"], "processed_tile_pairs": r["pairs"], "variant": args.variant},
         "forms": {f: {"frames_per_s": round(v["fps"], 2), "ms_per_step": round(v["ms_per_step"], 4),
+                      "compute": FORM_DESC.get(f, f),
                       "stage_ms": {k: round(x, 4) for k, x in v["stage_ms"].items()}} for f, v in res.items()},
         "roofline": {"kernel": stage, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
@@ -315,13 +480,28 @@ def main():
     }
     if "bf16" in res and "f32" in res:
         line["bf16_speedup_vs_f32"] = round(res["f32"]["ms_per_step"] / res["bf16"]["ms_per_step"], 4)
+    if "bf16" in res and "f32_valu" in res:
+        line["bf16_speedup_vs_plain_f32_valu"] = round(res["f32_valu"]["ms_per_step"] / res["bf16"]["ms_per_step"], 4)
+    _log("copy bandwidth")
+    line["hbm_copy"] = copy_bandwidth()
+    line["roofline"]["frac_of_copy"] = round(achieved / line["hbm_copy"]["gb_per_s"], 5)
+    if not args.no_sweep:
+        _log("feature-width sweep")
+        line["feat_dim_sweep"] = feature_width_sweep(max(5, args.steps // 2), 2)
+    if not args.no_configs:
+        _log("large and mid frames")
+        line["other_configs"] = other_configs(max(5, args.steps // 2), 2)
     if not args.no_batched:
+        _log("16 timestamps")
         try:
             line["batched_16_timestamps"] = run_batched(max(3, args.steps // 2), 2)
         except Exception as e:  # reported, never hides the main measurement
             line["batched_16_timestamps"] = {"error": repr(e)[:200]}
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(sc, args.cpu_sample_tiles)
+    if keep:
+        _log("FP64 oracle: accuracy and CPU baseline")
+        acc, cpu = accuracy_and_cpu_baseline(sc, res)
+        line["accuracy"] = acc
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 
 

@@ -89,7 +89,17 @@ typedef struct fe_config {
   int32_t tile_w, tile_h;        /* tile shape in pixels; tile_w * tile_h must
                                     be 64, 128 or 256 and tile_w one of
                                     8, 16, 32                                  */
-  int32_t threads_per_tile;      /* 0 = tile_w * tile_h (one pixel per thread) */
+  int32_t threads_per_tile;      /* threads of the compositing workgroup of a
+                                    tile: tile_w * tile_h (one per pixel:
+                                    every wave walks its pixels and runs the
+                                    contractions), 2 * tile_w * tile_h (two
+                                    per pixel: walker waves beside matrix-core
+                                    waves; matrix-core variant, BF16 features,
+                                    feat_dim <= 128 and at least as many
+                                    32-channel blocks as 64-pixel groups), or
+                                    0 = the two-per-pixel kernels wherever
+                                    they exist; other values are
+                                    FE_ERR_UNSUPPORTED                         */
   int32_t sh_degree;             /* 0..3                                        */
   int32_t feat_dim;              /* D, 1..256                                   */
   int32_t sh_dtype, feat_dtype;  /* fe_dtype                                    */

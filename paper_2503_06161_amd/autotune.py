@@ -1,7 +1,10 @@
-"""Tile-shape / kernel-variant selection by timing.
+"""Tile-shape / threads-per-tile / kernel-variant selection by timing.
 
 Every candidate renders the same image (the 3-sigma box rule makes the
-result independent of the tile shape), so the choice only changes speed.
+result independent of the tile shape; the kernels differ only in how the
+work is spread over threads), so the choice only changes speed.  Threads per
+tile is one per pixel or, where the wave-specialized matrix-core kernels
+exist, two per pixel.
 Candidates are timed with HIP events on the current stream (forward, or
 forward + backward), the fastest is kept, and results are cached in a JSON
 file keyed by device, image size, feature width, storage dtypes and a
@@ -50,6 +53,32 @@ def _store_cache(c):
     os.replace(tmp, path)
 
 
+def candidates_for(st: rast.Settings, cam, n: int, shapes=None, variants=None):
+    """(tile_w, tile_h, variant, threads_per_tile) combinations the library
+    accepts for these settings (checked with the host-only fe_validate).
+    threads_per_tile 0 lets each direction take the two-per-pixel kernel
+    where it exists (which can differ between forward and backward)."""
+    import ctypes as C
+    lib = rast.load_library()
+    cam_c = rast.camera_c(cam)
+    out = []
+    for tw, th in shapes or TILE_SHAPES:
+        for v in variants or VARIANTS:
+            # one thread per pixel, the library's choice per direction (0), two per pixel
+            for tpt in (tw * th, 0, 2 * tw * th):
+                if v == rast.FE_VARIANT_VALU and tpt != tw * th:
+                    continue                      # one kernel form only
+                s2 = rast.Settings(**{**st.__dict__, "tile_w": tw, "tile_h": th, "variant": v, "threads_per_tile": tpt})
+                if lib.fe_validate(C.byref(s2.to_c(1 << 20)), C.byref(cam_c), n) == rast.FE_OK:
+                    out.append((tw, th, v, tpt))
+    return out
+
+
+def _pick(st, c):
+    return rast.Settings(**{**st.__dict__, "tile_w": c["tile_w"], "tile_h": c["tile_h"], "variant": c["variant"],
+                            "threads_per_tile": c.get("threads_per_tile", 0)})
+
+
 def time_candidate(g: dict, cam, st: rast.Settings, d_rgb=None, d_feat=None, reps: int = 5) -> float:
     """Median milliseconds of one forward (+ backward when upstream gradients
     are given) for the settings ``st``."""
@@ -77,27 +106,28 @@ def time_candidate(g: dict, cam, st: rast.Settings, d_rgb=None, d_feat=None, rep
 
 def autotune(g: dict, cam, st: rast.Settings, d_rgb=None, d_feat=None, candidates=None, use_cache=True,
              verbose=False) -> rast.Settings:
-    """Return a copy of ``st`` with the fastest tile shape and variant."""
+    """Return a copy of ``st`` with the fastest tile shape, variant and
+    threads per tile."""
     n = int(g["means"].shape[0])
     key = cache_key(cam, st, n, d_rgb is not None)
     cache = _load_cache() if use_cache else {}
     if key in cache:
-        c = cache[key]
-        return rast.Settings(**{**st.__dict__, "tile_w": c["tile_w"], "tile_h": c["tile_h"], "variant": c["variant"]})
-    cands = candidates or [(tw, th, v) for (tw, th) in TILE_SHAPES for v in VARIANTS]
+        return _pick(st, cache[key])
+    cands = candidates or candidates_for(st, cam, n)
     results = []
-    for tw, th, v in cands:
-        s2 = rast.Settings(**{**st.__dict__, "tile_w": tw, "tile_h": th, "variant": v})
+    for tw, th, v, tpt in cands:
+        s2 = rast.Settings(**{**st.__dict__, "tile_w": tw, "tile_h": th, "variant": v, "threads_per_tile": tpt})
         ms = time_candidate(g, cam, s2, d_rgb, d_feat)
-        results.append((ms, tw, th, v))
+        results.append((ms, tw, th, v, tpt))
         if verbose:
-            print(f"autotune {tw}x{th} variant {v}: {ms:.3f} ms", flush=True)
-    ms, tw, th, v = min(results)
+            print(f"autotune {tw}x{th} variant {v} threads {tpt}: {ms:.3f} ms", flush=True)
+    ms, tw, th, v, tpt = min(results)
+    best = dict(tile_w=tw, tile_h=th, variant=v, threads_per_tile=tpt)
     if use_cache:
-        cache[key] = dict(tile_w=tw, tile_h=th, variant=v, ms=ms,
-                          all=[dict(tile_w=a, tile_h=b, variant=c, ms=m) for m, a, b, c in results])
+        cache[key] = dict(best, ms=ms, all=[dict(tile_w=a, tile_h=b, variant=c, threads_per_tile=t, ms=m)
+                                            for m, a, b, c, t in results])
         _store_cache(cache)
-    return rast.Settings(**{**st.__dict__, "tile_w": tw, "tile_h": th, "variant": v})
+    return _pick(st, best)
 
 
 def autotune_batch(frames, cams, st: rast.Settings, d_rgb=None, d_feat=None, candidates=None, use_cache=True,
@@ -111,12 +141,11 @@ def autotune_batch(frames, cams, st: rast.Settings, d_rgb=None, d_feat=None, can
     key = cache_key(cams[0], st, n, d_rgb is not None) + f"|batch{len(frames)}"
     cache = _load_cache() if use_cache else {}
     if key in cache:
-        c = cache[key]
-        return rast.Settings(**{**st.__dict__, "tile_w": c["tile_w"], "tile_h": c["tile_h"], "variant": c["variant"]})
-    cands = candidates or [(tw, th, v) for (tw, th) in TILE_SHAPES for v in VARIANTS]
+        return _pick(st, cache[key])
+    cands = candidates or candidates_for(st, cams[0], n)
     results = []
-    for tw, th, v in cands:
-        s2 = rast.Settings(**{**st.__dict__, "tile_w": tw, "tile_h": th, "variant": v})
+    for tw, th, v, tpt in cands:
+        s2 = rast.Settings(**{**st.__dict__, "tile_w": tw, "tile_h": th, "variant": v, "threads_per_tile": tpt})
         br = BatchRenderer(frames, cams, s2, mode, d_rgb, d_feat)
         br.launch()
         times = []
@@ -130,12 +159,13 @@ def autotune_batch(frames, cams, st: rast.Settings, d_rgb=None, d_feat=None, can
         br.close()
         times.sort()
         ms = times[len(times) // 2]
-        results.append((ms, tw, th, v))
+        results.append((ms, tw, th, v, tpt))
         if verbose:
-            print(f"autotune batch {tw}x{th} variant {v}: {ms:.3f} ms", flush=True)
-    ms, tw, th, v = min(results)
+            print(f"autotune batch {tw}x{th} variant {v} threads {tpt}: {ms:.3f} ms", flush=True)
+    ms, tw, th, v, tpt = min(results)
+    best = dict(tile_w=tw, tile_h=th, variant=v, threads_per_tile=tpt)
     if use_cache:
-        cache[key] = dict(tile_w=tw, tile_h=th, variant=v, ms=ms,
-                          all=[dict(tile_w=a, tile_h=b, variant=c, ms=m) for m, a, b, c in results])
+        cache[key] = dict(best, ms=ms, all=[dict(tile_w=a, tile_h=b, variant=c, threads_per_tile=t, ms=m)
+                                            for m, a, b, c, t in results])
         _store_cache(cache)
-    return rast.Settings(**{**st.__dict__, "tile_w": tw, "tile_h": th, "variant": v})
+    return _pick(st, best)

@@ -1111,12 +1111,12 @@ __global__ __launch_bounds__(2 * NT) void composite_bwd_ws_kernel(BwdArgs a) {
 // The wave-specialized form applies where contractor waves own whole channel
 // blocks; elsewhere one wave per 64 pixels runs both roles.
 template <int DP, int NT>
-constexpr bool bwd_uses_ws() { return DP <= 128 && DP / 32 >= NT / 64; }
+constexpr bool bwd_ws_available() { return DP <= 128 && DP / 32 >= NT / 64; }
 
 // Persistent form over many frames: each workgroup takes (frame, tile) items
 // from a queue sorted by walk length, longest first, until it is empty.
-template <int DP, typename FT, int NT>
-__global__ __launch_bounds__((bwd_uses_ws<DP, NT>() ? 2 * NT : NT)) void composite_bwd_persistent(
+template <int DP, typename FT, int NT, bool WS>
+__global__ __launch_bounds__((WS ? 2 * NT : NT)) void composite_bwd_persistent(
     const BwdArgs* __restrict__ args, TileQueue tq) {
   __shared__ uint32_t s_item;
   const uint32_t n_items = __builtin_amdgcn_readfirstlane(*tq.count);
@@ -1129,7 +1129,7 @@ __global__ __launch_bounds__((bwd_uses_ws<DP, NT>() ? 2 * NT : NT)) void composi
   __syncthreads();
   while (it < n_items) {
     const uint2 item = tq.items[it];
-    if constexpr (bwd_uses_ws<DP, NT>()) bwd_ws_tile<DP, FT, NT, false>(args[item.x], (int)item.y);
+    if constexpr (WS) bwd_ws_tile<DP, FT, NT, false>(args[item.x], (int)item.y);
     else bwd_mfma_tile<DP, FT, NT, false>(args[item.x], (int)item.y);
     if (threadIdx.x == 0) s_item = atomicAdd(tq.head, 1u);
     __syncthreads();
@@ -1266,32 +1266,45 @@ __global__ __launch_bounds__(256) void reduce_rows_kernel(ReduceArgs a) {
 }
 
 template <int DP, typename FT, int NT>
-static void launch_bwd_tiles(const BwdArgs& a, int tiles, hipStream_t s) {
-  if constexpr (bwd_uses_ws<DP, NT>())
-    hipLaunchKernelGGL((composite_bwd_ws_kernel<DP, FT, NT>), dim3(tiles), dim3(2 * NT), 0, s, a);
-  else
-    hipLaunchKernelGGL((composite_bwd_mfma_kernel<DP, FT, NT>), dim3(tiles), dim3(NT), 0, s, a);
+static void launch_bwd_tiles(const BwdArgs& a, int tiles, bool ws, hipStream_t s) {
+  if constexpr (bwd_ws_available<DP, NT>()) {
+    if (ws) {
+      hipLaunchKernelGGL((composite_bwd_ws_kernel<DP, FT, NT>), dim3(tiles), dim3(2 * NT), 0, s, a);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((composite_bwd_mfma_kernel<DP, FT, NT>), dim3(tiles), dim3(NT), 0, s, a);
 }
 
 template <int DP, typename FT>
-hipError_t launch_bwd_nt(int nt, const BwdArgs& a, int tiles, hipStream_t s) {
+hipError_t launch_bwd_nt(int nt, const BwdArgs& a, int tiles, bool ws, hipStream_t s) {
   switch (nt) {
-    case 64: launch_bwd_tiles<DP, FT, 64>(a, tiles, s); break;
-    case 128: launch_bwd_tiles<DP, FT, 128>(a, tiles, s); break;
-    default: launch_bwd_tiles<DP, FT, 256>(a, tiles, s); break;
+    case 64: launch_bwd_tiles<DP, FT, 64>(a, tiles, ws, s); break;
+    case 128: launch_bwd_tiles<DP, FT, 128>(a, tiles, ws, s); break;
+    default: launch_bwd_tiles<DP, FT, 256>(a, tiles, ws, s); break;
   }
   return hipGetLastError();
 }
 
 template <typename FT>
-hipError_t dispatch_bwd(int D, int nt, const BwdArgs& a, int tiles, hipStream_t s) {
-  if (D <= 32) return launch_bwd_nt<32, FT>(nt, a, tiles, s);
-  if (D <= 64) return launch_bwd_nt<64, FT>(nt, a, tiles, s);
-  if (D <= 128) return launch_bwd_nt<128, FT>(nt, a, tiles, s);
-  return launch_bwd_nt<256, FT>(nt, a, tiles, s);
+hipError_t dispatch_bwd(int D, int nt, const BwdArgs& a, int tiles, bool ws, hipStream_t s) {
+  if (D <= 32) return launch_bwd_nt<32, FT>(nt, a, tiles, ws, s);
+  if (D <= 64) return launch_bwd_nt<64, FT>(nt, a, tiles, ws, s);
+  if (D <= 128) return launch_bwd_nt<128, FT>(nt, a, tiles, ws, s);
+  return launch_bwd_nt<256, FT>(nt, a, tiles, ws, s);
 }
 
 }  // namespace
+
+// Wave-specialized backward (2 NT threads per tile) where its kernel exists
+// (D <= 128 and at least as many 32-channel blocks as 64-pixel chunks) and
+// threads_per_tile asks for it or leaves the choice to the library.
+bool backward_wave_specialized(const fe_config* cfg) {
+  const int nt = cfg->tile_w * cfg->tile_h, D = cfg->feat_dim;
+  const int dp = D <= 32 ? 32 : D <= 64 ? 64 : D <= 128 ? 128 : 256;
+  const bool available = dp <= 128 && dp / 32 >= nt / 64;
+  return available && cfg->threads_per_tile != nt;
+}
 
 // Rows are padded to whole 128-byte lines: each 32-channel block of dF and
 // the closing block of the row (the nine projected-space sums and zeros) is
@@ -1340,8 +1353,9 @@ hipError_t launch_composite_bwd_mfma(const fe_config* cfg, const fe_camera* cam,
   if (v.tiles == 0) return hipSuccess;
   const BwdArgs a = make_bwd_args(cfg, cam, g, v, fwd, d_rgb, d_feat, row_base, rows, row_cap, rowidx);
   const int nt = cfg->tile_w * cfg->tile_h;
-  return cfg->feat_dtype == FE_BF16 ? dispatch_bwd<uint16_t>(cfg->feat_dim, nt, a, v.tiles, s)
-                                    : dispatch_bwd<float>(cfg->feat_dim, nt, a, v.tiles, s);
+  const bool ws = backward_wave_specialized(cfg);
+  return cfg->feat_dtype == FE_BF16 ? dispatch_bwd<uint16_t>(cfg->feat_dim, nt, a, v.tiles, ws, s)
+                                    : dispatch_bwd<float>(cfg->feat_dim, nt, a, v.tiles, ws, s);
 }
 
 // ---- persistent multi-frame form (BF16 features, D <= 128) ----
@@ -1354,40 +1368,54 @@ void composite_bwd_record(const fe_config* cfg, const fe_camera* cam, const fe_g
   std::memcpy(dst, &a, sizeof(a));
 }
 
-template <int DP, int NT>
+template <int DP, int NT, bool WS>
 static int bwd_grid() {
   int per_cu = 0, dev = 0;
   hipDeviceProp_t prop;
   if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
-  const int block = bwd_uses_ws<DP, NT>() ? 2 * NT : NT;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, composite_bwd_persistent<DP, uint16_t, NT>, block, 0) !=
-      hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, composite_bwd_persistent<DP, uint16_t, NT, WS>,
+                                                   WS ? 2 * NT : NT, 0) != hipSuccess)
     return 0;
   return per_cu * prop.multiProcessorCount;
 }
 
+template <int DP, int NT>
+static int bwd_grid_ws(bool ws) {
+  if constexpr (bwd_ws_available<DP, NT>()) {
+    if (ws) return bwd_grid<DP, NT, true>();
+  }
+  return bwd_grid<DP, NT, false>();
+}
+
 template <int DP>
-static int bwd_grid_nt(int nt) {
-  return nt == 64 ? bwd_grid<DP, 64>() : nt == 128 ? bwd_grid<DP, 128>() : bwd_grid<DP, 256>();
+static int bwd_grid_nt(int nt, bool ws) {
+  return nt == 64 ? bwd_grid_ws<DP, 64>(ws) : nt == 128 ? bwd_grid_ws<DP, 128>(ws) : bwd_grid_ws<DP, 256>(ws);
 }
 
 int composite_bwd_persistent_grid(const fe_config* cfg) {
   const int nt = cfg->tile_w * cfg->tile_h, D = cfg->feat_dim;
-  return D <= 32 ? bwd_grid_nt<32>(nt) : D <= 64 ? bwd_grid_nt<64>(nt) : bwd_grid_nt<128>(nt);
+  const bool ws = backward_wave_specialized(cfg);
+  return D <= 32 ? bwd_grid_nt<32>(nt, ws) : D <= 64 ? bwd_grid_nt<64>(nt, ws) : bwd_grid_nt<128>(nt, ws);
 }
 
 template <int DP, int NT>
-static void bwd_persistent_launch(const BwdArgs* r, const TileQueue& q, int grid, hipStream_t s) {
-  const int block = bwd_uses_ws<DP, NT>() ? 2 * NT : NT;
-  hipLaunchKernelGGL((composite_bwd_persistent<DP, uint16_t, NT>), dim3(grid), dim3(block), 0, s, r, q);
+static void bwd_persistent_launch(const BwdArgs* r, const TileQueue& q, int grid, bool ws, hipStream_t s) {
+  if constexpr (bwd_ws_available<DP, NT>()) {
+    if (ws) {
+      hipLaunchKernelGGL((composite_bwd_persistent<DP, uint16_t, NT, true>), dim3(grid), dim3(2 * NT), 0, s, r, q);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((composite_bwd_persistent<DP, uint16_t, NT, false>), dim3(grid), dim3(NT), 0, s, r, q);
 }
 
 template <int DP>
-static hipError_t bwd_persistent_nt(int nt, const BwdArgs* r, const TileQueue& q, int grid, hipStream_t s) {
+static hipError_t bwd_persistent_nt(int nt, const BwdArgs* r, const TileQueue& q, int grid, bool ws,
+                                    hipStream_t s) {
   switch (nt) {
-    case 64: bwd_persistent_launch<DP, 64>(r, q, grid, s); break;
-    case 128: bwd_persistent_launch<DP, 128>(r, q, grid, s); break;
-    default: bwd_persistent_launch<DP, 256>(r, q, grid, s); break;
+    case 64: bwd_persistent_launch<DP, 64>(r, q, grid, ws, s); break;
+    case 128: bwd_persistent_launch<DP, 128>(r, q, grid, ws, s); break;
+    default: bwd_persistent_launch<DP, 256>(r, q, grid, ws, s); break;
   }
   return hipGetLastError();
 }
@@ -1396,9 +1424,11 @@ hipError_t launch_composite_bwd_persistent(const fe_config* cfg, const void* rec
                                            int grid, hipStream_t s) {
   if (grid < 1) return hipErrorInvalidValue;
   const int nt = cfg->tile_w * cfg->tile_h, D = cfg->feat_dim;
+  const bool ws = backward_wave_specialized(cfg);
   const BwdArgs* r = static_cast<const BwdArgs*>(records);
-  return D <= 32 ? bwd_persistent_nt<32>(nt, r, q, grid, s)
-                 : D <= 64 ? bwd_persistent_nt<64>(nt, r, q, grid, s) : bwd_persistent_nt<128>(nt, r, q, grid, s);
+  return D <= 32 ? bwd_persistent_nt<32>(nt, r, q, grid, ws, s)
+                 : D <= 64 ? bwd_persistent_nt<64>(nt, r, q, grid, ws, s)
+                           : bwd_persistent_nt<128>(nt, r, q, grid, ws, s);
 }
 
 hipError_t launch_reduce_rows(const fe_config* cfg, const StateView& v, const uint32_t* rowidx,

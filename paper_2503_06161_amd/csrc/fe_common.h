@@ -148,6 +148,13 @@ hipError_t launch_project_bwd(const CamConst& cc, const fe_config* cfg, const fe
                               const StateView& v, const float* grad2d, const fe_grads* out,
                               hipStream_t s);
 
+// Threads per tile of the matrix-core compositing kernels: one per pixel
+// (every wave walks its pixels and runs the contractions) or two per pixel
+// (wave-specialized: walker waves and matrix-core waves); threads_per_tile 0
+// takes the wave-specialized kernel wherever it exists.
+bool forward_wave_specialized(const fe_config* cfg);
+bool backward_wave_specialized(const fe_config* cfg);
+
 // ---- compositing of many frames from one work queue ----
 // Items are (frame, tile) pairs.  The queue builder writes them longest first
 // (by the tile's list length, or by its backward walk length), stores their

@@ -640,15 +640,17 @@ __global__ __launch_bounds__(2 * NT) void composite_fwd_ws_persistent(const Mfma
 }
 
 template <int DP, typename FT>
-hipError_t launch_nt(int nt, const MfmaArgs& a, int tiles, hipStream_t s) {
+hipError_t launch_nt(int nt, const MfmaArgs& a, int tiles, bool ws, hipStream_t s) {
   // wave-specialized kernel for BF16 features up to 128 channels
   if constexpr (std::is_same<FT, uint16_t>::value && DP <= 128) {
-    switch (nt) {
-      case 64: hipLaunchKernelGGL((composite_fwd_ws_kernel<DP, 64>), dim3(tiles), dim3(128), 0, s, a); break;
-      case 128: hipLaunchKernelGGL((composite_fwd_ws_kernel<DP, 128>), dim3(tiles), dim3(256), 0, s, a); break;
-      default: hipLaunchKernelGGL((composite_fwd_ws_kernel<DP, 256>), dim3(tiles), dim3(512), 0, s, a); break;
+    if (ws) {
+      switch (nt) {
+        case 64: hipLaunchKernelGGL((composite_fwd_ws_kernel<DP, 64>), dim3(tiles), dim3(128), 0, s, a); break;
+        case 128: hipLaunchKernelGGL((composite_fwd_ws_kernel<DP, 128>), dim3(tiles), dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL((composite_fwd_ws_kernel<DP, 256>), dim3(tiles), dim3(512), 0, s, a); break;
+      }
+      return hipGetLastError();
     }
-    return hipGetLastError();
   }
   switch (nt) {
     case 64: hipLaunchKernelGGL((composite_fwd_mfma_kernel<DP, FT, 64>), dim3(tiles), dim3(64), 0, s, a); break;
@@ -659,11 +661,11 @@ hipError_t launch_nt(int nt, const MfmaArgs& a, int tiles, hipStream_t s) {
 }
 
 template <typename FT>
-hipError_t dispatch(int D, int nt, const MfmaArgs& a, int tiles, hipStream_t s) {
-  if (D <= 32) return launch_nt<32, FT>(nt, a, tiles, s);
-  if (D <= 64) return launch_nt<64, FT>(nt, a, tiles, s);
-  if (D <= 128) return launch_nt<128, FT>(nt, a, tiles, s);
-  return launch_nt<256, FT>(nt, a, tiles, s);
+hipError_t dispatch(int D, int nt, const MfmaArgs& a, int tiles, bool ws, hipStream_t s) {
+  if (D <= 32) return launch_nt<32, FT>(nt, a, tiles, ws, s);
+  if (D <= 64) return launch_nt<64, FT>(nt, a, tiles, ws, s);
+  if (D <= 128) return launch_nt<128, FT>(nt, a, tiles, ws, s);
+  return launch_nt<256, FT>(nt, a, tiles, ws, s);
 }
 
 }  // namespace
@@ -700,13 +702,20 @@ hipError_t launch_composite_fwd_mfma(const fe_config* cfg, const fe_camera* cam,
   if (v.tiles == 0) return hipSuccess;
   const MfmaArgs a = make_args(cfg, cam, g, v, out);
   const int nt = cfg->tile_w * cfg->tile_h;
-  return cfg->feat_dtype == FE_BF16 ? dispatch<uint16_t>(cfg->feat_dim, nt, a, v.tiles, s)
-                                    : dispatch<float>(cfg->feat_dim, nt, a, v.tiles, s);
+  const bool ws = forward_wave_specialized(cfg);
+  return cfg->feat_dtype == FE_BF16 ? dispatch<uint16_t>(cfg->feat_dim, nt, a, v.tiles, ws, s)
+                                    : dispatch<float>(cfg->feat_dim, nt, a, v.tiles, ws, s);
+}
+
+// Wave-specialized forward (2 NT threads per tile) for BF16 features up to
+// 128 channels, unless threads_per_tile asks for one thread per pixel.
+bool forward_wave_specialized(const fe_config* cfg) {
+  return cfg->feat_dtype == FE_BF16 && cfg->feat_dim <= 128 && cfg->threads_per_tile != cfg->tile_w * cfg->tile_h;
 }
 
 // ---- persistent multi-frame form (wave-specialized kernels only) ----
 bool composite_persistent_supported(const fe_config* cfg) {
-  return cfg->variant != FE_VARIANT_VALU && cfg->feat_dtype == FE_BF16 && cfg->feat_dim <= 128;
+  return cfg->variant != FE_VARIANT_VALU && forward_wave_specialized(cfg);
 }
 
 size_t composite_fwd_record_bytes() { return sizeof(MfmaArgs); }

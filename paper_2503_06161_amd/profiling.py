@@ -1,0 +1,121 @@
+"""Summaries of rocprofv3 output for the kernels of this library.
+
+Reads the CSV files rocprofv3 writes (``--kernel-trace --stats`` and
+``--pmc`` runs, ``--output-format csv``) and prints short Markdown or JSON
+summaries: per-kernel average duration, and per-kernel counter values
+averaged over dispatches.  HBM traffic counters are scaled by the same
+counters read on a plain device copy of known size (``bench.py
+--calibrate-copy`` issues one 256 MiB copy), so that FETCH_SIZE / WRITE_SIZE
+become bytes.
+
+  python -m paper_2503_06161_amd.profiling trace <dir> [--match REGEX]
+  python -m paper_2503_06161_amd.profiling pmc <dir> [<dir> ...] [--match REGEX] [--json KERNEL]
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import json
+import os
+import re
+import sys
+from collections import defaultdict
+
+COPY_BYTES = 256 << 20      # bench.py --calibrate-copy
+
+
+def _csv_rows(root: str, suffix: str):
+    rows = []
+    for path in sorted(glob.glob(os.path.join(root, "**", f"*{suffix}"), recursive=True)):
+        with open(path, newline="") as f:
+            rows.extend(csv.DictReader(f))
+    return rows
+
+
+def _short(name: str) -> str:
+    name = re.sub(r"^void ", "", name)
+    name = re.sub(r"\(.*\)$", "", name)               # argument list
+    name = name.replace("fe::(anonymous namespace)::", "").replace("fe::", "")
+    return name.replace("unsigned short", "bf16")
+
+
+def kernel_times(root: str):
+    """{kernel: (dispatches, average us, grid, block, lds, vgpr, agpr, scratch)} from the kernel trace."""
+    acc = defaultdict(list)
+    info = {}
+    for r in _csv_rows(root, "kernel_trace.csv"):
+        k = _short(r["Kernel_Name"])
+        acc[k].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        info[k] = (r.get("Grid_Size", ""), r.get("Workgroup_Size", ""), r.get("LDS_Block_Size", ""),
+                   r.get("VGPR_Count", ""), r.get("Accum_VGPR_Count", ""), r.get("Scratch_Size", ""))
+    return {k: (len(v), sum(v) / len(v)) + info[k] for k, v in acc.items()}
+
+
+def counters(roots):
+    """{kernel: {counter: average value per dispatch}} over one or more --pmc runs."""
+    acc = defaultdict(lambda: defaultdict(list))
+    for root in roots:
+        for r in _csv_rows(root, "counter_collection.csv"):
+            acc[_short(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    return {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in acc.items()}
+
+
+def copy_scale(cnt):
+    """Bytes per FETCH_SIZE / WRITE_SIZE unit from the calibration copy
+    (the one kernel whose name holds 'copy' or 'elementwise')."""
+    for k, d in cnt.items():
+        if re.search(r"copy|elementwise", k, re.I) and "FETCH_SIZE" in d and "WRITE_SIZE" in d:
+            return COPY_BYTES / (d["FETCH_SIZE"] * 1024.0), COPY_BYTES / (d["WRITE_SIZE"] * 1024.0)
+    for k, d in cnt.items():
+        if re.search(r"copy|elementwise", k, re.I):
+            f = COPY_BYTES / (d["FETCH_SIZE"] * 1024.0) if "FETCH_SIZE" in d else None
+            w = COPY_BYTES / (d["WRITE_SIZE"] * 1024.0) if "WRITE_SIZE" in d else None
+            return f, w
+    return None, None
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("dir")
+    t.add_argument("--match", default=".")
+    p = sub.add_parser("pmc")
+    p.add_argument("dirs", nargs="+")
+    p.add_argument("--match", default=".")
+    p.add_argument("--json", default=None, help="print the traffic record of the first kernel matching this regex")
+    a = ap.parse_args(argv)
+    if a.cmd == "trace":
+        kt = kernel_times(a.dir)
+        print("| kernel | dispatches | avg µs | grid | block | LDS B | VGPR | AGPR | scratch |")
+        print("|---|---:|---:|---:|---:|---:|---:|---:|---:|")
+        for k, (n, us, grid, blk, lds, vg, ag, scr) in sorted(kt.items(), key=lambda kv: -kv[1][1] * kv[1][0]):
+            if re.search(a.match, k):
+                print(f"| `{k}` | {n} | {us:.2f} | {grid} | {blk} | {lds} | {vg} | {ag} | {scr} |")
+        return 0
+    cnt = counters(a.dirs)
+    fs, ws = copy_scale(cnt)
+    if a.json:
+        for k, d in cnt.items():
+            if re.search(a.json, k):
+                rd = d.get("FETCH_SIZE", 0.0) * 1024.0 * (fs or 0.0)
+                wr = d.get("WRITE_SIZE", 0.0) * 1024.0 * (ws or 0.0)
+                print(json.dumps({"kernel": k, "read_bytes": round(rd), "write_bytes": round(wr),
+                                  "bytes_per_launch": round(rd + wr), "fetch_scale": fs, "write_scale": ws}))
+                return 0
+        return 1
+    names = sorted({c for d in cnt.values() for c in d})
+    print(f"copy calibration: bytes per FETCH_SIZE KiB = {fs and fs * 1024:.1f}, per WRITE_SIZE KiB = "
+          f"{ws and ws * 1024:.1f}" if fs or ws else "no calibration copy in these runs")
+    print()
+    print("| kernel | " + " | ".join(names) + " |")
+    print("|---|" + "---:|" * len(names))
+    for k, d in sorted(cnt.items()):
+        if re.search(a.match, k):
+            print(f"| `{k}` | " + " | ".join(f"{d[c]:.4g}" if c in d else "" for c in names) + " |")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -141,12 +141,13 @@ class Settings:
     key_capacity: int | None = None
     row_capacity: int | None = None  # None: the forward's reported need (or key_capacity)
     variant: int = FE_VARIANT_AUTO
+    threads_per_tile: int = 0       # 0: library choice; tile pixels or twice that (fe_config.threads_per_tile)
     flags: int = 0
     stage_events: object = None     # optional ctypes array of 2*len(STAGES) hipEvent_t handles
 
     def to_c(self, cap: int, rows: int = 0) -> fe_config:
         c = fe_config()
-        c.tile_w, c.tile_h, c.threads_per_tile = self.tile_w, self.tile_h, 0
+        c.tile_w, c.tile_h, c.threads_per_tile = self.tile_w, self.tile_h, self.threads_per_tile
         c.sh_degree, c.feat_dim = self.sh_degree, self.feat_dim
         c.sh_dtype = FE_BF16 if self.sh_dtype == "bf16" else FE_F32
         c.feat_dtype = FE_BF16 if self.feat_dtype == "bf16" else FE_F32

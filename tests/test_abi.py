@@ -100,3 +100,26 @@ def test_forward_rejects_bad_arguments_before_any_gpu_work():
     rep = rast.fe_report()
     assert lib.fe_read_report(None, 0, C.byref(rep), None) == rast.FE_ERR_INVALID_ARG
     assert lib.fe_status_string(rast.FE_ERR_KEY_OVERFLOW) == b"sort key capacity exceeded"
+
+
+def test_threads_per_tile_choices():
+    """threads_per_tile: 0, one per pixel, or two per pixel where the
+    wave-specialized kernels exist in both directions (host-only checks)."""
+    from paper_2503_06161_amd import rast
+    lib = rast.load_library()
+    cam = rast.camera_c(_cam())
+
+    def v(**kw):
+        return lib.fe_validate(C.byref(_cfg(**kw).to_c(1 << 20)), C.byref(cam), 1000)
+
+    bf = dict(sh_dtype="bf16", feat_dtype="bf16", variant=rast.FE_VARIANT_MFMA)
+    assert v(feat_dim=128, threads_per_tile=0, **bf) == rast.FE_OK
+    assert v(feat_dim=128, threads_per_tile=256, **bf) == rast.FE_OK
+    assert v(feat_dim=128, threads_per_tile=512, **bf) == rast.FE_OK
+    assert v(feat_dim=64, tile_w=16, tile_h=8, threads_per_tile=256, **bf) == rast.FE_OK
+    assert v(feat_dim=32, threads_per_tile=512, **bf) == rast.FE_ERR_UNSUPPORTED      # 1 block < 4 pixel groups
+    assert v(feat_dim=200, threads_per_tile=512, **bf) == rast.FE_ERR_UNSUPPORTED     # D > 128
+    assert v(feat_dim=128, threads_per_tile=512, variant=rast.FE_VARIANT_MFMA) == rast.FE_ERR_UNSUPPORTED  # FP32
+    assert v(feat_dim=128, threads_per_tile=512, sh_dtype="bf16", feat_dtype="bf16",
+             variant=rast.FE_VARIANT_VALU) == rast.FE_ERR_UNSUPPORTED
+    assert v(feat_dim=128, threads_per_tile=100, **bf) == rast.FE_ERR_UNSUPPORTED

@@ -26,17 +26,23 @@ def test_candidates_agree_and_choice_is_cached(tmp_path, monkeypatch):
     d = U.to_device(sc, "bf16")
     st = rast.Settings(sh_degree=3, feat_dim=32, sh_dtype="bf16", feat_dtype="bf16")
     ref = None
-    for tw, th in autotune.TILE_SHAPES:
-        for v in autotune.VARIANTS:
-            s2 = rast.Settings(**{**st.__dict__, "tile_w": tw, "tile_h": th, "variant": v})
-            f = rast.render_forward(d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["feat"], cam, s2)
-            if ref is None:
-                ref = f
-            assert torch.equal(f.rgb, ref.rgb) and torch.equal(f.final_T, ref.final_T)
-            torch.testing.assert_close(f.feat, ref.feat, rtol=0, atol=2e-6)
+    cands = autotune.candidates_for(st, cam, sc.n)
+    # both thread counts are offered where the two-per-pixel kernels exist
+    assert (8, 8, rast.FE_VARIANT_MFMA, 64) in cands and (8, 8, rast.FE_VARIANT_MFMA, 128) in cands
+    assert (16, 16, rast.FE_VARIANT_MFMA, 256) in cands and (16, 16, rast.FE_VARIANT_MFMA, 0) in cands
+    assert (16, 16, rast.FE_VARIANT_MFMA, 512) not in cands      # D = 32: one channel block, four pixel groups
+    assert (16, 16, rast.FE_VARIANT_VALU, 512) not in cands and (16, 16, rast.FE_VARIANT_VALU, 256) in cands
+    for tw, th, v, tpt in cands:
+        s2 = rast.Settings(**{**st.__dict__, "tile_w": tw, "tile_h": th, "variant": v, "threads_per_tile": tpt})
+        f = rast.render_forward(d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["feat"], cam, s2)
+        if ref is None:
+            ref = f
+        assert torch.equal(f.rgb, ref.rgb) and torch.equal(f.final_T, ref.final_T)
+        torch.testing.assert_close(f.feat, ref.feat, rtol=0, atol=2e-6)
     g_rgb = torch.zeros(3, 64, 96, device="cuda")
     g_feat = torch.full((32, 64, 96), 1e-3, device="cuda")
     best = autotune.autotune(d, cam, st, g_rgb, g_feat, verbose=True)
     assert (best.tile_w, best.tile_h) in autotune.TILE_SHAPES
-    again = autotune.autotune(d, cam, st, g_rgb, g_feat, candidates=[(8, 8, rast.FE_VARIANT_VALU)])
-    assert (again.tile_w, again.tile_h, again.variant) == (best.tile_w, best.tile_h, best.variant)
+    again = autotune.autotune(d, cam, st, g_rgb, g_feat, candidates=[(8, 8, rast.FE_VARIANT_VALU, 64)])
+    assert ((again.tile_w, again.tile_h, again.variant, again.threads_per_tile)
+            == (best.tile_w, best.tile_h, best.variant, best.threads_per_tile))

@@ -130,3 +130,28 @@ def test_metric_window_d128(dtype, variant):
     torch.cuda.synchronize()
     ob = U.oracle_backward(sw, st, d_rgb, d_feat, cam=cam)
     U.check_grads(gr, ob)
+
+
+@pytest.mark.parametrize("tile,threads", [((16, 16), 256), ((16, 16), 512), ((16, 8), 128), ((16, 8), 256),
+                                          ((8, 8), 64), ((8, 8), 128)])
+def test_threads_per_tile(tile, threads):
+    # one thread per pixel (single-role kernels) or two (wave-specialized),
+    # 56x40 window of the metric workload, D = 128 BF16, against the oracle
+    say("metric window 56x40 D=128 bf16 tile", tile, "threads per tile", threads)
+    sc = make_scene("metric")
+    cam = crop_camera(sc.cam, 292, 232, 56, 40)
+    sw = _subset_scene(sc, cam)
+    st = U.settings_for(sc, tile=tile, dtype="bf16", variant=rast.FE_VARIANT_MFMA, threads_per_tile=threads)
+    fwd, d = U.gpu_forward(sw, st, cam=cam)
+    gs = U.read_state(fwd, sc.n, st, cam)
+    orc = U.oracle_forward(sw, st, cam=cam)
+    U.compare_keys(gs, orc)
+    say("fwd", U.compare_images(fwd, orc, sw, st))
+    rng = np.random.default_rng(13)
+    d_rgb = rng.normal(0, 1, (3, 40, 56)).astype(np.float32)
+    d_feat = rng.normal(0, 1, (128, 40, 56)).astype(np.float32)
+    gr = rast.render_backward(fwd, d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["feat"],
+                              torch.from_numpy(d_rgb).cuda(), torch.from_numpy(d_feat).cuda(), st)
+    torch.cuda.synchronize()
+    U.check_grads(gr, U.oracle_backward(sw, st, d_rgb, d_feat, cam=cam))
+
