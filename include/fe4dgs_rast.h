@@ -238,6 +238,25 @@ fe_status fe_render_backward(const fe_config* cfg, const fe_camera* cam, const f
                              const float* d_rgb, const float* d_feat, const fe_grads* out,
                              void* scratch, size_t scratch_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * fe_render_backward with its scratch in a library-held device array of
+ * FE_NOALLOC_SCRATCH_BYTES per GPU (allocated when the library's device code
+ * is loaded on that GPU, held until the process ends).  Same arguments and
+ * results as fe_render_backward without scratch / scratch_bytes; the device
+ * is the current one (the stream must belong to it).  Returns
+ * FE_ERR_WORKSPACE_TOO_SMALL, before enqueuing anything, when
+ * fe_backward_scratch_bytes() exceeds FE_NOALLOC_SCRATCH_BYTES: set
+ * row_capacity to the forward's report.rows_needed (or a bound of it) rather
+ * than leaving it at key_capacity.  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (other streams, other threads) race;
+ * calls in order on one stream do not.  Calls no allocating routine. */
+#define FE_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+fe_status fe_render_backward_noalloc(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
+                                     const fe_images* fwd, const void* state, size_t state_bytes,
+                                     const float* d_rgb, const float* d_feat, const fe_grads* out,
+                                     void* stream);
+
 /* Copy the device report of `state` to the host.  Synchronises `stream`.
  * Returns report->status as the call's status (FE_ERR_KEY_OVERFLOW when the
  * frame needed more keys than key_capacity, FE_ERR_ROW_OVERFLOW when a

@@ -84,6 +84,9 @@ EXPORTS = {
     "fe_render_backward": (C.c_int, [C.POINTER(fe_config), C.POINTER(fe_camera), C.POINTER(fe_gaussians),
                                      C.POINTER(fe_images), C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
                                      C.POINTER(fe_grads), C.c_void_p, C.c_size_t, C.c_void_p]),
+    "fe_render_backward_noalloc": (C.c_int, [C.POINTER(fe_config), C.POINTER(fe_camera), C.POINTER(fe_gaussians),
+                                             C.POINTER(fe_images), C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
+                                             C.POINTER(fe_grads), C.c_void_p]),
     "fe_read_report": (C.c_int, [C.c_void_p, C.c_size_t, C.POINTER(fe_report), C.c_void_p]),
     "fe_batch_workspace_bytes": (C.c_size_t, [C.POINTER(fe_config), C.POINTER(fe_camera), C.c_int32,
                                               C.POINTER(C.c_int64)]),
@@ -333,6 +336,41 @@ def render_backward(fwd: ForwardResult, means, scales, quats, opacity, sh, feat,
             raise RasterError(FE_ERR_ROW_OVERFLOW, f"fe_render_backward needs {rep['rows_needed']} rows, "
                                                    f"row_capacity is {cfg.row_capacity}")
         _check(rep["status"], "fe_render_backward (device)")
+    return grads
+
+
+NOALLOC_SCRATCH_BYTES = 256 << 20    # FE_NOALLOC_SCRATCH_BYTES
+
+
+def render_backward_noalloc(fwd: ForwardResult, means, scales, quats, opacity, sh, feat, d_rgb, d_feat,
+                            st: Settings, grads: dict, stream=None, check: bool = True) -> dict:
+    """fe_render_backward_noalloc: the backward with its scratch in the
+    library's per-GPU array (nothing is allocated; ``grads`` are the caller's
+    float32 output buffers).  Raises FE_ERR_WORKSPACE_TOO_SMALL when the
+    frame's scratch exceeds NOALLOC_SCRATCH_BYTES."""
+    lib = load_library()
+    H, W, D = fwd.cam.height, fwd.cam.width, st.feat_dim
+    _req(d_rgb, torch.float32, (3, H, W), "d_rgb")
+    _req(d_feat, torch.float32, (D, H, W), "d_feat")
+    g = _gaussians_c(means, scales, quats, opacity, sh, feat, st)
+    cfg = fe_config.from_buffer_copy(fwd.cfg)
+    cfg.stage_events = None
+    if st.row_capacity is not None:
+        cfg.row_capacity = int(st.row_capacity)
+    elif fwd.report is not None:
+        cfg.row_capacity = max(int(fwd.report["rows_needed"]), 1)
+    gr = fe_grads(_ptr(grads["means"]), _ptr(grads["scales"]), _ptr(grads["quats"]), _ptr(grads["opacity"]),
+                  _ptr(grads["sh"]), _ptr(grads["feat"]), _ptr(grads.get("means2d")))
+    im = fe_images(_ptr(fwd.rgb), _ptr(fwd.feat), _ptr(fwd.final_T), _ptr(fwd.n_contrib))
+    _check(lib.fe_render_backward_noalloc(C.byref(cfg), C.byref(fwd.cam), C.byref(g), C.byref(im),
+                                          C.c_void_p(fwd.state.data_ptr()), fwd.state.numel(),
+                                          C.c_void_p(d_rgb.data_ptr()), C.c_void_p(d_feat.data_ptr()), C.byref(gr),
+                                          C.c_void_p(_stream_handle(stream))), "fe_render_backward_noalloc")
+    if check:
+        rep = read_report(fwd.state, stream)
+        if rep["backward_status"] == FE_ERR_ROW_OVERFLOW:
+            raise RasterError(FE_ERR_ROW_OVERFLOW, "fe_render_backward_noalloc: row capacity exceeded")
+        _check(rep["status"], "fe_render_backward_noalloc (device)")
     return grads
 
 
