@@ -53,6 +53,8 @@ def _parse():
     ap.add_argument("--variant", default="mfma", choices=["mfma", "valu"],
                     help="compositing kernels: matrix cores (default) or vector ALU")
     ap.add_argument("--no-batched", action="store_true", help="skip the 16-timestamp graph form")
+    ap.add_argument("--batch-tile", default=None,
+                    help="TWxTH[:THREADS] for the 16-timestamp form instead of the autotuner's choice")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for HBM counters)")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the FP64-oracle accuracy block")
@@ -190,7 +192,7 @@ def run_form(sc, form, steps, warmup, variant="mfma", key_capacity=None, keep=Fa
     return res
 
 
-def run_batched(steps, warmup):
+def run_batched(steps, warmup, fixed=None):
     """16 timestamps of one deforming scene (50k-200k Gaussians per frame,
     D=64 BF16, 640x512), forward+backward of all frames as one graph replay."""
     import numpy as np
@@ -212,9 +214,16 @@ def run_batched(steps, warmup):
     d_rgb = [t(rng.normal(0, 1e-3, (3, H, W)).astype(np.float32)) for _ in fr]
     d_feat = [t(rng.normal(0, 1e-3, (64, H, W)).astype(np.float32)) for _ in fr]
     st = rast.Settings(sh_degree=3, feat_dim=64, sh_dtype="bf16", feat_dtype="bf16")
-    # tile shape and variant from the batch autotuner (untimed; whole replays)
-    from paper_2503_06161_amd import autotune
-    st = autotune.autotune_batch(frames, cams, st, d_rgb, d_feat)
+    if fixed:
+        shape, _, tpt = fixed.partition(":")
+        tw, th = (int(x) for x in shape.split("x"))
+        st = rast.Settings(**{**st.__dict__, "tile_w": tw, "tile_h": th, "variant": rast.FE_VARIANT_MFMA,
+                              "threads_per_tile": int(tpt or 0)})
+    else:
+        # tile shape, threads per tile and variant from the batch autotuner
+        # (untimed; whole replays)
+        from paper_2503_06161_amd import autotune
+        st = autotune.autotune_batch(frames, cams, st, d_rgb, d_feat)
     br = BatchRenderer(frames, cams, st, rast.FE_MODE_FORWARD_BACKWARD, d_rgb, d_feat)
     for _ in range(warmup):
         br.launch()
@@ -494,7 +503,7 @@ def main():
     if not args.no_batched:
         _log("16 timestamps")
         try:
-            line["batched_16_timestamps"] = run_batched(max(3, args.steps // 2), 2)
+            line["batched_16_timestamps"] = run_batched(max(3, args.steps // 2), 2, args.batch_tile)
         except Exception as e:  # reported, never hides the main measurement
             line["batched_16_timestamps"] = {"error": repr(e)[:200]}
     if keep:
