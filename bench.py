@@ -63,13 +63,21 @@ def _parse():
     return ap.parse_args()
 
 
+def _depth_grad(sc):
+    """Upstream gradient of the depth image, N(0, 1e-3) like the others (its
+    own generator, so the scene's draws are unchanged)."""
+    import numpy as np
+    return np.random.default_rng(1000 + sc.n).normal(0.0, 1e-3, (sc.cam.height, sc.cam.width)).astype(np.float32)
+
+
 def _device_inputs(sc, form):
     import numpy as np
     import torch
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     lo = torch.bfloat16 if form == "bf16" else torch.float32
-    return dict(means=t(sc.means), scales=t(sc.scales), quats=t(sc.quats), opacity=t(sc.opacity),
-                sh=t(sc.sh).to(lo).contiguous(), feat=t(sc.feat).to(lo).contiguous()), t(sc.d_rgb), t(sc.d_feat)
+    return (dict(means=t(sc.means), scales=t(sc.scales), quats=t(sc.quats), opacity=t(sc.opacity),
+                 sh=t(sc.sh).to(lo).contiguous(), feat=t(sc.feat).to(lo).contiguous()), t(sc.d_rgb), t(sc.d_feat),
+            t(_depth_grad(sc)))
 
 
 def _processed_pairs(n_contrib, tile_w, tile_h):
@@ -88,10 +96,11 @@ def _algorithmic_bytes(stage, n, k, pairs, H, W, D, L, eb):
     """Bytes a stage must move once (inputs read once, outputs written once)."""
     K3 = 3 * (L + 1) ** 2
     rec = 8 + 16 + 16 + 8                       # xy, conic+opacity, colour, pixel box
+    # per pixel: colour (3), depth (1), D features, final T and n_contrib
     if stage == "composite":
-        return pairs * (rec + D * eb) + H * W * ((D + 3) * 4 + 8)
+        return pairs * (rec + D * eb) + H * W * ((D + 4) * 4 + 8)
     if stage == "composite_bwd":
-        return H * W * ((D + 3) * 4 + 8) + pairs * (rec + D * eb) + pairs * (D + 9) * 4
+        return H * W * ((D + 4) * 4 + 8) + pairs * (rec + D * eb) + pairs * (D + 10) * 4
     if stage == "project":
         return n * (12 + 12 + 16 + 4 + K3 * eb) + n * (rec + 8)
     if stage == "project_bwd":
@@ -109,7 +118,7 @@ def run_form(sc, form, steps, warmup, variant="mfma", key_capacity=None, keep=Fa
     `keep` the last step's images and gradients are returned on the host."""
     import torch
     from paper_2503_06161_amd import rast
-    d, d_rgb, d_feat = _device_inputs(sc, form)
+    d, d_rgb, d_feat, d_depth = _device_inputs(sc, form)
     st = rast.Settings(sh_degree=sc.sh_degree, feat_dim=sc.feat_dim, tile_w=16, tile_h=16,
                        sh_dtype=form, feat_dtype=form, key_capacity=key_capacity,
                        variant=rast.FE_VARIANT_VALU if variant == "valu" else rast.FE_VARIANT_MFMA)
@@ -118,7 +127,7 @@ def run_form(sc, form, steps, warmup, variant="mfma", key_capacity=None, keep=Fa
     rep = fwd.report
     st.key_capacity = fwd.cfg.key_capacity
     st.row_capacity = max(int(rep["rows_needed"]), 1)
-    out = dict(rgb=fwd.rgb, feat=fwd.feat, final_T=fwd.final_T, n_contrib=fwd.n_contrib)
+    out = dict(rgb=fwd.rgb, feat=fwd.feat, final_T=fwd.final_T, n_contrib=fwd.n_contrib, depth=fwd.depth)
     grads = None
     scratch = None
 
@@ -126,7 +135,8 @@ def run_form(sc, form, steps, warmup, variant="mfma", key_capacity=None, keep=Fa
         nonlocal fwd, grads, scratch
         st.stage_events = events
         f = rast.render_forward(*args, sc.cam, st, check=False, state=fwd.state, out=out)
-        g = rast.render_backward(f, *args, d_rgb, d_feat, st, grads=grads, scratch=scratch, check=False)
+        g = rast.render_backward(f, *args, d_rgb, d_feat, st, grads=grads, scratch=scratch, check=False,
+                                 d_depth=d_depth)
         fwd, grads, scratch = f, g, g["_scratch"]
 
     for _ in range(warmup):
@@ -184,10 +194,10 @@ def run_form(sc, form, steps, warmup, variant="mfma", key_capacity=None, keep=Fa
     res = dict(ms_per_step=1e3 * (t1 - t0) / steps, fps=steps / (t1 - t0), stage_ms=stage_ms, pairs=pairs,
                keys=int(rep2["keys_needed"]), report=rep2, eb=2 if form == "bf16" else 4)
     if keep:
-        res["images"] = {k: out[k].double().cpu().numpy() for k in ("rgb", "feat", "final_T")}
+        res["images"] = {k: out[k].double().cpu().numpy() for k in ("rgb", "feat", "depth", "final_T")}
         res["grads"] = {k: grads[k].double().cpu().numpy() for k in ("means", "scales", "quats", "opacity", "sh",
                                                                         "feat")}
-    del d, d_rgb, d_feat, fwd, grads, scratch, out
+    del d, d_rgb, d_feat, d_depth, fwd, grads, scratch, out
     torch.cuda.empty_cache()
     return res
 
@@ -213,6 +223,7 @@ def run_batched(steps, warmup, fixed=None):
     H, W = sc.cam.height, sc.cam.width
     d_rgb = [t(rng.normal(0, 1e-3, (3, H, W)).astype(np.float32)) for _ in fr]
     d_feat = [t(rng.normal(0, 1e-3, (64, H, W)).astype(np.float32)) for _ in fr]
+    d_depth = [t(rng.normal(0, 1e-3, (H, W)).astype(np.float32)) for _ in fr]
     st = rast.Settings(sh_degree=3, feat_dim=64, sh_dtype="bf16", feat_dtype="bf16")
     if fixed:
         shape, _, tpt = fixed.partition(":")
@@ -224,7 +235,7 @@ def run_batched(steps, warmup, fixed=None):
         # (untimed; whole replays)
         from paper_2503_06161_amd import autotune
         st = autotune.autotune_batch(frames, cams, st, d_rgb, d_feat)
-    br = BatchRenderer(frames, cams, st, rast.FE_MODE_FORWARD_BACKWARD, d_rgb, d_feat)
+    br = BatchRenderer(frames, cams, st, rast.FE_MODE_FORWARD_BACKWARD, d_rgb, d_feat, d_depth=d_depth)
     for _ in range(warmup):
         br.launch()
     torch.cuda.synchronize()
@@ -239,20 +250,20 @@ def run_batched(steps, warmup, fixed=None):
     # the same 16 frames as 16 separate forward+backward calls on one stream
     # (same settings, buffers sized once)
     per = []
-    for f, cam, gr_, gf_ in zip(frames, cams, d_rgb, d_feat):
+    for f, cam, gr_, gf_, gd_ in zip(frames, cams, d_rgb, d_feat, d_depth):
         args = (f["means"], f["scales"], f["quats"], f["opacity"], f["sh"], f["feat"])
         fw = rast.render_forward(*args, cam, st, check=True)
         st_f = rast.Settings(**{**st.__dict__, "key_capacity": fw.cfg.key_capacity,
                                 "row_capacity": max(int(fw.report["rows_needed"]), 1)})
-        per.append([args, cam, gr_, gf_, st_f, fw, None, None])
+        per.append([args, cam, gr_, gf_, gd_, st_f, fw, None, None])
 
     def calls():
         for e in per:
-            args, cam, gr_, gf_, st_f, fw, g, scr = e
-            out = dict(rgb=fw.rgb, feat=fw.feat, final_T=fw.final_T, n_contrib=fw.n_contrib)
+            args, cam, gr_, gf_, gd_, st_f, fw, g, scr = e
+            out = dict(rgb=fw.rgb, feat=fw.feat, final_T=fw.final_T, n_contrib=fw.n_contrib, depth=fw.depth)
             f2 = rast.render_forward(*args, cam, st_f, check=False, state=fw.state, out=out)
-            g2 = rast.render_backward(f2, *args, gr_, gf_, st_f, grads=g, scratch=scr, check=False)
-            e[5], e[6], e[7] = f2, g2, g2["_scratch"]
+            g2 = rast.render_backward(f2, *args, gr_, gf_, st_f, grads=g, scratch=scr, check=False, d_depth=gd_)
+            e[6], e[7], e[8] = f2, g2, g2["_scratch"]
 
     for _ in range(warmup):
         calls()
@@ -277,9 +288,10 @@ def _img_errors(g, o, clean):
     without a near-threshold decision (those are counted, not compared)."""
     import numpy as np
     out = {}
-    for k in ("rgb", "feat"):
+    for k in ("rgb", "feat", "depth"):
         ref = max(float(np.abs(o[k]).max()), 1e-30)
-        out[k] = float(np.abs(g[k] - o[k])[:, clean].max() / ref)
+        diff = np.abs(g[k] - o[k]).reshape(-1, *clean.shape)
+        out[k] = float(diff[:, clean].max() / ref)
     out["final_T"] = float(np.abs(g["final_T"] - o["final_T"])[clean].max())
     out["pixels_near_threshold"] = int((~clean).sum())
     return out
@@ -307,16 +319,18 @@ def accuracy_and_cpu_baseline(sc, forms):
     from paper_2503_06161_amd.scenes import bf16_round
     cfg = oracle.OracleConfig(tile_w=16, tile_h=16, sh_degree=sc.sh_degree)
     base = dict(means=sc.means, scales=sc.scales, quats=sc.quats, opacity=sc.opacity)
+    d_depth = _depth_grad(sc)
     refs = {}
     t_bwd = None
     for name, sh, feat in (("stored_bf16", bf16_round(sc.sh), bf16_round(sc.feat)), ("f32", sc.sh, sc.feat)):
         inp = dict(base, sh=sh, feat=feat)
         of = oracle.render_forward(**inp, cam=sc.cam, cfg=cfg, amb_delta=(2e-6, 2e-6, 1e-5))
         t0 = time.perf_counter()
-        ob = oracle.render_backward(**inp, cam=sc.cam, cfg=cfg, d_rgb=sc.d_rgb, d_feat=sc.d_feat)
+        ob = oracle.render_backward(**inp, cam=sc.cam, cfg=cfg, d_rgb=sc.d_rgb, d_feat=sc.d_feat, d_depth=d_depth)
         if name == "stored_bf16":
             t_bwd = time.perf_counter() - t0
-        refs[name] = ({"rgb": of["rgb"].numpy(), "feat": of["feat"].numpy(), "final_T": of["final_T"].numpy()},
+        refs[name] = ({"rgb": of["rgb"].numpy(), "feat": of["feat"].numpy(), "depth": of["depth"].numpy(),
+                       "final_T": of["final_T"].numpy()},
                       ~of["ambiguous"].numpy(), ob)
     acc = {}
     for form, r in forms.items():

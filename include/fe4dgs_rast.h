@@ -10,8 +10,9 @@
  *   - it is binned into screen tiles by its 3-sigma pixel box, and every
  *     tile's list is ordered front to back (by view-space depth, ties by
  *     Gaussian index);
- *   - every pixel blends colour and the D semantic channels front to back with
- *     the same weights alpha_i prod_{j<i}(1 - alpha_j) (eqs. 7 and 8), where
+ *   - every pixel blends colour, depth and the D semantic channels front to
+ *     back with the same weights alpha_i prod_{j<i}(1 - alpha_j) (eqs. 7 and
+ *     8; colour, depth and semantics in one pass, Sec. 3 overview), where
  *     alpha_i = min(0.99, o_i exp(-q/2)) (eq. 1 in 2-D), q = d^T Sigma'^-1 d,
  *     Gaussians with q > 9 or outside their box are ignored, alpha < 1/255 is
  *     skipped, and a pixel stops before the Gaussian that would take its
@@ -28,8 +29,9 @@
  *     0..3, coefficient index l^2 + l + m, layout [n][(L+1)^2][3];
  *     colour = max(0, sum_k sh_k Y_k(dir) + 0.5), dir = normalise(mu - campos).
  *   - images are planar float32: rgb [3][H][W], feat [D][H][W],
- *     final_T [H][W], n_contrib [H][W] (1 + list position of the last
- *     blended Gaussian in the pixel's tile list).
+ *     depth [H][W] (sum of the weights times each Gaussian's view-space depth
+ *     tz; background 0), final_T [H][W], n_contrib [H][W] (1 + list position
+ *     of the last blended Gaussian in the pixel's tile list).
  *   - BF16 storage is accepted for sh and feat only (round-to-nearest-even
  *     bfloat16, passed as uint16 bit patterns); all arithmetic and every
  *     gradient are float32 (projection geometry in float64).
@@ -55,7 +57,7 @@
 extern "C" {
 #endif
 
-#define FE4DGS_ABI_VERSION 3
+#define FE4DGS_ABI_VERSION 4
 
 typedef enum fe_status {
   FE_OK = 0,
@@ -154,6 +156,7 @@ typedef struct fe_images {
   float* feat;                   /* [D][H][W]                                   */
   float* final_T;                /* [H][W]                                      */
   int32_t* n_contrib;            /* [H][W]                                      */
+  float* depth;                  /* [H][W], or NULL (not written)               */
 } fe_images;
 
 /* Backward outputs (device, float32; overwritten unless FE_FLAG_NO_ZERO_GRADS). */
@@ -191,7 +194,8 @@ typedef struct fe_state_layout {
   size_t total;
   size_t xy;                     /* float2 [n]    pixel position (u, v)         */
   size_t conic_opacity;          /* float4 [n]    conic (A, B, C), opacity      */
-  size_t rgb;                    /* float4 [n]    colour (r, g, b, 0)           */
+  size_t rgb;                    /* float4 [n]    colour and view-space depth
+                                                  (r, g, b, tz)                 */
   size_t box;                    /* int16x4 [n]   pixel box (i0, j0, i1, j1)    */
   size_t depth_key;              /* uint32 [n]    float32 depth bits of each
                                                   Gaussian (culled: 0xFFFFFFFF) */
@@ -227,16 +231,17 @@ size_t    fe_backward_scratch_bytes(const fe_config* cfg, const fe_camera* cam, 
 fe_status fe_render_forward(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
                             const fe_images* out, void* state, size_t state_bytes, void* stream);
 
-/* Backward of fe_render_forward for upstream gradients d_rgb [3][H][W] and
- * d_feat [D][H][W] (device float32; none flows into final_T / n_contrib).
+/* Backward of fe_render_forward for upstream gradients d_rgb [3][H][W],
+ * d_feat [D][H][W] and d_depth [H][W] (device float32; d_depth may be NULL for
+ * no depth gradient; none flows into final_T / n_contrib).
  * `fwd` must be the images that forward wrote (final_T and n_contrib are
  * read).  `scratch` (device, 256-byte aligned, >= fe_backward_scratch_bytes)
  * holds per-Gaussian screen-space gradients; a misaligned scratch returns
  * FE_ERR_INVALID_ARG. */
 fe_status fe_render_backward(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
                              const fe_images* fwd, const void* state, size_t state_bytes,
-                             const float* d_rgb, const float* d_feat, const fe_grads* out,
-                             void* scratch, size_t scratch_bytes, void* stream);
+                             const float* d_rgb, const float* d_feat, const float* d_depth,
+                             const fe_grads* out, void* scratch, size_t scratch_bytes, void* stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc):
@@ -254,8 +259,8 @@ fe_status fe_render_backward(const fe_config* cfg, const fe_camera* cam, const f
 #define FE_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
 fe_status fe_render_backward_noalloc(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
                                      const fe_images* fwd, const void* state, size_t state_bytes,
-                                     const float* d_rgb, const float* d_feat, const fe_grads* out,
-                                     void* stream);
+                                     const float* d_rgb, const float* d_feat, const float* d_depth,
+                                     const fe_grads* out, void* stream);
 
 /* Copy the device report of `state` to the host.  Synchronises `stream`.
  * Returns report->status as the call's status (FE_ERR_KEY_OVERFLOW when the
@@ -293,7 +298,8 @@ size_t fe_batch_workspace_bytes(const fe_config* cfg, const fe_camera* cams, int
                                 const int64_t* n);
 
 /* Create a plan.  Arrays of length `frames`: cams, g, out, d_rgb, d_feat,
- * grads (d_rgb / d_feat / grads may be NULL for FE_MODE_FORWARD; the gradient
+ * d_depth, grads (d_rgb / d_feat / grads may be NULL for FE_MODE_FORWARD;
+ * d_depth, or any of its entries, may be NULL for no depth gradient; the gradient
  * pointers of a frame with n == 0 may be NULL).  Returns FE_ERR_HIP when the
  * device cannot be queried for the persistent launch size.  The plan
  * owns host memory and HIP graph handles only; `workspace` (256-byte
@@ -302,7 +308,7 @@ size_t fe_batch_workspace_bytes(const fe_config* cfg, const fe_camera* cams, int
 fe_status fe_batch_plan_create(const fe_config* cfg, const fe_camera* cams, int32_t frames,
                                const fe_gaussians* g, const fe_images* out,
                                const float* const* d_rgb, const float* const* d_feat,
-                               const fe_grads* grads, int32_t mode, void* workspace,
+                               const float* const* d_depth, const fe_grads* grads, int32_t mode, void* workspace,
                                size_t workspace_bytes, fe_batch_plan** plan);
 
 /* Enqueue one replay of every frame on `stream` (capturing on first use). */

@@ -16,11 +16,12 @@ from . import rast
 
 class BatchRenderer:
     """frames: list of dicts with device tensors means, scales, quats,
-    opacity, sh, feat (one frame each); cams: list of cameras; d_rgb / d_feat:
-    lists of upstream gradients (needed for the backward modes)."""
+    opacity, sh, feat (one frame each); cams: list of cameras; d_rgb / d_feat
+    (/ d_depth, optional): lists of upstream gradients (needed for the
+    backward modes)."""
 
     def __init__(self, frames, cams, st: rast.Settings, mode=rast.FE_MODE_FORWARD_BACKWARD, d_rgb=None,
-                 d_feat=None, capacity_margin=1.25):
+                 d_feat=None, capacity_margin=1.25, d_depth=None):
         lib = rast.load_library()
         self.lib = lib
         self.frames = frames
@@ -47,9 +48,11 @@ class BatchRenderer:
             H, W = int(cam.height), int(cam.width)
             self.out.append(dict(rgb=torch.empty(3, H, W, device=dev), feat=torch.empty(st.feat_dim, H, W, device=dev),
                                  final_T=torch.empty(H, W, device=dev),
-                                 n_contrib=torch.empty(H, W, dtype=torch.int32, device=dev)))
+                                 n_contrib=torch.empty(H, W, dtype=torch.int32, device=dev),
+                                 depth=torch.empty(H, W, device=dev)))
         self.out_c = (rast.fe_images * F)(*[rast.fe_images(o["rgb"].data_ptr(), o["feat"].data_ptr(),
-                                                            o["final_T"].data_ptr(), o["n_contrib"].data_ptr())
+                                                            o["final_T"].data_ptr(), o["n_contrib"].data_ptr(),
+                                                            o["depth"].data_ptr())
                                              for o in self.out])
         bwd = (mode & rast.FE_MODE_BACKWARD) != 0
         self.grads = []
@@ -64,10 +67,12 @@ class BatchRenderer:
                                                                  ("means", "scales", "quats", "opacity", "sh", "feat")],
                                                                None) for g in self.grads])
             self.d_rgb, self.d_feat = list(d_rgb), list(d_feat)
+            self.d_depth = list(d_depth) if d_depth is not None else [None] * F
             self.drgb_c = (C.c_void_p * F)(*[t.data_ptr() for t in self.d_rgb])
             self.dfeat_c = (C.c_void_p * F)(*[t.data_ptr() for t in self.d_feat])
+            self.ddepth_c = (C.c_void_p * F)(*[None if t is None else t.data_ptr() for t in self.d_depth])
         else:
-            self.grads_c, self.drgb_c, self.dfeat_c = None, None, None
+            self.grads_c, self.drgb_c, self.dfeat_c, self.ddepth_c = None, None, None, None
         ns = (C.c_int64 * F)(*[f["means"].shape[0] for f in frames])
         wb = lib.fe_batch_workspace_bytes(C.byref(self.cfg), self.cams_c, F, ns)
         if wb == 0:
@@ -75,7 +80,7 @@ class BatchRenderer:
         self.workspace = torch.empty(wb, dtype=torch.uint8, device=dev)
         plan = C.c_void_p()
         rast._check(lib.fe_batch_plan_create(C.byref(self.cfg), self.cams_c, F, self.g_c, self.out_c,
-                                             self.drgb_c, self.dfeat_c, self.grads_c, mode,
+                                             self.drgb_c, self.dfeat_c, self.ddepth_c, self.grads_c, mode,
                                              C.c_void_p(self.workspace.data_ptr()), wb, C.byref(plan)),
                     "fe_batch_plan_create")
         self.plan = plan

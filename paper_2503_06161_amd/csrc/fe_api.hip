@@ -228,7 +228,8 @@ static fe_status backward_post(const fe_config* cfg, const fe_camera* cam, const
 
 static fe_status backward_impl(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
                                const fe_images* fwd, const void* state, const Layout& L, const float* d_rgb,
-                               const float* d_feat, const fe_grads* out, void* scratch, hipStream_t s) {
+                               const float* d_feat, const float* d_depth, const fe_grads* out, void* scratch,
+                               hipStream_t s) {
   StateView v = make_view(L, const_cast<void*>(state));
   const BwdBuffers b = bwd_buffers(cfg, cam, g->n, scratch);
   hipError_t e;
@@ -236,8 +237,8 @@ static fe_status backward_impl(const fe_config* cfg, const fe_camera* cam, const
     fe_status st = backward_pre(L, state, b, s);
     if (st != FE_OK) return st;
     stage_mark(cfg, FE_STAGE_COMPOSITE_BWD, 0, s);
-    if ((e = launch_composite_bwd_mfma(cfg, cam, g, v, fwd, d_rgb, d_feat, b.row_base, b.rows, b.row_cap, b.rowidx,
-                                       s)) != hipSuccess)
+    if ((e = launch_composite_bwd_mfma(cfg, cam, g, v, fwd, d_rgb, d_feat, d_depth, b.row_base, b.rows, b.row_cap,
+                                       b.rowidx, s)) != hipSuccess)
       return FE_ERR_HIP;
     stage_mark(cfg, FE_STAGE_COMPOSITE_BWD, 1, s);
     return backward_post(cfg, cam, g, L, state, b, out, s);
@@ -249,7 +250,7 @@ static fe_status backward_impl(const fe_config* cfg, const fe_camera* cam, const
       return FE_ERR_HIP;
   }
   stage_mark(cfg, FE_STAGE_COMPOSITE_BWD, 0, s);
-  if ((e = launch_composite_bwd(cfg, cam, g, v, fwd, d_rgb, d_feat, b.grad2d, out->feat, s)) != hipSuccess)
+  if ((e = launch_composite_bwd(cfg, cam, g, v, fwd, d_rgb, d_feat, d_depth, b.grad2d, out->feat, s)) != hipSuccess)
     return FE_ERR_HIP;
   stage_mark(cfg, FE_STAGE_COMPOSITE_BWD, 1, s);
   stage_mark(cfg, FE_STAGE_PROJECT_BWD, 0, s);
@@ -359,7 +360,7 @@ fe_status fe_render_forward(const fe_config* cfg, const fe_camera* cam, const fe
 
 fe_status fe_render_backward(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
                              const fe_images* fwd, const void* state, size_t state_bytes,
-                             const float* d_rgb, const float* d_feat, const fe_grads* out,
+                             const float* d_rgb, const float* d_feat, const float* d_depth, const fe_grads* out,
                              void* scratch, size_t scratch_bytes, void* stream) {
   fe_status st = fe_validate(cfg, cam, g ? g->n : -1);
   if (st != FE_OK) return st;
@@ -374,7 +375,8 @@ fe_status fe_render_backward(const fe_config* cfg, const fe_camera* cam, const f
   if (state_bytes < L.total) return FE_ERR_WORKSPACE_TOO_SMALL;
   if (scratch_bytes < fe_backward_scratch_bytes(cfg, cam, g->n)) return FE_ERR_WORKSPACE_TOO_SMALL;
   if (g->n == 0) return FE_OK;
-  return backward_impl(cfg, cam, g, fwd, state, L, d_rgb, d_feat, out, scratch, static_cast<hipStream_t>(stream));
+  return backward_impl(cfg, cam, g, fwd, state, L, d_rgb, d_feat, d_depth, out, scratch,
+                       static_cast<hipStream_t>(stream));
 }
 
 fe_status fe_read_report(const void* state, size_t state_bytes, fe_report* out, void* stream) {
@@ -413,7 +415,7 @@ struct fe_batch_plan {
   std::vector<fe_camera> cams;
   std::vector<fe_gaussians> g;
   std::vector<fe_images> out;
-  std::vector<const float*> d_rgb, d_feat;
+  std::vector<const float*> d_rgb, d_feat, d_depth;
   std::vector<fe_grads> grads;
   std::vector<Layout> layouts;
   std::vector<size_t> state_off, scratch_off;
@@ -484,7 +486,7 @@ size_t fe_batch_workspace_bytes(const fe_config* cfg, const fe_camera* cams, int
 fe_status fe_batch_plan_create(const fe_config* cfg, const fe_camera* cams, int32_t frames,
                                const fe_gaussians* g, const fe_images* out,
                                const float* const* d_rgb, const float* const* d_feat,
-                               const fe_grads* grads, int32_t mode, void* workspace,
+                               const float* const* d_depth, const fe_grads* grads, int32_t mode, void* workspace,
                                size_t workspace_bytes, fe_batch_plan** plan) {
   if (!plan) return FE_ERR_INVALID_ARG;
   *plan = nullptr;
@@ -527,6 +529,10 @@ fe_status fe_batch_plan_create(const fe_config* cfg, const fe_camera* cams, int3
   if (bwd) {
     p->d_rgb.assign(d_rgb, d_rgb + frames);
     p->d_feat.assign(d_feat, d_feat + frames);
+    if (d_depth)
+      p->d_depth.assign(d_depth, d_depth + frames);
+    else
+      p->d_depth.assign(frames, nullptr);
     p->grads.assign(grads, grads + frames);
   }
   p->persistent = batch_persistent(cfg, cams, frames);
@@ -598,7 +604,7 @@ static fe_status frame_enqueue(fe_batch_plan* p, int f, hipStream_t s) {
     st = forward_impl(&p->cfg, &p->cams[f], &p->g[f], &p->out[f], p->ws + p->state_off[f], p->layouts[f], s);
   if (st == FE_OK && (p->mode & FE_MODE_BACKWARD) && p->g[f].n > 0)
     st = backward_impl(&p->cfg, &p->cams[f], &p->g[f], &p->out[f], p->ws + p->state_off[f], p->layouts[f],
-                       p->d_rgb[f], p->d_feat[f], &p->grads[f], p->ws + p->scratch_off[f], s);
+                       p->d_rgb[f], p->d_feat[f], p->d_depth[f], &p->grads[f], p->ws + p->scratch_off[f], s);
   return st;
 }
 
@@ -616,8 +622,8 @@ static fe_status upload_multi(fe_batch_plan* p) {
     composite_fwd_record(&p->cfg, &p->cams[f], &p->g[f], v, &p->out[f], recf.data() + f * rf);
     if (bwd) {
       const BwdBuffers b = bwd_buffers(&p->cfg, &p->cams[f], p->g[f].n, p->ws + p->scratch_off[f]);
-      composite_bwd_record(&p->cfg, &p->cams[f], &p->g[f], v, &p->out[f], p->d_rgb[f], p->d_feat[f], b.row_base,
-                           b.rows, b.row_cap, b.rowidx, recb.data() + f * rb);
+      composite_bwd_record(&p->cfg, &p->cams[f], &p->g[f], v, &p->out[f], p->d_rgb[f], p->d_feat[f], p->d_depth[f],
+                           b.row_base, b.rows, b.row_cap, b.rowidx, recb.data() + f * rb);
     }
     rng[f] = v.ranges;
     walk[f] = v.tile_maxlast;

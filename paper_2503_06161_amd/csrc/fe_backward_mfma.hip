@@ -16,7 +16,7 @@
 // Partial results are not added into the outputs with device-wide atomics
 // (the eight XCDs keep no common cache, so those run at memory speed).  Each
 // (tile, list position) walked writes one row [dL/df (D), dL/d(u, v, A, B, C,
-// opacity, r, g, b)] into a compact buffer; rows of a tile start at an
+// opacity, r, g, b, depth)] into a compact buffer; rows of a tile start at an
 // exclusive scan of the tiles' walk lengths.  A second kernel sums, per
 // Gaussian, the rows of the tiles it was walked in, found through the
 // emit-position -> sorted-position map written by the tile sort.
@@ -48,6 +48,7 @@ struct BwdArgs {
   const int32_t* n_contrib;
   const float* d_rgb;
   const float* d_feat;
+  const float* d_depth;      // [H][W] or null (no depth gradient)
   const uint32_t* tile_maxlast;
   const uint32_t* row_base;
   float* rows;
@@ -109,7 +110,7 @@ __device__ __forceinline__ void bwd_mfma_tile(const BwdArgs& a, const int tile) 
   __bf16 (*s_w)[2][kNB][WROW] = reinterpret_cast<__bf16 (*)[2][kNB][WROW]>(s_raw);
   float (*s_df)[kNB][DFROW] = reinterpret_cast<float (*)[kNB][DFROW]>(s_raw + kWBytes);   // [KSPL]
   __shared__ int s_live[NW];
-  __shared__ float s_gr[3][NT];                              // upstream colour gradient of the tile
+  __shared__ float s_gr[4][NT];                              // upstream colour and depth gradient of the tile
   // MFMA B operands of the colour sums, per wave and 32-pixel k step: lane l
   // holds colour l % 16 (zero from 3 on) at pixels 8 (l / 16) + 0..7, hi / lo
   __shared__ bf16x8 s_grb[NW][2][2][64];
@@ -196,7 +197,7 @@ __device__ __forceinline__ void bwd_mfma_tile(const BwdArgs& a, const int tile) 
   load_ids(walk);
 
   // ---- per-pixel state ----
-  float gr0 = 0.f, gr1 = 0.f, gr2 = 0.f;
+  float gr0 = 0.f, gr1 = 0.f, gr2 = 0.f, gr3 = 0.f;   // upstream colour and depth gradient
   float T = 1.0f;
   int last = 0;
   if (inside) {
@@ -204,6 +205,7 @@ __device__ __forceinline__ void bwd_mfma_tile(const BwdArgs& a, const int tile) 
     gr0 = a.d_rgb[p];
     gr1 = a.d_rgb[HW + p];
     gr2 = a.d_rgb[2 * HW + p];
+    gr3 = a.d_depth ? a.d_depth[p] : 0.f;
     T = a.final_T[p];
     last = a.n_contrib[p];
   }
@@ -215,6 +217,7 @@ __device__ __forceinline__ void bwd_mfma_tile(const BwdArgs& a, const int tile) 
   s_gr[0][threadIdx.x] = gr0;
   s_gr[1][threadIdx.x] = gr1;
   s_gr[2][threadIdx.x] = gr2;
+  s_gr[3][threadIdx.x] = gr3;
   load_data();
   load_ids(walk - kNB);
 #pragma unroll
@@ -261,7 +264,7 @@ __device__ __forceinline__ void bwd_mfma_tile(const BwdArgs& a, const int tile) 
       bf16x8 h, l;
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        const float x = n < 3 ? s_gr[n < 3 ? n : 0][64 * wave + 32 * ks + 8 * (lane >> 4) + j] : 0.f;
+        const float x = n < 4 ? s_gr[n < 4 ? n : 0][64 * wave + 32 * ks + 8 * (lane >> 4) + j] : 0.f;
         __bf16 xh, xl;
         split2(x, xh, xl);
         h[j] = xh;
@@ -375,7 +378,7 @@ __device__ __forceinline__ void bwd_mfma_tile(const BwdArgs& a, const int tile) 
         for (int u = GR - 1; u >= 0; --u) {
           const int i = gi * GR + u;
           const float4 c = s_rgb[i];
-          const float sv = S[i] + ((gr0 * c.x + gr1 * c.y) + gr2 * c.z);
+          const float sv = S[i] + (((gr0 * c.x + gr1 * c.y) + gr2 * c.z) + gr3 * c.w);
           const float inv_om = __builtin_amdgcn_rcpf(1.0f - al[u]);
           const float Tn = T * inv_om;
           const float w = al[u] * Tn;
@@ -464,7 +467,7 @@ __device__ __forceinline__ void bwd_mfma_tile(const BwdArgs& a, const int tile) 
           cs = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, gl, cs, 0, 0, 0);
           cs = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl, gh, cs, 0, 0, 0);
         }
-        if ((lane & 15) < 3) {
+        if ((lane & 15) < 4) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) atomicAdd(&s_red[6 + (lane & 15)][16 * mb + 4 * (lane >> 4) + v], cs[v]);
         }
@@ -510,7 +513,7 @@ __device__ __forceinline__ void bwd_mfma_tile(const BwdArgs& a, const int tile) 
       }
     }
     if constexpr (KSPL > 1) __syncthreads();   // partial sums of all waves are in LDS
-    // ---- rest of the rows of this batch: [dL/df (D) | u v A B C o r g b | pad],
+    // ---- rest of the rows of this batch: [dL/df (D) | u v A B C o r g b depth | pad],
     //      one float4 per thread and step.  The walk left the pixel sums S, Sx,
     //      Sy, Sxx, Sxy, Syy of X, X dx, X dy, X dx^2, X dx dy, X dy^2; with the
     //      Gaussian's conic (a, b, c) and opacity o the projected-space
@@ -544,6 +547,7 @@ __device__ __forceinline__ void bwd_mfma_tile(const BwdArgs& a, const int tile) 
               case 6: x = s_red[6][i]; break;
               case 7: x = s_red[7][i]; break;
               case 8: x = s_red[8][i]; break;
+              case 9: x = s_red[9][i]; break;
               default: break;
             }
           }
@@ -601,13 +605,13 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
   // per walker wave: pixel moments (about the tile centre) and colour sums of
   // each Gaussian of a batch, and the X values of a 16-Gaussian half
   __shared__ float s_mom[2][NW][6][kNB];
-  __shared__ float s_col[2][NW][3][kNB];
+  __shared__ float s_col[2][NW][4][kNB];
   __shared__ float s_xm[NW][16][64];
   __shared__ int s_live[2][NW];
   __shared__ __attribute__((aligned(16))) unsigned char s_raw[kShared];
   float (*s_g)[GROW] = reinterpret_cast<float (*)[GROW]>(s_raw);
   __bf16 (*s_w)[NW][2][kNB][WROW] = reinterpret_cast<__bf16 (*)[NW][2][kNB][WROW]>(s_raw);   // [2]
-  __shared__ float s_gr[3][NT];
+  __shared__ float s_gr[4][NT];
   __shared__ bf16x8 s_grb[NW][2][2][64];
 
   const bool walker = (int)threadIdx.x < NT;
@@ -728,7 +732,7 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
   }
 
   // ---- walkers: per-pixel state ----
-  float gr0 = 0.f, gr1 = 0.f, gr2 = 0.f;
+  float gr0 = 0.f, gr1 = 0.f, gr2 = 0.f, gr3 = 0.f;   // upstream colour and depth gradient
   float T = 1.0f;
   int last = 0;
   if (walker && inside) {
@@ -736,6 +740,7 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
     gr0 = a.d_rgb[p];
     gr1 = a.d_rgb[HW + p];
     gr2 = a.d_rgb[2 * HW + p];
+    gr3 = a.d_depth ? a.d_depth[p] : 0.f;
     T = a.final_T[p];
     last = a.n_contrib[p];
   }
@@ -743,6 +748,7 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
     s_gr[0][q] = gr0;
     s_gr[1][q] = gr1;
     s_gr[2][q] = gr2;
+    s_gr[3][q] = gr3;
   }
 
   // ---- upstream feature gradient into the two operand layouts, one 32-channel
@@ -801,7 +807,7 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
       bf16x8 h, l;
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        const float x = n < 3 ? s_gr[n < 3 ? n : 0][64 * wave + 32 * ks + 8 * (lane >> 4) + j] : 0.f;
+        const float x = n < 4 ? s_gr[n < 4 ? n : 0][64 * wave + 32 * ks + 8 * (lane >> 4) + j] : 0.f;
         __bf16 xh, xl;
         split2(x, xh, xl);
         h[j] = xh;
@@ -887,7 +893,7 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
               for (int u = GR - 1; u >= 0; --u) {
                 const int i = gi * GR + u;
                 const float4 c = s_rgb[b2][i];
-                const float sv = S[i] + ((gr0 * c.x + gr1 * c.y) + gr2 * c.z);
+                const float sv = S[i] + (((gr0 * c.x + gr1 * c.y) + gr2 * c.z) + gr3 * c.w);
                 const float Tn = T * inv[u];
                 const float w = al[u] * Tn;
                 const float da = Tn * sv - acc * inv[u];
@@ -992,7 +998,7 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
               cs = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, gl, cs, 0, 0, 0);
               cs = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl, gh, cs, 0, 0, 0);
             }
-            if ((lane & 15) < 3) {
+            if ((lane & 15) < 4) {
 #pragma unroll
               for (int v = 0; v < 4; ++v) s_col[b2][wave][lane & 15][16 * mb + 4 * (lane >> 4) + v] = cs[v];
             }
@@ -1043,14 +1049,14 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
         // its conic and opacity; the row is closed with zeros up to its stride
         if (q < nb) {
           const int i = q;
-          float P[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, Cc[3] = {0.f, 0.f, 0.f};
+          float P[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, Cc[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
           for (int w = 0; w < NW; ++w) {
             if (!s_live[b2][w]) continue;
 #pragma unroll
             for (int k2 = 0; k2 < 6; ++k2) P[k2] += s_mom[b2][w][k2][i];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) Cc[c] += s_col[b2][w][c][i];
+            for (int c = 0; c < 4; ++c) Cc[c] += s_col[b2][w][c][i];
           }
           const float2 m = s_xy[b3][i];
           const float4 co = s_co[b3][i];
@@ -1062,7 +1068,7 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
           const float S2 = __builtin_fmaf(-ux, __builtin_fmaf(-ux, P[0], 2.0f * P[1]), P[3]);   // X dx^2
           const float S3 = __builtin_fmaf(-ux, __builtin_fmaf(-uy, P[0], P[2]), __builtin_fmaf(-uy, P[1], P[4]));
           const float S4 = __builtin_fmaf(-uy, __builtin_fmaf(-uy, P[0], 2.0f * P[2]), P[5]);   // X dy^2
-          float v9[9];
+          float v9[10];
           v9[0] = co.w * (co.x * S0 + co.y * S1);
           v9[1] = co.w * (co.y * S0 + co.z * S1);
           v9[2] = -0.5f * co.w * S2;
@@ -1072,10 +1078,11 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
           v9[6] = Cc[0];
           v9[7] = Cc[1];
           v9[8] = Cc[2];
+          v9[9] = Cc[3];
           auto pick = [&](int t) {
             float x = 0.f;
 #pragma unroll
-            for (int k2 = 0; k2 < 9; ++k2) x = t == k2 ? v9[k2] : x;
+            for (int k2 = 0; k2 < 10; ++k2) x = t == k2 ? v9[k2] : x;
             return x;
           };
           float* row = &a.rows[(row0 + pos0 + i) * a.RS];
@@ -1195,9 +1202,9 @@ __device__ __forceinline__ void reduce_one(const ReduceArgs& a, int64_t g, uint3
           const int grp = sub + q * LPG;
           v[t][q] = (r[t] && grp < D4) ? *reinterpret_cast<const float4*>(src + 4 * grp) : make_float4(0.f, 0.f, 0.f, 0.f);
         }
-        // channels past the last whole group, and the 9 projected-space sums
+        // channels past the last whole group, and the 10 projected-space sums
         const int c = 4 * D4 + sub;
-        t9[t] = (r[t] && c < a.D + 9) ? src[c] : 0.f;
+        t9[t] = (r[t] && c < a.D + 10) ? src[c] : 0.f;
       }
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
@@ -1233,13 +1240,13 @@ __device__ __forceinline__ void reduce_one(const ReduceArgs& a, int64_t g, uint3
       }
     }
   }
-  // lane sub holds column 4 D4 + sub: a leftover channel or one of the 9 sums
+  // lane sub holds column 4 D4 + sub: a leftover channel or one of the 10 sums
   const int c = 4 * D4 + sub;
   if (c < a.D) fo[c] = a.accumulate ? fo[c] + acc9 : acc9;
-  // the 9 sums sit in lanes (D - 4 D4) .. (D - 4 D4 + 8)
+  // the 10 sums sit in lanes (D - 4 D4) .. (D - 4 D4 + 9)
   const int k9 = c - a.D;
-  if (k9 >= 0 && k9 < 9) a.grad2d[g * 12 + k9] = acc9;
-  if (sub < 3) a.grad2d[g * 12 + 9 + sub] = 0.f;
+  if (k9 >= 0 && k9 < 10) a.grad2d[g * 12 + k9] = acc9;
+  if (sub < 2) a.grad2d[g * 12 + 10 + sub] = 0.f;
 }
 
 // Each group of LPG lanes sums the rows of NG consecutive Gaussians; their
@@ -1310,10 +1317,10 @@ bool backward_wave_specialized(const fe_config* cfg) {
 // the closing block of the row (the nine projected-space sums and zeros) is
 // then one full, aligned line written by one store instruction, instead of
 // partial lines written at different times by different waves.
-int backward_row_stride(int D) { return (D + 9 + 31) & ~31; }
+int backward_row_stride(int D) { return (D + 10 + 31) & ~31; }
 
 static BwdArgs make_bwd_args(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g, const StateView& v,
-                              const fe_images* fwd, const float* d_rgb, const float* d_feat,
+                              const fe_images* fwd, const float* d_rgb, const float* d_feat, const float* d_depth,
                               const uint32_t* row_base, float* rows, int64_t row_cap, uint32_t* rowidx) {
   BwdArgs a{};
   a.ranges = v.ranges;
@@ -1327,6 +1334,7 @@ static BwdArgs make_bwd_args(const fe_config* cfg, const fe_camera* cam, const f
   a.n_contrib = fwd->n_contrib;
   a.d_rgb = d_rgb;
   a.d_feat = d_feat;
+  a.d_depth = d_depth;
   a.tile_maxlast = v.tile_maxlast;
   a.row_base = row_base;
   a.rows = rows;
@@ -1348,10 +1356,10 @@ static BwdArgs make_bwd_args(const fe_config* cfg, const fe_camera* cam, const f
 
 hipError_t launch_composite_bwd_mfma(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
                                      const StateView& v, const fe_images* fwd, const float* d_rgb,
-                                     const float* d_feat, const uint32_t* row_base, float* rows,
+                                     const float* d_feat, const float* d_depth, const uint32_t* row_base, float* rows,
                                      int64_t row_cap, uint32_t* rowidx, hipStream_t s) {
   if (v.tiles == 0) return hipSuccess;
-  const BwdArgs a = make_bwd_args(cfg, cam, g, v, fwd, d_rgb, d_feat, row_base, rows, row_cap, rowidx);
+  const BwdArgs a = make_bwd_args(cfg, cam, g, v, fwd, d_rgb, d_feat, d_depth, row_base, rows, row_cap, rowidx);
   const int nt = cfg->tile_w * cfg->tile_h;
   const bool ws = backward_wave_specialized(cfg);
   return cfg->feat_dtype == FE_BF16 ? dispatch_bwd<uint16_t>(cfg->feat_dim, nt, a, v.tiles, ws, s)
@@ -1362,9 +1370,9 @@ hipError_t launch_composite_bwd_mfma(const fe_config* cfg, const fe_camera* cam,
 size_t composite_bwd_record_bytes() { return sizeof(BwdArgs); }
 
 void composite_bwd_record(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g, const StateView& v,
-                          const fe_images* fwd, const float* d_rgb, const float* d_feat, const uint32_t* row_base,
-                          float* rows, int64_t row_cap, uint32_t* rowidx, void* dst) {
-  const BwdArgs a = make_bwd_args(cfg, cam, g, v, fwd, d_rgb, d_feat, row_base, rows, row_cap, rowidx);
+                          const fe_images* fwd, const float* d_rgb, const float* d_feat, const float* d_depth,
+                          const uint32_t* row_base, float* rows, int64_t row_cap, uint32_t* rowidx, void* dst) {
+  const BwdArgs a = make_bwd_args(cfg, cam, g, v, fwd, d_rgb, d_feat, d_depth, row_base, rows, row_cap, rowidx);
   std::memcpy(dst, &a, sizeof(a));
 }
 
@@ -1449,7 +1457,7 @@ hipError_t launch_reduce_rows(const fe_config* cfg, const StateView& v, const ui
   a.vec_out = cfg->feat_dim % 4 == 0 && reinterpret_cast<uintptr_t>(grad_feat) % 16 == 0;
   const int D = cfg->feat_dim;
   // lanes per Gaussian: enough 4-channel groups per lane for the row, and at
-  // least 16 lanes so that the leftover channels and the 9 sums have a lane
+  // least 16 lanes so that the leftover channels and the 10 sums have a lane
   constexpr int NG = 4;   // Gaussians per lane group
   if (D <= 64) {
     const unsigned blocks = (unsigned)((v.n + 16 * NG - 1) / (16 * NG));

@@ -136,11 +136,12 @@ hipError_t launch_composite_fwd_mfma(const fe_config* cfg, const fe_camera* cam,
                                      const StateView& v, const fe_images* out, hipStream_t s);
 hipError_t launch_composite_bwd(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
                                 const StateView& v, const fe_images* fwd, const float* d_rgb,
-                                const float* d_feat, float* grad2d, float* grad_feat, hipStream_t s);
+                                const float* d_feat, const float* d_depth, float* grad2d, float* grad_feat,
+                                hipStream_t s);
 int backward_row_stride(int D);
 hipError_t launch_composite_bwd_mfma(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
                                      const StateView& v, const fe_images* fwd, const float* d_rgb,
-                                     const float* d_feat, const uint32_t* row_base, float* rows,
+                                     const float* d_feat, const float* d_depth, const uint32_t* row_base, float* rows,
                                      int64_t row_cap, uint32_t* rowidx, hipStream_t s);
 hipError_t launch_reduce_rows(const fe_config* cfg, const StateView& v, const uint32_t* rowidx,
                               const float* rows, float* grad2d, float* grad_feat, hipStream_t s);
@@ -185,8 +186,8 @@ hipError_t launch_composite_fwd_persistent(const fe_config* cfg, const void* rec
                                            int grid, hipStream_t s);
 size_t composite_bwd_record_bytes();
 void composite_bwd_record(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g, const StateView& v,
-                          const fe_images* fwd, const float* d_rgb, const float* d_feat, const uint32_t* row_base,
-                          float* rows, int64_t row_cap, uint32_t* rowidx, void* dst);
+                          const fe_images* fwd, const float* d_rgb, const float* d_feat, const float* d_depth,
+                          const uint32_t* row_base, float* rows, int64_t row_cap, uint32_t* rowidx, void* dst);
 int composite_bwd_persistent_grid(const fe_config* cfg);
 hipError_t launch_composite_bwd_persistent(const fe_config* cfg, const void* records, const TileQueue& q,
                                            int grid, hipStream_t s);

@@ -31,9 +31,11 @@ struct CompArgs {
   float* out_feat;           // [D][H][W]
   float* out_T;              // [H][W]
   int32_t* out_n;            // [H][W]
+  float* out_depth;          // [H][W] or null
   // backward
   const float* d_rgb;
   const float* d_feat;
+  const float* d_depth;      // [H][W] or null
   float* grad2d;             // [n][12]
   float* grad_feat;          // [n][D]
   uint32_t* tile_maxlast;    // [tiles]
@@ -113,7 +115,7 @@ __global__ __launch_bounds__(NT) void composite_fwd_kernel(CompArgs a) {
   const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
   const uint2 rg = a.ranges[tile];
   float T = 1.0f;
-  float C0 = 0.f, C1 = 0.f, C2 = 0.f;
+  float C0 = 0.f, C1 = 0.f, C2 = 0.f, C3 = 0.f;   // colour, depth
   float Z[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) Z[k] = 0.f;
@@ -138,6 +140,7 @@ __global__ __launch_bounds__(NT) void composite_fwd_kernel(CompArgs a) {
         C0 = __builtin_fmaf(w, c.x, C0);
         C1 = __builtin_fmaf(w, c.y, C1);
         C2 = __builtin_fmaf(w, c.z, C2);
+        C3 = __builtin_fmaf(w, c.w, C3);
         const float4* f4 = reinterpret_cast<const float4*>(s_f + j * D);
 #pragma unroll
         for (int k4 = 0; k4 < D / 4; ++k4) {
@@ -158,6 +161,7 @@ __global__ __launch_bounds__(NT) void composite_fwd_kernel(CompArgs a) {
     a.out_rgb[p] = __builtin_fmaf(T, a.bg[0], C0);
     a.out_rgb[HW + p] = __builtin_fmaf(T, a.bg[1], C1);
     a.out_rgb[2 * HW + p] = __builtin_fmaf(T, a.bg[2], C2);
+    if (a.out_depth) a.out_depth[p] = C3;
 #pragma unroll
     for (int k = 0; k < D; ++k)
       if (k < a.D) a.out_feat[k * HW + p] = Z[k];
@@ -201,7 +205,7 @@ __global__ __launch_bounds__(NT) void composite_bwd_kernel(CompArgs a) {
   const uint2 rg = a.ranges[tile];
   const int64_t HW = (int64_t)a.W * a.H;
   const int64_t p = (int64_t)py * a.W + px;
-  float gr[3] = {0.f, 0.f, 0.f};
+  float gr[4] = {0.f, 0.f, 0.f, 0.f};   // colour, depth
   float gf[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) gf[k] = 0.f;
@@ -211,6 +215,7 @@ __global__ __launch_bounds__(NT) void composite_bwd_kernel(CompArgs a) {
     gr[0] = a.d_rgb[p];
     gr[1] = a.d_rgb[HW + p];
     gr[2] = a.d_rgb[2 * HW + p];
+    gr[3] = a.d_depth ? a.d_depth[p] : 0.f;
 #pragma unroll
     for (int k = 0; k < D; ++k)
       if (k < a.D) gf[k] = a.d_feat[k * HW + p];
@@ -237,14 +242,14 @@ __global__ __launch_bounds__(NT) void composite_bwd_kernel(CompArgs a) {
       bool contrib = false;
       if (inside && pos < last) contrib = pair_alpha(fpx, fpy, px, py, s_xy[j], s_co[j], s_tg[j], s_box[j], dx, dy, G, alpha);
       if (__ballot(contrib) == 0ull) continue;
-      float v[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      float v[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       float w = 0.f;
       if (contrib) {
         const float om = 1.0f - alpha;
         T = T / om;
         w = alpha * T;
         const float4 c = s_rgb[j];
-        float s = (gr[0] * c.x + gr[1] * c.y) + gr[2] * c.z;
+        float s = ((gr[0] * c.x + gr[1] * c.y) + gr[2] * c.z) + gr[3] * c.w;
         const float4* f4 = reinterpret_cast<const float4*>(s_f + j * D);
 #pragma unroll
         for (int k4 = 0; k4 < D / 4; ++k4) {
@@ -259,6 +264,7 @@ __global__ __launch_bounds__(NT) void composite_bwd_kernel(CompArgs a) {
         v[6] = w * gr[0];
         v[7] = w * gr[1];
         v[8] = w * gr[2];
+        v[9] = w * gr[3];
         const float4 co = s_co[j];
         const float opG = co.w * G;
         if (opG <= kAlphaMax) {
@@ -273,7 +279,7 @@ __global__ __launch_bounds__(NT) void composite_bwd_kernel(CompArgs a) {
       }
       const uint32_t g = s_gid[j];
 #pragma unroll
-      for (int k = 0; k < 9; ++k) {
+      for (int k = 0; k < 10; ++k) {
         const float r = wave_sum(v[k]);
         if (lane == 0 && r != 0.f) atomicAdd(a.grad2d + (int64_t)g * 12 + k, r);
       }
@@ -353,6 +359,7 @@ hipError_t launch_composite_fwd(const fe_config* cfg, const fe_camera* cam, cons
   a.out_feat = out->feat;
   a.out_T = out->final_T;
   a.out_n = out->n_contrib;
+  a.out_depth = out->depth;
   const int nt = cfg->tile_w * cfg->tile_h;
   return cfg->feat_dtype == FE_BF16 ? dispatch_d<uint16_t, false>(cfg->feat_dim, nt, a, v.tiles, s)
                                     : dispatch_d<float, false>(cfg->feat_dim, nt, a, v.tiles, s);
@@ -360,12 +367,14 @@ hipError_t launch_composite_fwd(const fe_config* cfg, const fe_camera* cam, cons
 
 hipError_t launch_composite_bwd(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
                                 const StateView& v, const fe_images* fwd, const float* d_rgb,
-                                const float* d_feat, float* grad2d, float* grad_feat, hipStream_t s) {
+                                const float* d_feat, const float* d_depth, float* grad2d, float* grad_feat,
+                                hipStream_t s) {
   CompArgs a = make_args(cfg, cam, g, v);
   a.out_T = fwd->final_T;
   a.out_n = fwd->n_contrib;
   a.d_rgb = d_rgb;
   a.d_feat = d_feat;
+  a.d_depth = d_depth;
   a.grad2d = grad2d;
   a.grad_feat = grad_feat;
   const int nt = cfg->tile_w * cfg->tile_h;

@@ -51,6 +51,7 @@ struct MfmaArgs {
   float* out_feat;
   float* out_T;
   int32_t* out_n;
+  float* out_depth;              // [H][W] or null
   uint32_t* tile_maxlast;        // [tiles] largest n_contrib of the tile
   unsigned long long* report;
   float bg[3];
@@ -146,7 +147,7 @@ void composite_fwd_mfma_kernel(MfmaArgs a) {
   const uint2 rg = a.ranges[tile];
 
   float T = 1.0f;
-  float C0 = 0.f, C1 = 0.f, C2 = 0.f;
+  float C0 = 0.f, C1 = 0.f, C2 = 0.f, C3 = 0.f;   // colour, depth
   int last = 0;
   bool done = !inside;
   f32x16 acc[2][CB];
@@ -270,6 +271,7 @@ void composite_fwd_mfma_kernel(MfmaArgs a) {
           C0 = __builtin_fmaf(w, c.x, C0);
           C1 = __builtin_fmaf(w, c.y, C1);
           C2 = __builtin_fmaf(w, c.z, C2);
+          C3 = __builtin_fmaf(w, c.w, C3);
           wv[gi * GR + u] = w;
           T = take ? Tn : T;
           last = take ? (int)(b0 - rg.x) + i + 1 : last;
@@ -322,6 +324,7 @@ void composite_fwd_mfma_kernel(MfmaArgs a) {
     a.out_rgb[p] = __builtin_fmaf(T, a.bg[0], C0);
     a.out_rgb[HW + p] = __builtin_fmaf(T, a.bg[1], C1);
     a.out_rgb[2 * HW + p] = __builtin_fmaf(T, a.bg[2], C2);
+    if (a.out_depth) a.out_depth[p] = C3;
     a.out_T[p] = T;
     a.out_n[p] = last;
   }
@@ -454,7 +457,7 @@ __device__ __forceinline__ void fwd_ws_tile(const MfmaArgs& a, const int tile) {
     // leaves T, the colour and the weights unchanged with no per-pair mask
     // logic, so the front-to-back chain is a few dependent VALU operations.
     float T = inside ? 1.0f : -1.0f;
-    float C0 = 0.f, C1 = 0.f, C2 = 0.f;
+    float C0 = 0.f, C1 = 0.f, C2 = 0.f, C3 = 0.f;   // colour, depth
     int last = 0;
     for (int kk = 0;; ++kk) {
       const int k = __builtin_amdgcn_readfirstlane(kk);   // scalar: keeps the barrier loop uniform
@@ -497,6 +500,7 @@ __device__ __forceinline__ void fwd_ws_tile(const MfmaArgs& a, const int tile) {
             C0 = __builtin_fmaf(w, c.x, C0);
             C1 = __builtin_fmaf(w, c.y, C1);
             C2 = __builtin_fmaf(w, c.z, C2);
+            C3 = __builtin_fmaf(w, c.w, C3);
             wv[u] = w;
             lrel = w != 0.f ? u + 1 : lrel;
           }
@@ -518,6 +522,7 @@ __device__ __forceinline__ void fwd_ws_tile(const MfmaArgs& a, const int tile) {
       a.out_rgb[p] = __builtin_fmaf(T, a.bg[0], C0);
       a.out_rgb[HW + p] = __builtin_fmaf(T, a.bg[1], C1);
       a.out_rgb[2 * HW + p] = __builtin_fmaf(T, a.bg[2], C2);
+      if (a.out_depth) a.out_depth[p] = C3;
       a.out_T[p] = T;
       a.out_n[p] = last;
     }
@@ -684,6 +689,7 @@ static MfmaArgs make_args(const fe_config* cfg, const fe_camera* cam, const fe_g
   a.out_feat = out->feat;
   a.out_T = out->final_T;
   a.out_n = out->n_contrib;
+  a.out_depth = out->depth;
   a.tile_maxlast = v.tile_maxlast;
   a.report = v.report;
   for (int k = 0; k < 3; ++k) a.bg[k] = cfg->bg_rgb[k];

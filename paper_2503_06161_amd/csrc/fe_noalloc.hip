@@ -40,14 +40,14 @@ fe_status scratch_address(void** out) {
 
 extern "C" fe_status fe_render_backward_noalloc(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g,
                                                 const fe_images* fwd, const void* state, size_t state_bytes,
-                                                const float* d_rgb, const float* d_feat, const fe_grads* out,
-                                                void* stream) {
+                                                const float* d_rgb, const float* d_feat, const float* d_depth,
+                                                const fe_grads* out, void* stream) {
   const fe_status v = fe_validate(cfg, cam, g ? g->n : -1);
   if (v != FE_OK) return v;
   if (fe_backward_scratch_bytes(cfg, cam, g->n) > kStaticScratchBytes) return FE_ERR_WORKSPACE_TOO_SMALL;
   void* mem = nullptr;
   const fe_status st = scratch_address(&mem);
   if (st != FE_OK) return st;
-  return fe_render_backward(cfg, cam, g, fwd, state, state_bytes, d_rgb, d_feat, out, mem, kStaticScratchBytes,
-                            stream);
+  return fe_render_backward(cfg, cam, g, fwd, state, state_bytes, d_rgb, d_feat, d_depth, out, mem,
+                            kStaticScratchBytes, stream);
 }

@@ -301,7 +301,8 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(ProjArgs a) {
           for (int k = 0; k < K; ++k)
             for (int ch = 0; ch < 3; ++ch) acc[ch] += (double)shr[k * 3 + ch] * Y[k];
           for (int ch = 0; ch < 3; ++ch) col[ch] = fmax(acc[ch] + 0.5, 0.0);
-          rgb = make_float4((float)col[0], (float)col[1], (float)col[2], 0.f);
+          // colour and the view-space depth (the depth image's value)
+          rgb = make_float4((float)col[0], (float)col[1], (float)col[2], (float)G.tz);
           if (i0 <= i1 && j0 <= j1 && isfinite(G.u) && isfinite(G.v)) {
             const int ii0 = (int)i0, ii1 = (int)i1, jj0 = (int)j0, jj1 = (int)j1;
             box = make_short4((short)ii0, (short)jj0, (short)ii1, (short)jj1);
@@ -337,7 +338,7 @@ struct ProjBwdArgs {
   const float* scales;
   const float* quats;
   const void* sh;
-  const float* grad2d;    // [n][12]: u v A B C o r g b - - -
+  const float* grad2d;    // [n][12]: u v A B C o r g b depth - -
   const uint32_t* count;
   float* g_means;
   float* g_scales;
@@ -422,6 +423,8 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjBwdArgs a) {
     gtz += -cc.fx * G.tx / tz2 * gu;
     gty += cc.fy / tz * gv;
     gtz += -cc.fy * G.ty / tz2 * gv;
+    // depth image: d(depth)/d(tz) = 1
+    gtz += (double)g2[9];
     // t = W mu + t_c
     for (int k = 0; k < 3; ++k) gm[k] = cc.R[0 * 3 + k] * gtx + cc.R[1 * 3 + k] * gty + cc.R[2 * 3 + k] * gtz;
     // Sigma = M M^T, M = R diag(s):  dM = 2 dSigma M

@@ -53,7 +53,8 @@ class fe_gaussians(C.Structure):
 
 
 class fe_images(C.Structure):
-    _fields_ = [("rgb", C.c_void_p), ("feat", C.c_void_p), ("final_T", C.c_void_p), ("n_contrib", C.c_void_p)]
+    _fields_ = [("rgb", C.c_void_p), ("feat", C.c_void_p), ("final_T", C.c_void_p), ("n_contrib", C.c_void_p),
+                ("depth", C.c_void_p)]
 
 
 class fe_grads(C.Structure):
@@ -83,17 +84,17 @@ EXPORTS = {
                                     C.POINTER(fe_images), C.c_void_p, C.c_size_t, C.c_void_p]),
     "fe_render_backward": (C.c_int, [C.POINTER(fe_config), C.POINTER(fe_camera), C.POINTER(fe_gaussians),
                                      C.POINTER(fe_images), C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
-                                     C.POINTER(fe_grads), C.c_void_p, C.c_size_t, C.c_void_p]),
+                                     C.c_void_p, C.POINTER(fe_grads), C.c_void_p, C.c_size_t, C.c_void_p]),
     "fe_render_backward_noalloc": (C.c_int, [C.POINTER(fe_config), C.POINTER(fe_camera), C.POINTER(fe_gaussians),
                                              C.POINTER(fe_images), C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
-                                             C.POINTER(fe_grads), C.c_void_p]),
+                                             C.c_void_p, C.POINTER(fe_grads), C.c_void_p]),
     "fe_read_report": (C.c_int, [C.c_void_p, C.c_size_t, C.POINTER(fe_report), C.c_void_p]),
     "fe_batch_workspace_bytes": (C.c_size_t, [C.POINTER(fe_config), C.POINTER(fe_camera), C.c_int32,
                                               C.POINTER(C.c_int64)]),
     "fe_batch_plan_create": (C.c_int, [C.POINTER(fe_config), C.POINTER(fe_camera), C.c_int32,
                                        C.POINTER(fe_gaussians), C.POINTER(fe_images), C.POINTER(C.c_void_p),
-                                       C.POINTER(C.c_void_p), C.POINTER(fe_grads), C.c_int32, C.c_void_p,
-                                       C.c_size_t, C.POINTER(C.c_void_p)]),
+                                       C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(fe_grads), C.c_int32,
+                                       C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)]),
     "fe_batch_launch": (C.c_int, [C.c_void_p, C.c_void_p]),
     "fe_batch_read_report": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(fe_report), C.c_void_p]),
     "fe_batch_plan_destroy": (None, [C.c_void_p]),
@@ -114,7 +115,7 @@ def load_library(path: str = LIB_PATH):
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
-    if lib.fe_abi_version() != 3:
+    if lib.fe_abi_version() != 4:
         raise ImportError("libfe4dgs_rast.so ABI version mismatch")
     _lib = lib
     return lib
@@ -213,6 +214,7 @@ class ForwardResult:
     cfg: fe_config
     cam: fe_camera
     report: dict | None = None
+    depth: torch.Tensor | None = None
 
 
 def _gaussians_c(means, scales, quats, opacity, sh, feat, st: Settings):
@@ -272,8 +274,10 @@ def render_forward(means, scales, quats, opacity, sh, feat, cam, st: Settings, c
         if out is None:
             out = dict(rgb=torch.empty(3, H, W, device=dev), feat=torch.empty(D, H, W, device=dev),
                        final_T=torch.empty(H, W, device=dev),
-                       n_contrib=torch.empty(H, W, dtype=torch.int32, device=dev))
-        im = fe_images(_ptr(out["rgb"]), _ptr(out["feat"]), _ptr(out["final_T"]), _ptr(out["n_contrib"]))
+                       n_contrib=torch.empty(H, W, dtype=torch.int32, device=dev),
+                       depth=torch.empty(H, W, device=dev))
+        im = fe_images(_ptr(out["rgb"]), _ptr(out["feat"]), _ptr(out["final_T"]), _ptr(out["n_contrib"]),
+                       _ptr(out.get("depth")))
         _check(lib.fe_render_forward(C.byref(cfg), C.byref(cam_c), C.byref(g), C.byref(im),
                                      C.c_void_p(state.data_ptr()), state.numel(),
                                      C.c_void_p(_stream_handle(stream))), "fe_render_forward")
@@ -287,14 +291,16 @@ def render_forward(means, scales, quats, opacity, sh, feat, cam, st: Settings, c
                     continue
                 raise RasterError(FE_ERR_KEY_OVERFLOW, f"fe_render_forward needs {rep['keys_needed']} keys")
             _check(rep["status"], "fe_render_forward (device)")
-        return ForwardResult(out["rgb"], out["feat"], out["final_T"], out["n_contrib"], state, cfg, cam_c, rep)
+        return ForwardResult(out["rgb"], out["feat"], out["final_T"], out["n_contrib"], state, cfg, cam_c, rep,
+                             out.get("depth"))
     raise RasterError(FE_ERR_KEY_OVERFLOW, "fe_render_forward: capacity did not converge")
 
 
 def render_backward(fwd: ForwardResult, means, scales, quats, opacity, sh, feat, d_rgb, d_feat,
                     st: Settings, stream=None, grads: dict | None = None, scratch: torch.Tensor | None = None,
-                    want_means2d: bool = False, check: bool = True) -> dict:
-    """Gradients of <d_rgb, rgb> + <d_feat, feat> for every input (float32).
+                    want_means2d: bool = False, check: bool = True, d_depth=None) -> dict:
+    """Gradients of <d_rgb, rgb> + <d_feat, feat> (+ <d_depth, depth>) for
+    every input (float32).
     With ``check`` the report is read back (one stream synchronisation) and a
     backward that ran out of partial rows (a ``row_capacity`` below the
     frame's need) raises instead of returning invalid gradients."""
@@ -305,6 +311,8 @@ def render_backward(fwd: ForwardResult, means, scales, quats, opacity, sh, feat,
     H, W, D = fwd.cam.height, fwd.cam.width, st.feat_dim
     _req(d_rgb, torch.float32, (3, H, W), "d_rgb")
     _req(d_feat, torch.float32, (D, H, W), "d_feat")
+    if d_depth is not None:
+        _req(d_depth, torch.float32, (H, W), "d_depth")
     g = _gaussians_c(means, scales, quats, opacity, sh, feat, st)
     if grads is None:
         grads = dict(means=torch.empty(n, 3, device=dev), scales=torch.empty(n, 3, device=dev),
@@ -323,10 +331,11 @@ def render_backward(fwd: ForwardResult, means, scales, quats, opacity, sh, feat,
         scratch = torch.empty(max(sc_bytes, 1), dtype=torch.uint8, device=dev)
     gr = fe_grads(_ptr(grads["means"]), _ptr(grads["scales"]), _ptr(grads["quats"]), _ptr(grads["opacity"]),
                   _ptr(grads["sh"]), _ptr(grads["feat"]), _ptr(grads.get("means2d")))
-    im = fe_images(_ptr(fwd.rgb), _ptr(fwd.feat), _ptr(fwd.final_T), _ptr(fwd.n_contrib))
+    im = fe_images(_ptr(fwd.rgb), _ptr(fwd.feat), _ptr(fwd.final_T), _ptr(fwd.n_contrib), _ptr(fwd.depth))
     _check(lib.fe_render_backward(C.byref(cfg), C.byref(fwd.cam), C.byref(g), C.byref(im),
                                   C.c_void_p(fwd.state.data_ptr()), fwd.state.numel(),
-                                  C.c_void_p(d_rgb.data_ptr()), C.c_void_p(d_feat.data_ptr()), C.byref(gr),
+                                  C.c_void_p(d_rgb.data_ptr()), C.c_void_p(d_feat.data_ptr()),
+                                  C.c_void_p(_ptr(d_depth)), C.byref(gr),
                                   C.c_void_p(scratch.data_ptr()), scratch.numel(),
                                   C.c_void_p(_stream_handle(stream))), "fe_render_backward")
     grads["_scratch"] = scratch
@@ -343,7 +352,7 @@ NOALLOC_SCRATCH_BYTES = 256 << 20    # FE_NOALLOC_SCRATCH_BYTES
 
 
 def render_backward_noalloc(fwd: ForwardResult, means, scales, quats, opacity, sh, feat, d_rgb, d_feat,
-                            st: Settings, grads: dict, stream=None, check: bool = True) -> dict:
+                            st: Settings, grads: dict, stream=None, check: bool = True, d_depth=None) -> dict:
     """fe_render_backward_noalloc: the backward with its scratch in the
     library's per-GPU array (nothing is allocated; ``grads`` are the caller's
     float32 output buffers).  Raises FE_ERR_WORKSPACE_TOO_SMALL when the
@@ -352,6 +361,8 @@ def render_backward_noalloc(fwd: ForwardResult, means, scales, quats, opacity, s
     H, W, D = fwd.cam.height, fwd.cam.width, st.feat_dim
     _req(d_rgb, torch.float32, (3, H, W), "d_rgb")
     _req(d_feat, torch.float32, (D, H, W), "d_feat")
+    if d_depth is not None:
+        _req(d_depth, torch.float32, (H, W), "d_depth")
     g = _gaussians_c(means, scales, quats, opacity, sh, feat, st)
     cfg = fe_config.from_buffer_copy(fwd.cfg)
     cfg.stage_events = None
@@ -361,10 +372,11 @@ def render_backward_noalloc(fwd: ForwardResult, means, scales, quats, opacity, s
         cfg.row_capacity = max(int(fwd.report["rows_needed"]), 1)
     gr = fe_grads(_ptr(grads["means"]), _ptr(grads["scales"]), _ptr(grads["quats"]), _ptr(grads["opacity"]),
                   _ptr(grads["sh"]), _ptr(grads["feat"]), _ptr(grads.get("means2d")))
-    im = fe_images(_ptr(fwd.rgb), _ptr(fwd.feat), _ptr(fwd.final_T), _ptr(fwd.n_contrib))
+    im = fe_images(_ptr(fwd.rgb), _ptr(fwd.feat), _ptr(fwd.final_T), _ptr(fwd.n_contrib), _ptr(fwd.depth))
     _check(lib.fe_render_backward_noalloc(C.byref(cfg), C.byref(fwd.cam), C.byref(g), C.byref(im),
                                           C.c_void_p(fwd.state.data_ptr()), fwd.state.numel(),
-                                          C.c_void_p(d_rgb.data_ptr()), C.c_void_p(d_feat.data_ptr()), C.byref(gr),
+                                          C.c_void_p(d_rgb.data_ptr()), C.c_void_p(d_feat.data_ptr()),
+                                          C.c_void_p(_ptr(d_depth)), C.byref(gr),
                                           C.c_void_p(_stream_handle(stream))), "fe_render_backward_noalloc")
     if check:
         rep = read_report(fwd.state, stream)
@@ -376,8 +388,8 @@ def render_backward_noalloc(fwd: ForwardResult, means, scales, quats, opacity, s
 
 class RasterizeFE(torch.autograd.Function):
     """Differentiable rasterization: (means, scales, quats, opacity, sh,
-    feat) -> (rgb [3,H,W], feat [D,H,W]).  final_T and n_contrib are returned
-    as non-differentiable outputs."""
+    feat) -> (rgb [3,H,W], feat [D,H,W], depth [H,W]).  final_T and n_contrib
+    are returned as non-differentiable outputs."""
 
     @staticmethod
     def forward(ctx, means, scales, quats, opacity, sh, feat, cam, st: Settings):
@@ -386,10 +398,10 @@ class RasterizeFE(torch.autograd.Function):
         ctx.fwd = fwd
         ctx.st = st
         ctx.mark_non_differentiable(fwd.final_T, fwd.n_contrib)
-        return fwd.rgb, fwd.feat, fwd.final_T, fwd.n_contrib
+        return fwd.rgb, fwd.feat, fwd.depth, fwd.final_T, fwd.n_contrib
 
     @staticmethod
-    def backward(ctx, g_rgb, g_feat, _g_T, _g_n):
+    def backward(ctx, g_rgb, g_feat, g_depth, _g_T, _g_n):
         means, scales, quats, opacity, sh, feat = ctx.saved_tensors
         fwd = ctx.fwd
         H, W = fwd.cam.height, fwd.cam.width
@@ -398,12 +410,13 @@ class RasterizeFE(torch.autograd.Function):
         if g_feat is None:
             g_feat = torch.zeros(ctx.st.feat_dim, H, W, device=means.device)
         gr = render_backward(fwd, means, scales, quats, opacity, sh, feat, g_rgb.contiguous().float(),
-                             g_feat.contiguous().float(), ctx.st)
+                             g_feat.contiguous().float(), ctx.st,
+                             d_depth=None if g_depth is None else g_depth.contiguous().float())
         ctx.fp32_grads = gr   # the float32 buffers, before any dtype cast
         return (gr["means"], gr["scales"], gr["quats"], gr["opacity"], gr["sh"].to(sh.dtype),
                 gr["feat"].to(feat.dtype), None, None)
 
 
 def rasterize(means, scales, quats, opacity, sh, feat, cam, st: Settings):
-    """Differentiable render; returns (rgb, feat, final_T, n_contrib)."""
+    """Differentiable render; returns (rgb, feat, depth, final_T, n_contrib)."""
     return RasterizeFE.apply(means, scales, quats, opacity, sh, feat, cam, st)

@@ -109,6 +109,8 @@ def compare_images(fwd, orc, sc, st, tiles=None, tol=1e-5, feat_in=None):
     g_feat = fwd.feat.double().cpu().numpy()
     g_T = fwd.final_T.double().cpu().numpy()
     g_n = fwd.n_contrib.cpu().numpy()
+    g_d = fwd.depth.double().cpu().numpy() if getattr(fwd, "depth", None) is not None else None
+    o_d = orc["depth"].numpy()
     o_rgb, o_feat = orc["rgb"].numpy(), orc["feat"].numpy()
     o_T, o_n = orc["final_T"].numpy(), orc["n_contrib"].numpy()
     H, W = o_T.shape
@@ -127,6 +129,11 @@ def compare_images(fwd, orc, sc, st, tiles=None, tol=1e-5, feat_in=None):
         err = np.abs(g - o)[:, clean].max() / ref if clean.any() else 0.0
         stats[name] = err
         assert err <= tol, (name, err)
+    if g_d is not None:
+        ref = max(np.abs(o_d[mask]).max(), 1e-30)
+        err = np.abs(g_d - o_d)[clean].max() / ref if clean.any() else 0.0
+        stats["depth"] = err
+        assert err <= tol, ("depth", err)
     errT = np.abs(g_T - o_T)[clean].max() if clean.any() else 0.0
     stats["final_T"] = errT
     assert errT <= tol, ("final_T", errT)
@@ -138,6 +145,7 @@ def compare_images(fwd, orc, sc, st, tiles=None, tol=1e-5, feat_in=None):
     feat_in = stored_inputs(sc, st.feat_dtype)["feat"] if feat_in is None else feat_in
     ref_r = max(np.abs(o_rgb[:, mask]).max(), 1e-30)
     ref_f = max(np.abs(o_feat[:, mask]).max(), 1e-30)
+    ref_d = max(np.abs(o_d[mask]).max(), 1e-30)
     for j, i in zip(*np.nonzero(amb)):
         t = (j // st.tile_h) * (-(-W // st.tile_w)) + i // st.tile_w
         vs = pixel_variants(int(i), int(j), orc["proj"], feat_in, orc["lists"], orc["cam"], orc["cfg"],
@@ -146,7 +154,7 @@ def compare_images(fwd, orc, sc, st, tiles=None, tol=1e-5, feat_in=None):
         if vs is not None:
             for (vr, vf, vT, vn, vd) in vs:
                 if (np.abs(vr - g_rgb[:, j, i]).max() <= tol * ref_r and np.abs(vf - g_feat[:, j, i]).max() <= tol * ref_f
-                        and abs(vT - g_T[j, i]) <= tol):
+                        and abs(vT - g_T[j, i]) <= tol and (g_d is None or abs(vd - g_d[j, i]) <= tol * ref_d)):
                     ok = True
                     break
         unresolved += 0 if ok else 1
@@ -156,10 +164,26 @@ def compare_images(fwd, orc, sc, st, tiles=None, tol=1e-5, feat_in=None):
     return stats
 
 
-def oracle_backward(sc, st, d_rgb, d_feat, cam=None, tiles=None):
+def oracle_backward(sc, st, d_rgb, d_feat, cam=None, tiles=None, d_depth=None):
     inp = stored_inputs(sc, st.feat_dtype)
     return oracle.render_backward(**inp, cam=cam if cam is not None else sc.cam, cfg=oracle_cfg(sc, st),
-                                  d_rgb=d_rgb, d_feat=d_feat, parity=True, tiles=tiles)
+                                  d_rgb=d_rgb, d_feat=d_feat, parity=True, tiles=tiles, d_depth=d_depth)
+
+
+def depth_grad(H, W, seed, std=1e-3):
+    """An upstream depth-image gradient (its own generator, so the other
+    draws of a test are unchanged)."""
+    return np.random.default_rng(10_000 + seed).normal(0, std, (H, W)).astype(np.float32)
+
+
+def screen_grads(gr, n):
+    """The backward's per-Gaussian screen-space sums from its scratch:
+    u v A B C opacity r g b depth."""
+    g2 = gr["_scratch"][: 48 * n].view(torch.float32).reshape(n, 12).cpu().numpy()
+    return dict(xy=g2[:, 0:2], conic=g2[:, 2:5], opacity2d=g2[:, 5], rgb2d=g2[:, 6:9], depth2d=g2[:, 9])
+
+
+SCREEN_KEYS = ("xy", "conic", "opacity2d", "rgb2d", "depth2d")
 
 
 def normwise(a, b):

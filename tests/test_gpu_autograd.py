@@ -1,6 +1,7 @@
 """torch.autograd.Function wiring, and the GPU gradients against FP64 central
 finite differences of the oracle on the 64-Gaussian 32x32 window of the
-640x512, 300k-Gaussian, D=128 workload (both storage forms)."""
+640x512, 300k-Gaussian, D=128 workload (both storage forms); the loss takes
+the colour, feature and depth images."""
 import numpy as np
 import pytest
 import torch
@@ -39,6 +40,7 @@ def _window_scene():
     rng = np.random.default_rng(21)
     sub.d_rgb = rng.normal(0, 1, (3, 32, 32)).astype(np.float32)
     sub.d_feat = rng.normal(0, 1, (128, 32, 32)).astype(np.float32)
+    sub.d_depth = rng.normal(0, 1, (32, 32)).astype(np.float32)
     return sub
 
 
@@ -50,14 +52,15 @@ def test_autograd_function_matches_c_abi():
     leaves = {k: d[k].clone().requires_grad_(True) for k in ("means", "scales", "quats", "opacity")}
     sh = d["sh"].clone().requires_grad_(True)
     ft = d["feat"].clone().requires_grad_(True)
-    rgb, feat, T, n = rast.rasterize(leaves["means"], leaves["scales"], leaves["quats"], leaves["opacity"], sh, ft,
-                                     sc.cam, st)
-    assert not T.requires_grad and not n.requires_grad
+    rgb, feat, depth, T, n = rast.rasterize(leaves["means"], leaves["scales"], leaves["quats"], leaves["opacity"],
+                                            sh, ft, sc.cam, st)
+    assert not T.requires_grad and not n.requires_grad and depth.requires_grad
     g_rgb, g_feat = torch.from_numpy(sc.d_rgb).cuda(), torch.from_numpy(sc.d_feat).cuda()
-    ((rgb * g_rgb).sum() + (feat * g_feat).sum()).backward()
+    g_depth = torch.from_numpy(sc.d_depth).cuda()
+    ((rgb * g_rgb).sum() + (feat * g_feat).sum() + (depth * g_depth).sum()).backward()
     fwd = rast.render_forward(d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["feat"], sc.cam, st)
     ref = rast.render_backward(fwd, d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["feat"],
-                               g_rgb, g_feat, st)
+                               g_rgb, g_feat, st, d_depth=g_depth)
     for k in ("means", "scales", "quats", "opacity"):
         torch.testing.assert_close(leaves[k].grad, ref[k], rtol=1e-5, atol=1e-7)
     assert sh.grad.dtype == torch.bfloat16 and ft.grad.dtype == torch.bfloat16
@@ -71,7 +74,8 @@ def test_gradients_vs_fp64_finite_differences(dtype):
     st = U.settings_for(sc, dtype=dtype)
     fwd, d = U.gpu_forward(sc, st, cam=sc.cam)
     gr = rast.render_backward(fwd, d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["feat"],
-                              torch.from_numpy(sc.d_rgb).cuda(), torch.from_numpy(sc.d_feat).cuda(), st)
+                              torch.from_numpy(sc.d_rgb).cuda(), torch.from_numpy(sc.d_feat).cuda(), st,
+                              d_depth=torch.from_numpy(sc.d_depth).cuda())
     torch.cuda.synchronize()
     inp = U.stored_inputs(sc, dtype)
     params = {k: np.asarray(v, np.float64) for k, v in inp.items()}
@@ -81,7 +85,7 @@ def test_gradients_vs_fp64_finite_differences(dtype):
     for name in ("means", "scales", "quats", "opacity", "sh", "feat"):
         flat = params[name].reshape(-1)
         idx = list(rng.choice(flat.size, size=min(24, flat.size), replace=False))
-        fd, valid = oracle.fd_gradient(params, name, idx, sc.cam, cfg, sc.d_rgb, sc.d_feat)
+        fd, valid = oracle.fd_gradient(params, name, idx, sc.cam, cfg, sc.d_rgb, sc.d_feat, d_depth=sc.d_depth)
         g = gr[name].cpu().numpy().reshape(-1)[idx]
         nvalid += int(valid.sum())
         # every group needs enough samples whose discrete trace is unchanged at x +- h

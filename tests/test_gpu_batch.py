@@ -133,8 +133,10 @@ def test_batched_frames_match_oracle(tile):
     H, W = cams[0].height, cams[0].width
     d_rgb = [rng.normal(0, 1, (3, H, W)).astype(np.float32) for _ in frames]
     d_feat = [rng.normal(0, 1, (64, H, W)).astype(np.float32) for _ in frames]
+    d_depth = [rng.normal(0, 1, (H, W)).astype(np.float32) for _ in frames]
     br = BatchRenderer(frames, cams, st, rast.FE_MODE_FORWARD_BACKWARD,
-                       [torch.from_numpy(x).cuda() for x in d_rgb], [torch.from_numpy(x).cuda() for x in d_feat])
+                       [torch.from_numpy(x).cuda() for x in d_rgb], [torch.from_numpy(x).cuda() for x in d_feat],
+                       d_depth=[torch.from_numpy(x).cuda() for x in d_depth])
     for rep in range(2):
         br.launch()
         torch.cuda.synchronize()
@@ -152,7 +154,8 @@ def test_batched_frames_match_oracle(tile):
             fw = F()
             fw.rgb, fw.feat, fw.final_T, fw.n_contrib = (br.out[k]["rgb"], br.out[k]["feat"], br.out[k]["final_T"],
                                                          br.out[k]["n_contrib"])
+            fw.depth = br.out[k]["depth"]
             say("replay", rep, "frame", k, U.compare_images(fw, orc, s2, st))
-            ob = U.oracle_backward(s2, st, d_rgb[k], d_feat[k], cam=cams[k])
+            ob = U.oracle_backward(s2, st, d_rgb[k], d_feat[k], cam=cams[k], d_depth=d_depth[k])
             U.check_grads(br.grads[k], ob)
     br.close()

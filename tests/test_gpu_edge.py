@@ -150,10 +150,12 @@ def test_ragged_and_tiny_images(wh, variant):
     rng = np.random.default_rng(3)
     d_rgb = rng.normal(0, 1, (3, h, w)).astype(np.float32)
     d_feat = rng.normal(0, 1, (sc.feat_dim, h, w)).astype(np.float32)
+    d_depth = U.depth_grad(h, w, 3, std=1.0)
     gr = rast.render_backward(fwd, d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["feat"],
-                              torch.from_numpy(d_rgb).cuda(), torch.from_numpy(d_feat).cuda(), st)
+                              torch.from_numpy(d_rgb).cuda(), torch.from_numpy(d_feat).cuda(), st,
+                              d_depth=torch.from_numpy(d_depth).cuda())
     torch.cuda.synchronize()
-    ob = U.oracle_backward(sc, st, d_rgb, d_feat, cam=cam)
+    ob = U.oracle_backward(sc, st, d_rgb, d_feat, cam=cam, d_depth=d_depth)
     U.check_grads(gr, ob)
 
 

@@ -46,10 +46,13 @@ def _fwd_bwd(sc, st, cam, seed):
     H, W = cam.height, cam.width
     d_rgb = rng.normal(0, 1, (3, H, W)).astype(np.float32)
     d_feat = rng.normal(0, 1, (sc.feat_dim, H, W)).astype(np.float32)
+    d_depth = U.depth_grad(H, W, seed, std=1.0)
     gr = rast.render_backward(fwd, d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["feat"],
-                              torch.from_numpy(d_rgb).cuda(), torch.from_numpy(d_feat).cuda(), st)
+                              torch.from_numpy(d_rgb).cuda(), torch.from_numpy(d_feat).cuda(), st,
+                              d_depth=torch.from_numpy(d_depth).cuda())
     torch.cuda.synchronize()
-    ob = U.oracle_backward(sc, st, d_rgb, d_feat, cam=cam)
+    ob = U.oracle_backward(sc, st, d_rgb, d_feat, cam=cam, d_depth=d_depth)
+    U.check_grads(U.screen_grads(gr, sc.n), ob, keys=U.SCREEN_KEYS)
     U.check_grads(gr, ob)
 
 

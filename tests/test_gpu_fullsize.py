@@ -53,13 +53,13 @@ def _whole_frame(sc, dtype):
     # walk of a tile being its largest n_contrib (compared with the oracle above)
     walks = _tile_walks(fwd.n_contrib.cpu().numpy(), st.tile_w, st.tile_h)
     assert fwd.report["rows_needed"] == int(walks.sum())
+    d_depth = U.depth_grad(sc.cam.height, sc.cam.width, 1)
     gr = rast.render_backward(fwd, d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["feat"],
-                              torch.from_numpy(sc.d_rgb).cuda(), torch.from_numpy(sc.d_feat).cuda(), st)
+                              torch.from_numpy(sc.d_rgb).cuda(), torch.from_numpy(sc.d_feat).cuda(), st,
+                              d_depth=torch.from_numpy(d_depth).cuda())
     torch.cuda.synchronize()
-    ob = U.oracle_backward(sc, st, sc.d_rgb, sc.d_feat)
-    g2 = gr["_scratch"][: 48 * sc.n].view(torch.float32).reshape(sc.n, 12).cpu().numpy()
-    screen = dict(xy=g2[:, 0:2], conic=g2[:, 2:5], opacity2d=g2[:, 5], rgb2d=g2[:, 6:9])
-    U.check_grads(screen, ob, keys=("xy", "conic", "opacity2d", "rgb2d"))
+    ob = U.oracle_backward(sc, st, sc.d_rgb, sc.d_feat, d_depth=d_depth)
+    U.check_grads(U.screen_grads(gr, sc.n), ob, keys=U.SCREEN_KEYS)
     U.check_grads(gr, ob)
 
 
@@ -95,8 +95,10 @@ def test_large_frame_capacity_8n_sampled_tiles():
         mask[y0:y0 + 16, x0:x0 + 16] = 1.0
     d_rgb = (sc.d_rgb * mask).astype(np.float32)
     d_feat = (sc.d_feat * mask).astype(np.float32)
+    d_depth = (U.depth_grad(sc.cam.height, sc.cam.width, 2) * mask).astype(np.float32)
     gr = rast.render_backward(fwd, d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["feat"],
-                              torch.from_numpy(d_rgb).cuda(), torch.from_numpy(d_feat).cuda(), st)
+                              torch.from_numpy(d_rgb).cuda(), torch.from_numpy(d_feat).cuda(), st,
+                              d_depth=torch.from_numpy(d_depth).cuda())
     torch.cuda.synchronize()
-    ob = U.oracle_backward(sc, st, d_rgb, d_feat, tiles=sample)
+    ob = U.oracle_backward(sc, st, d_rgb, d_feat, tiles=sample, d_depth=d_depth)
     U.check_grads(gr, ob)

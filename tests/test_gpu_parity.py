@@ -97,13 +97,13 @@ def test_mid_window_forward_backward(dtype, variant):
     rng = np.random.default_rng(11)
     d_rgb = rng.normal(0, 1e-3, (3, 76, 100)).astype(np.float32)
     d_feat = rng.normal(0, 1e-3, (32, 76, 100)).astype(np.float32)
+    d_depth = U.depth_grad(76, 100, 11)
     gr = rast.render_backward(fwd, d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["feat"],
-                              torch.from_numpy(d_rgb).cuda(), torch.from_numpy(d_feat).cuda(), st)
+                              torch.from_numpy(d_rgb).cuda(), torch.from_numpy(d_feat).cuda(), st,
+                              d_depth=torch.from_numpy(d_depth).cuda())
     torch.cuda.synchronize()
-    ob = U.oracle_backward(sw, st, d_rgb, d_feat, cam=cam)
-    g2 = gr["_scratch"][: 48 * sc.n].view(torch.float32).reshape(sc.n, 12).cpu().numpy()
-    screen = dict(xy=g2[:, 0:2], conic=g2[:, 2:5], opacity2d=g2[:, 5], rgb2d=g2[:, 6:9])
-    U.check_grads(screen, ob, keys=("xy", "conic", "opacity2d", "rgb2d"))
+    ob = U.oracle_backward(sw, st, d_rgb, d_feat, cam=cam, d_depth=d_depth)
+    U.check_grads(U.screen_grads(gr, sc.n), ob, keys=U.SCREEN_KEYS)
     U.check_grads(gr, ob)
 
 
@@ -125,10 +125,13 @@ def test_metric_window_d128(dtype, variant):
     rng = np.random.default_rng(12)
     d_rgb = rng.normal(0, 1e-3, (3, 48, 64)).astype(np.float32)
     d_feat = rng.normal(0, 1e-3, (128, 48, 64)).astype(np.float32)
+    d_depth = U.depth_grad(48, 64, 12)
     gr = rast.render_backward(fwd, d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["feat"],
-                              torch.from_numpy(d_rgb).cuda(), torch.from_numpy(d_feat).cuda(), st)
+                              torch.from_numpy(d_rgb).cuda(), torch.from_numpy(d_feat).cuda(), st,
+                              d_depth=torch.from_numpy(d_depth).cuda())
     torch.cuda.synchronize()
-    ob = U.oracle_backward(sw, st, d_rgb, d_feat, cam=cam)
+    ob = U.oracle_backward(sw, st, d_rgb, d_feat, cam=cam, d_depth=d_depth)
+    U.check_grads(U.screen_grads(gr, sc.n), ob, keys=U.SCREEN_KEYS)
     U.check_grads(gr, ob)
 
 
@@ -150,8 +153,12 @@ def test_threads_per_tile(tile, threads):
     rng = np.random.default_rng(13)
     d_rgb = rng.normal(0, 1, (3, 40, 56)).astype(np.float32)
     d_feat = rng.normal(0, 1, (128, 40, 56)).astype(np.float32)
+    d_depth = U.depth_grad(40, 56, 13)
     gr = rast.render_backward(fwd, d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["feat"],
-                              torch.from_numpy(d_rgb).cuda(), torch.from_numpy(d_feat).cuda(), st)
+                              torch.from_numpy(d_rgb).cuda(), torch.from_numpy(d_feat).cuda(), st,
+                              d_depth=torch.from_numpy(d_depth).cuda())
     torch.cuda.synchronize()
-    U.check_grads(gr, U.oracle_backward(sw, st, d_rgb, d_feat, cam=cam))
+    ob = U.oracle_backward(sw, st, d_rgb, d_feat, cam=cam, d_depth=d_depth)
+    U.check_grads(U.screen_grads(gr, sc.n), ob, keys=U.SCREEN_KEYS)
+    U.check_grads(gr, ob)
 

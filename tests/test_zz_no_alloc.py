@@ -44,15 +44,17 @@ def test_noalloc_backward_equals_backward_twice_second_smaller(dtype):
         rng = np.random.default_rng(40 + k)
         d_rgb = torch.from_numpy(rng.normal(0, 1, (3, cam.height, cam.width)).astype(np.float32)).cuda()
         d_feat = torch.from_numpy(rng.normal(0, 1, (128, cam.height, cam.width)).astype(np.float32)).cuda()
+        d_depth = torch.from_numpy(rng.normal(0, 1, (cam.height, cam.width)).astype(np.float32)).cuda()
         args = (d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["feat"])
-        ref = rast.render_backward(fwd, *args, d_rgb, d_feat, st)
+        ref = rast.render_backward(fwd, *args, d_rgb, d_feat, st, d_depth=d_depth)
         K = (s2.sh_degree + 1) ** 2
-        got = rast.render_backward_noalloc(fwd, *args, d_rgb, d_feat, st, _empty_grads(n, K, 128))
+        got = rast.render_backward_noalloc(fwd, *args, d_rgb, d_feat, st, _empty_grads(n, K, 128), d_depth=d_depth)
         torch.cuda.synchronize()
         for name in U.GRAD_KEYS:
             assert torch.equal(got[name], ref[name]), (k, name)
         if k == 1:
-            ob = U.oracle_backward(s2, st, d_rgb.cpu().numpy(), d_feat.cpu().numpy(), cam=cam)
+            ob = U.oracle_backward(s2, st, d_rgb.cpu().numpy(), d_feat.cpu().numpy(), cam=cam,
+                                   d_depth=d_depth.cpu().numpy())
             U.check_grads(got, ob)
 
 
