@@ -54,7 +54,7 @@ def _parse():
                     help="compositing kernels: matrix cores (default) or vector ALU")
     ap.add_argument("--no-batched", action="store_true", help="skip the 16-timestamp graph form")
     ap.add_argument("--batch-tile", default=None,
-                    help="TWxTH[:THREADS] for the 16-timestamp form instead of the autotuner's choice")
+                    help="TWxTH[:THREADS[:FLAGS]] for the 16-timestamp form instead of the autotuner's choice")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for HBM counters)")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the FP64-oracle accuracy block")
@@ -226,10 +226,11 @@ def run_batched(steps, warmup, fixed=None):
     d_depth = [t(rng.normal(0, 1e-3, (H, W)).astype(np.float32)) for _ in fr]
     st = rast.Settings(sh_degree=3, feat_dim=64, sh_dtype="bf16", feat_dtype="bf16")
     if fixed:
-        shape, _, tpt = fixed.partition(":")
+        shape, _, rest = fixed.partition(":")
+        tpt, _, fl = rest.partition(":")
         tw, th = (int(x) for x in shape.split("x"))
         st = rast.Settings(**{**st.__dict__, "tile_w": tw, "tile_h": th, "variant": rast.FE_VARIANT_MFMA,
-                              "threads_per_tile": int(tpt or 0)})
+                              "threads_per_tile": int(tpt or 0), "flags": int(fl or 0)})
     else:
         # tile shape, threads per tile and variant from the batch autotuner
         # (untimed; whole replays)
@@ -277,6 +278,7 @@ def run_batched(steps, warmup, fixed=None):
     return dict(frames=len(fr), gaussians_per_frame=[f["n"] for f in fr], ms_per_replay=round(ms, 4),
                 frames_per_s=round(len(fr) * 1e3 / ms, 2), status_errors=bad,
                 tile=f"{st.tile_w}x{st.tile_h}", threads_per_tile=st.threads_per_tile,
+                persistent_compositing=not (st.flags & rast.FE_FLAG_BATCH_PER_FRAME),
                 variant="valu" if st.variant == rast.FE_VARIANT_VALU else "mfma",
                 separate_calls={"ms_per_16_frames": round(ms_calls, 4),
                                 "frames_per_s": round(len(fr) * 1e3 / ms_calls, 2)},

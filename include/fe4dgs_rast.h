@@ -131,6 +131,10 @@ typedef struct fe_config {
 
 #define FE_FLAG_NO_ZERO_GRADS 0x1u  /* backward accumulates into *out instead of
                                        overwriting it                           */
+#define FE_FLAG_BATCH_PER_FRAME 0x2u  /* batch plans: every frame runs its own
+                                       compositing kernels (frames on parallel
+                                       graph branches) instead of the
+                                       persistent multi-frame launches          */
 
 #define FE_VARIANT_AUTO 0           /* library default                          */
 #define FE_VARIANT_VALU 1           /* vector-ALU blending in both directions   */

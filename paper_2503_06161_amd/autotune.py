@@ -75,8 +75,9 @@ def candidates_for(st: rast.Settings, cam, n: int, shapes=None, variants=None):
 
 
 def _pick(st, c):
+    flags = (st.flags & ~rast.FE_FLAG_BATCH_PER_FRAME) | c.get("batch_flags", 0)
     return rast.Settings(**{**st.__dict__, "tile_w": c["tile_w"], "tile_h": c["tile_h"], "variant": c["variant"],
-                            "threads_per_tile": c.get("threads_per_tile", 0)})
+                            "threads_per_tile": c.get("threads_per_tile", 0), "flags": flags})
 
 
 def time_candidate(g: dict, cam, st: rast.Settings, d_rgb=None, d_feat=None, reps: int = 5) -> float:
@@ -142,10 +143,14 @@ def autotune_batch(frames, cams, st: rast.Settings, d_rgb=None, d_feat=None, can
     cache = _load_cache() if use_cache else {}
     if key in cache:
         return _pick(st, cache[key])
-    cands = candidates or candidates_for(st, cams[0], n)
+    # each candidate twice: persistent multi-frame compositing, and every
+    # frame's own kernels on parallel graph branches
+    cands = candidates or [c + (fl,) for c in candidates_for(st, cams[0], n)
+                           for fl in (0, rast.FE_FLAG_BATCH_PER_FRAME)]
     results = []
-    for tw, th, v, tpt in cands:
-        s2 = rast.Settings(**{**st.__dict__, "tile_w": tw, "tile_h": th, "variant": v, "threads_per_tile": tpt})
+    for tw, th, v, tpt, fl in cands:
+        s2 = rast.Settings(**{**st.__dict__, "tile_w": tw, "tile_h": th, "variant": v, "threads_per_tile": tpt,
+                              "flags": (st.flags & ~rast.FE_FLAG_BATCH_PER_FRAME) | fl})
         br = BatchRenderer(frames, cams, s2, mode, d_rgb, d_feat)
         br.launch()
         times = []
@@ -159,13 +164,13 @@ def autotune_batch(frames, cams, st: rast.Settings, d_rgb=None, d_feat=None, can
         br.close()
         times.sort()
         ms = times[len(times) // 2]
-        results.append((ms, tw, th, v, tpt))
+        results.append((ms, tw, th, v, tpt, fl))
         if verbose:
-            print(f"autotune batch {tw}x{th} variant {v} threads {tpt}: {ms:.3f} ms", flush=True)
-    ms, tw, th, v, tpt = min(results)
-    best = dict(tile_w=tw, tile_h=th, variant=v, threads_per_tile=tpt)
+            print(f"autotune batch {tw}x{th} variant {v} threads {tpt} flags {fl}: {ms:.3f} ms", flush=True)
+    ms, tw, th, v, tpt, fl = min(results)
+    best = dict(tile_w=tw, tile_h=th, variant=v, threads_per_tile=tpt, batch_flags=fl)
     if use_cache:
-        cache[key] = dict(best, ms=ms, all=[dict(tile_w=a, tile_h=b, variant=c, threads_per_tile=t, ms=m)
-                                            for m, a, b, c, t in results])
+        cache[key] = dict(best, ms=ms, all=[dict(tile_w=a, tile_h=b, variant=c, threads_per_tile=t, batch_flags=f,
+                                                 ms=m) for m, a, b, c, t, f in results])
         _store_cache(cache)
     return _pick(st, best)

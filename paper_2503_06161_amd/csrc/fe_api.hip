@@ -430,7 +430,7 @@ struct fe_batch_plan {
 };
 
 static bool batch_persistent(const fe_config* cfg, const fe_camera* cams, int32_t frames) {
-  if (!composite_persistent_supported(cfg)) return false;
+  if ((cfg->flags & FE_FLAG_BATCH_PER_FRAME) || !composite_persistent_supported(cfg)) return false;
   for (int f = 1; f < frames; ++f)
     if (cams[f].width != cams[0].width || cams[f].height != cams[0].height) return false;
   return true;

@@ -606,7 +606,9 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
   // each Gaussian of a batch, and the X values of a 16-Gaussian half
   __shared__ float s_mom[2][NW][6][kNB];
   __shared__ float s_col[2][NW][4][kNB];
-  __shared__ float s_xm[NW][16][64];
+  // rows padded to 68 floats: the moment pass reads 16 rows at one column,
+  // 16 bytes per lane, which then fall in 16 distinct bank groups
+  __shared__ float s_xm[NW][16][68];
   __shared__ int s_live[2][NW];
   __shared__ __attribute__((aligned(16))) unsigned char s_raw[kShared];
   float (*s_g)[GROW] = reinterpret_cast<float (*)[GROW]>(s_raw);
@@ -710,17 +712,18 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
       if (e < kNB * FQ) {
         const int i = e % kNB;
         const int c = (e / kNB) * 4;
+        if constexpr (F32) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const float v = i < nb ? fv[k2].get(j) : 0.f;
-          if constexpr (F32) {
+          for (int j = 0; j < 4; ++j) {
+            const float v = i < nb ? fv[k2].get(j) : 0.f;
             __bf16 h, m;
             split2(v, h, m);
             s_f[b2][0][i][c + j] = h;
             s_f[b2][1][i][c + j] = m;
-          } else {
-            s_f[b2][0][i][c + j] = (__bf16)v;   // exact: the value is a bf16
           }
+        } else {
+          // the stored bf16 bits go to LDS unchanged, four channels per store
+          *reinterpret_cast<uint2*>(&s_f[b2][0][i][c]) = i < nb ? fv[k2].v : make_uint2(0u, 0u);
         }
       }
     }
@@ -1079,18 +1082,28 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
           v9[7] = Cc[1];
           v9[8] = Cc[2];
           v9[9] = Cc[3];
-          auto pick = [&](int t) {
-            float x = 0.f;
-#pragma unroll
-            for (int k2 = 0; k2 < 10; ++k2) x = t == k2 ? v9[k2] : x;
-            return x;
-          };
           float* row = &a.rows[(row0 + pos0 + i) * a.RS];
-          int c = a.D;
-          for (; (c & 3) != 0 && c < a.RS; ++c) row[c] = pick(c - a.D);
-          for (; c < a.RS; c += 4)
-            *reinterpret_cast<float4*>(row + c) =
-                make_float4(pick(c - a.D), pick(c + 1 - a.D), pick(c + 2 - a.D), pick(c + 3 - a.D));
+          if ((a.D & 3) == 0) {
+            // the sums start on a 16-byte boundary: three vector stores, then
+            // zeros to the end of the row's last 128-byte line
+            float4* r4 = reinterpret_cast<float4*>(row + a.D);
+            r4[0] = make_float4(v9[0], v9[1], v9[2], v9[3]);
+            r4[1] = make_float4(v9[4], v9[5], v9[6], v9[7]);
+            r4[2] = make_float4(v9[8], v9[9], 0.f, 0.f);
+            for (int c = a.D + 12; c < a.RS; c += 4) *reinterpret_cast<float4*>(row + c) = make_float4(0.f, 0.f, 0.f, 0.f);
+          } else {
+            auto pick = [&](int t) {
+              float x = 0.f;
+#pragma unroll
+              for (int k2 = 0; k2 < 10; ++k2) x = t == k2 ? v9[k2] : x;
+              return x;
+            };
+            int c = a.D;
+            for (; (c & 3) != 0 && c < a.RS; ++c) row[c] = pick(c - a.D);
+            for (; c < a.RS; c += 4)
+              *reinterpret_cast<float4*>(row + c) =
+                  make_float4(pick(c - a.D), pick(c + 1 - a.D), pick(c + 2 - a.D), pick(c + 3 - a.D));
+          }
         }
         if (q < nb) a.rowidx[ep_w] = (uint32_t)(row0 + pos0 + q + 1);
       }
@@ -1136,8 +1149,11 @@ __global__ __launch_bounds__((WS ? 2 * NT : NT)) void composite_bwd_persistent(
   __syncthreads();
   while (it < n_items) {
     const uint2 item = tq.items[it];
-    if constexpr (WS) bwd_ws_tile<DP, FT, NT, false>(args[item.x], (int)item.y);
-    else bwd_mfma_tile<DP, FT, NT, false>(args[item.x], (int)item.y);
+    // the frame record is copied out of global memory, so that the tile's
+    // stores cannot be taken to alias it (its fields stay in registers)
+    const BwdArgs a = args[item.x];
+    if constexpr (WS) bwd_ws_tile<DP, FT, NT, false>(a, (int)item.y);
+    else bwd_mfma_tile<DP, FT, NT, false>(a, (int)item.y);
     if (threadIdx.x == 0) s_item = atomicAdd(tq.head, 1u);
     __syncthreads();
     it = __builtin_amdgcn_readfirstlane(s_item);

@@ -636,7 +636,8 @@ __global__ __launch_bounds__(2 * NT) void composite_fwd_ws_persistent(const Mfma
   __syncthreads();
   while (it < n_items) {
     const uint2 item = tq.items[it];
-    fwd_ws_tile<DP, NT>(args[item.x], (int)item.y);
+    const MfmaArgs a = args[item.x];   // a private copy of the frame record (see the backward)
+    fwd_ws_tile<DP, NT>(a, (int)item.y);
     if (threadIdx.x == 0) s_item = atomicAdd(tq.head, 1u);
     __syncthreads();
     it = __builtin_amdgcn_readfirstlane(s_item);

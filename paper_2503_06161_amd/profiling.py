@@ -34,8 +34,14 @@ def _csv_rows(root: str, suffix: str):
 
 
 def _short(name: str) -> str:
-    name = re.sub(r"^void ", "", name)
-    name = re.sub(r"\(.*\)$", "", name)               # argument list
+    name = re.sub(r"^void ", "", name.strip())
+    if name.endswith(")"):                            # drop the argument list (the last balanced group)
+        depth = 0
+        for i in range(len(name) - 1, -1, -1):
+            depth += {")": 1, "(": -1}.get(name[i], 0)
+            if depth == 0:
+                name = name[:i]
+                break
     name = name.replace("fe::(anonymous namespace)::", "").replace("fe::", "")
     return name.replace("unsigned short", "bf16")
 

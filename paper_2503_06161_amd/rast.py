@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libfe4dgs_rast.so")
  FE_ERR_ROW_OVERFLOW) = range(7)
 FE_F32, FE_BF16 = 0, 1
 FE_FLAG_NO_ZERO_GRADS = 1
+FE_FLAG_BATCH_PER_FRAME = 2
 FE_VARIANT_AUTO, FE_VARIANT_VALU, FE_VARIANT_MFMA = 0, 1, 2
 FE_MODE_FORWARD, FE_MODE_BACKWARD, FE_MODE_FORWARD_BACKWARD = 1, 2, 3
 STAGES = ("project", "sort", "composite", "composite_bwd", "reduce", "project_bwd")
