@@ -1120,12 +1120,12 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
 
 template <int DP, typename FT, int NT>
 __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
-  bwd_mfma_tile<DP, FT, NT, true>(a, (int)blockIdx.x);
+  bwd_mfma_tile<DP, FT, NT, true>(a, xcd_tile((int)blockIdx.x, (int)gridDim.x));
 }
 
 template <int DP, typename FT, int NT>
 __global__ __launch_bounds__(2 * NT) void composite_bwd_ws_kernel(BwdArgs a) {
-  bwd_ws_tile<DP, FT, NT, true>(a, (int)blockIdx.x);
+  bwd_ws_tile<DP, FT, NT, true>(a, xcd_tile((int)blockIdx.x, (int)gridDim.x));
 }
 
 // The wave-specialized form applies where contractor waves own whole channel

@@ -193,6 +193,22 @@ hipError_t launch_composite_bwd_persistent(const fe_config* cfg, const void* rec
                                            int grid, hipStream_t s);
 
 // ---- small device helpers ----
+// Workgroups of a launch are handed to the eight XCDs in turn (workgroup b
+// runs on XCD b % 8), and each XCD has its own L2.  Tiles are dealt to the
+// XCDs in runs of kXcdRun consecutive tiles (row-major), so that neighbouring
+// tiles, which share 128-byte lines of the planar images (a 16-pixel tile row
+// is half a line) and many Gaussians, are processed by one L2 one after the
+// other, while every XCD still gets tiles from the whole image.  Workgroups
+// past the last whole round keep their own index.
+constexpr int kXcds = 8;
+constexpr int kXcdRun = 16;
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  constexpr int round = kXcds * kXcdRun;
+  if (b >= n - n % round) return b;
+  const int x = b % kXcds, j = b / kXcds;
+  return ((j / kXcdRun) * kXcds + x) * kXcdRun + j % kXcdRun;
+}
+
 // Per-tile quantities that steer loops containing barriers are read back as
 // scalars: the compiler then treats them as uniform and never lowers such a
 // loop (or an early exit around it) with a per-lane exit mask.

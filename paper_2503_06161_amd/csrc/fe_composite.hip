@@ -107,7 +107,7 @@ __global__ __launch_bounds__(NT) void composite_fwd_kernel(CompArgs a) {
   __shared__ int4 s_box[NB];
   __shared__ uint32_t s_gid[NB];
   __shared__ __attribute__((aligned(16))) float s_f[NB * D];
-  const int tile = blockIdx.x;
+  const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
   const int tile_h = NT / a.tile_w;
   const int px = (tile % a.tiles_x) * a.tile_w + (int)threadIdx.x % a.tile_w;
   const int py = (tile / a.tiles_x) * tile_h + (int)threadIdx.x / a.tile_w;
@@ -196,7 +196,7 @@ __global__ __launch_bounds__(NT) void composite_bwd_kernel(CompArgs a) {
   __shared__ uint32_t s_gid[NB];
   __shared__ __attribute__((aligned(16))) float s_f[NB * D];
   __shared__ int s_maxlast;
-  const int tile = blockIdx.x;
+  const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
   const int tile_h = NT / a.tile_w;
   const int px = (tile % a.tiles_x) * a.tile_w + (int)threadIdx.x % a.tile_w;
   const int py = (tile / a.tiles_x) * tile_h + (int)threadIdx.x / a.tile_w;

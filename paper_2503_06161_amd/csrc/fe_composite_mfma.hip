@@ -135,7 +135,7 @@ void composite_fwd_mfma_kernel(MfmaArgs a) {
   __shared__ __attribute__((aligned(16))) __bf16 s_f[NPL][kNB][FROW];
   __shared__ int s_maxlast;
 
-  const int tile = blockIdx.x;
+  const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int tile_h = NT / a.tile_w;
@@ -617,7 +617,7 @@ __device__ __forceinline__ void fwd_ws_tile(const MfmaArgs& a, const int tile) {
 
 template <int DP, int NT>
 __global__ __launch_bounds__(2 * NT) void composite_fwd_ws_kernel(MfmaArgs a) {
-  fwd_ws_tile<DP, NT>(a, (int)blockIdx.x);
+  fwd_ws_tile<DP, NT>(a, xcd_tile((int)blockIdx.x, (int)gridDim.x));
 }
 
 // Persistent form over many frames: each workgroup takes (frame, tile) items

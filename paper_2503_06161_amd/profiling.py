@@ -67,18 +67,19 @@ def counters(roots):
     return {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in acc.items()}
 
 
-def copy_scale(cnt):
-    """Bytes per FETCH_SIZE / WRITE_SIZE unit from the calibration copy
-    (the one kernel whose name holds 'copy' or 'elementwise')."""
-    for k, d in cnt.items():
-        if re.search(r"copy|elementwise", k, re.I) and "FETCH_SIZE" in d and "WRITE_SIZE" in d:
-            return COPY_BYTES / (d["FETCH_SIZE"] * 1024.0), COPY_BYTES / (d["WRITE_SIZE"] * 1024.0)
-    for k, d in cnt.items():
-        if re.search(r"copy|elementwise", k, re.I):
-            f = COPY_BYTES / (d["FETCH_SIZE"] * 1024.0) if "FETCH_SIZE" in d else None
-            w = COPY_BYTES / (d["WRITE_SIZE"] * 1024.0) if "WRITE_SIZE" in d else None
-            return f, w
-    return None, None
+def copy_scale(roots):
+    """Bytes per FETCH_SIZE / WRITE_SIZE unit, from the calibration copy: the
+    copy dispatch with the largest count in each run is the 256 MiB
+    device-to-device copy of ``bench.py --calibrate-copy``."""
+    best = {}
+    for root in roots:
+        for r in _csv_rows(root, "counter_collection.csv"):
+            if re.search(r"copy|elementwise", r["Kernel_Name"], re.I) and r["Counter_Name"] in ("FETCH_SIZE", "WRITE_SIZE"):
+                v = float(r["Counter_Value"])
+                best[r["Counter_Name"]] = max(best.get(r["Counter_Name"], 0.0), v)
+    f = COPY_BYTES / best["FETCH_SIZE"] if best.get("FETCH_SIZE") else None
+    w = COPY_BYTES / best["WRITE_SIZE"] if best.get("WRITE_SIZE") else None
+    return f, w
 
 
 def main(argv=None):
@@ -101,19 +102,19 @@ def main(argv=None):
                 print(f"| `{k}` | {n} | {us:.2f} | {grid} | {blk} | {lds} | {vg} | {ag} | {scr} |")
         return 0
     cnt = counters(a.dirs)
-    fs, ws = copy_scale(cnt)
+    fs, ws = copy_scale(a.dirs)
     if a.json:
         for k, d in cnt.items():
             if re.search(a.json, k):
-                rd = d.get("FETCH_SIZE", 0.0) * 1024.0 * (fs or 0.0)
-                wr = d.get("WRITE_SIZE", 0.0) * 1024.0 * (ws or 0.0)
+                rd = d.get("FETCH_SIZE", 0.0) * (fs or 0.0)
+                wr = d.get("WRITE_SIZE", 0.0) * (ws or 0.0)
                 print(json.dumps({"kernel": k, "read_bytes": round(rd), "write_bytes": round(wr),
                                   "bytes_per_launch": round(rd + wr), "fetch_scale": fs, "write_scale": ws}))
                 return 0
         return 1
     names = sorted({c for d in cnt.values() for c in d})
-    print(f"copy calibration: bytes per FETCH_SIZE KiB = {fs and fs * 1024:.1f}, per WRITE_SIZE KiB = "
-          f"{ws and ws * 1024:.1f}" if fs or ws else "no calibration copy in these runs")
+    print(f"copy calibration: bytes per FETCH_SIZE unit = {fs:.1f}, per WRITE_SIZE unit = {ws:.1f}"
+          if fs and ws else "no calibration copy in these runs")
     print()
     print("| kernel | " + " | ".join(names) + " |")
     print("|---|" + "---:|" * len(names))
