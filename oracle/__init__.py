@@ -10,7 +10,8 @@ Every function follows the paper's definitions in plain PyTorch CPU float64:
 * eq. (2)  Sigma = R S S^T R^T;
 * eq. (9)  Sigma' = J W Sigma W^T J^T (affine approximation of projection);
 * eqs. (7)-(8) front-to-back blending of colour and semantic features with
-  the same weights alpha_i prod_{j<i} (1 - alpha_j).
+  the same weights alpha_i prod_{j<i} (1 - alpha_j);
+* eq. (10) the pointwise-convolution decoder and its per-pixel L1 loss.
 The discrete rules the paper leaves open (tile binning, alpha clamp, skip and
 stop thresholds, SH convention, pixel centres) are the readings listed in the
 design notes; each is restated where it is used.
@@ -24,7 +25,8 @@ from .project import project, OracleCamera, OracleConfig
 from .raster import (bin_gaussians, composite, render_forward, brute_force_render,
                      TileLists)
 from .grad import render_backward, fd_gradient
+from .decoder import decoder_l1
 
 __all__ = ["sh_basis", "sh_coeff_count", "project", "OracleCamera", "OracleConfig",
            "bin_gaussians", "composite", "render_forward", "brute_force_render",
-           "TileLists", "render_backward", "fd_gradient"]
+           "TileLists", "render_backward", "fd_gradient", "decoder_l1"]

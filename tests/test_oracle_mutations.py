@@ -60,6 +60,10 @@ MUTATIONS = [
      "SH normalisation of m > 0"),
     ("sh.py", "row[l - m] = math.sqrt(2.0) * k * pz * im[m]", "row[l - m] = math.sqrt(2.0) * k * pz * re[m]",
      "SH sine term replaced by the cosine term"),
+    ("decoder.py", "loss = r.abs().sum() / P", "loss = r.abs().sum() / (P * C)", "loss averaged over channels too"),
+    ("decoder.py", "d_feat=(Wt.T @ s)", "d_feat=(Wt.T @ (r / P))", "L2 gradient instead of the L1 subgradient"),
+    ("decoder.py", "dec = Wt @ zf + b[:, None]", "dec = Wt @ zf", "decoder bias dropped"),
+    ("decoder.py", "d_weight=(s @ zf.T)", "d_weight=(s @ zf.T).T.T * 0.5", "weight gradient halved"),
 ]
 
 
