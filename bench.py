@@ -13,7 +13,8 @@ the FP64 oracle (at the stored BF16 values and at the FP32 originals).
 
 Also reported (untimed by the headline): a sweep of the feature width
 (16..256), the 1280x1024 frame with 1M Gaussians, the 100k-Gaussian FP32
-frame, 16 timestamps as one graph replay and as 16 separate calls, and the
+frame, 16 timestamps as one graph replay and as 16 separate calls, the
+fused semantic decoder + L1 feature loss on the frame's feature map, and the
 bandwidth of a plain device copy.
 
 Prints one JSON line.  Stage durations come from HIP events that the library
@@ -60,6 +61,7 @@ def _parse():
     ap.add_argument("--no-accuracy", action="store_true", help="skip the FP64-oracle accuracy block")
     ap.add_argument("--no-sweep", action="store_true", help="skip the feature-width sweep")
     ap.add_argument("--no-configs", action="store_true", help="skip the large and mid frames")
+    ap.add_argument("--no-decoder", action="store_true", help="skip the semantic decoder + feature loss")
     return ap.parse_args()
 
 
@@ -396,6 +398,48 @@ def other_configs(steps, warmup):
     return res
 
 
+def decoder_frame(steps, warmup):
+    """The semantic decoder + L1 feature loss on the metric frame's feature
+    map (640x512, D=128 -> 256 channels), float32 and bfloat16 targets: one
+    fe_decoder_l1 call (loss, d_feat, d_weight, d_bias; no decoded map)
+    timed with HIP events on its stream.  Algorithmic bytes: z read, target
+    read, d_feat written; algorithmic flops: the three products W z, W^T s,
+    s z^T (2 C D P each)."""
+    import torch
+    from paper_2503_06161_amd import rast
+    from paper_2503_06161_amd.scenes import decoder_inputs
+    D, H, W, C_ = 128, 512, 640, rast.DECODER_CHANNELS
+    P = H * W
+    out = {}
+    for tdt in ("f32", "bf16"):
+        z, w, b, t = decoder_inputs(31, D, H, W, target_dtype=tdt)
+        zt, wt, bt = (torch.from_numpy(a).cuda() for a in (z, w, b))
+        tt = torch.from_numpy(t).cuda()
+        if tdt == "bf16":
+            tt = tt.to(torch.bfloat16)
+        ws = torch.empty(rast.decoder_workspace_bytes(D, P), dtype=torch.uint8, device="cuda")
+        for _ in range(warmup):
+            rast.decoder_l1(zt, wt, bt, tt, workspace=ws)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            rast.decoder_l1(zt, wt, bt, tt, workspace=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        eb = 4 if tdt == "f32" else 2
+        by = P * (D * 4 + C_ * eb + D * 4)
+        fl = 3 * 2 * C_ * D * P
+        out[tdt] = {"ms": round(ms, 4), "algorithmic_bytes": by, "algorithmic_flops": fl,
+                    "hbm_gb_s": round(by / (ms * 1e-3) / 1e9, 1),
+                    "hbm_frac": round(by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    "tflop_s": round(fl / (ms * 1e-3) / 1e12, 2),
+                    "mfma_issued_tflop_s": round(7 / 3 * fl / (ms * 1e-3) / 1e12, 2)}
+    return {"workload": "640x512 feature map, D=128 -> 256 channels, 1x1 convolution + L1 loss and all gradients",
+            "results": out}
+
+
 def copy_bandwidth():
     """Achievable HBM bandwidth: a plain 256 MiB device-to-device copy
     (read + write bytes over its event-timed duration, best of 10)."""
@@ -516,6 +560,9 @@ def main():
     if not args.no_configs:
         _log("large and mid frames")
         line["other_configs"] = other_configs(max(5, args.steps // 2), 2)
+    if not args.no_decoder:
+        _log("semantic decoder + feature loss")
+        line["decoder_l1"] = decoder_frame(max(5, args.steps), 3)
     if not args.no_batched:
         _log("16 timestamps")
         try:

@@ -57,7 +57,7 @@
 extern "C" {
 #endif
 
-#define FE4DGS_ABI_VERSION 4
+#define FE4DGS_ABI_VERSION 5
 
 typedef enum fe_status {
   FE_OK = 0,
@@ -265,6 +265,43 @@ fe_status fe_render_backward_noalloc(const fe_config* cfg, const fe_camera* cam,
                                      const fe_images* fwd, const void* state, size_t state_bytes,
                                      const float* d_rgb, const float* d_feat, const float* d_depth,
                                      const fe_grads* out, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Semantic decoder and feature loss (Sec. 3.3, eq. 10), fused: the rendered
+ * feature map z [in_dim][pixels] (planar float32, as fe_render_forward writes
+ * it) goes through the pointwise convolution z' = W z + b (W [256][in_dim]
+ * row-major, b [256]) and is compared with the target map t [256][pixels] by
+ * L = (1 / pixels) sum_x |z'(x) - t(x)|_1 (the target at the render
+ * resolution).  One call returns L and its gradients, with
+ * s = sign(z' - t) (sign(0) = 0): d_feat = W^T s / pixels (ready to be the
+ * backward's d_feat), d_weight = s z^T / pixels, d_bias = sum_x s / pixels;
+ * `decoded` (optional) receives z'.  Products are taken from bf16 parts of
+ * the float32 operands (about 16 significant bits per product), sums in
+ * float32.  in_dim is 32, 64 or 128 (else FE_ERR_UNSUPPORTED); target_dtype
+ * FE_F32 or FE_BF16; 1 <= pixels <= 2^26; weight 16-byte aligned (else
+ * FE_ERR_INVALID_ARG).  All pointers are device memory; d_feat and decoded may
+ * be NULL; no output may overlap an input.  Launches asynchronously on
+ * `stream`; results are ready when the stream reaches the end of the call.  The workspace (256-byte aligned, >= fe_decoder_workspace_bytes;
+ * 0 for unsupported sizes) holds one partial gradient per workgroup and the
+ * residual signs (2 bits per output value).
+ * ---------------------------------------------------------------------- */
+typedef struct fe_decoder {
+  int32_t in_dim;                /* D of the feature map                        */
+  int32_t target_dtype;          /* fe_dtype of `target`                        */
+  int64_t pixels;                /* H * W >= 1                                  */
+  const float* feat;             /* [in_dim][pixels]                            */
+  const float* weight;           /* [256][in_dim]                               */
+  const float* bias;             /* [256]                                       */
+  const void* target;            /* [256][pixels]                               */
+  float* loss;                   /* [1]                                         */
+  float* d_feat;                 /* [in_dim][pixels] or NULL                    */
+  float* d_weight;               /* [256][in_dim]                               */
+  float* d_bias;                 /* [256]                                       */
+  float* decoded;                /* [256][pixels] or NULL                       */
+} fe_decoder;
+
+size_t    fe_decoder_workspace_bytes(int32_t in_dim, int64_t pixels);
+fe_status fe_decoder_l1(const fe_decoder* d, void* workspace, size_t workspace_bytes, void* stream);
 
 /* Copy the device report of `state` to the host.  Synchronises `stream`.
  * Returns report->status as the call's status (FE_ERR_KEY_OVERFLOW when the

@@ -379,6 +379,41 @@ fe_status fe_render_backward(const fe_config* cfg, const fe_camera* cam, const f
                        static_cast<hipStream_t>(stream));
 }
 
+// one partial (dW, db, loss) per workgroup of the persistent decoder grid,
+// then the sign masks (2 bits per output value)
+static size_t decoder_partial_bytes(int32_t in_dim, int target_dtype) {
+  const int grid = decoder_grid_size(in_dim, target_dtype);
+  return grid < 1 ? 0 : align256((size_t)grid * decoder_partial_floats(in_dim) * sizeof(float));
+}
+
+size_t fe_decoder_workspace_bytes(int32_t in_dim, int64_t pixels) {
+  if ((in_dim != 32 && in_dim != 64 && in_dim != 128) || pixels < 1) return 0;
+  const size_t a = decoder_partial_bytes(in_dim, FE_F32), b = decoder_partial_bytes(in_dim, FE_BF16);
+  if (!a || !b) return 0;
+  return (a > b ? a : b) + decoder_sign_bytes(pixels);
+}
+
+fe_status fe_decoder_l1(const fe_decoder* d, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!d || !workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return FE_ERR_INVALID_ARG;
+  if (d->in_dim != 32 && d->in_dim != 64 && d->in_dim != 128) return FE_ERR_UNSUPPORTED;
+  if (d->target_dtype != FE_F32 && d->target_dtype != FE_BF16) return FE_ERR_INVALID_ARG;
+  if (d->pixels < 1 || d->pixels > ((int64_t)1 << 26)) return FE_ERR_INVALID_ARG;
+  if (!d->feat || !d->weight || !d->bias || !d->target || !d->loss || !d->d_weight || !d->d_bias)
+    return FE_ERR_INVALID_ARG;
+  if (reinterpret_cast<uintptr_t>(d->weight) % 16 != 0) return FE_ERR_INVALID_ARG;
+  int grid = decoder_grid_size(d->in_dim, d->target_dtype);
+  if (grid < 1) return FE_ERR_HIP;
+  // at least 16 pixel blocks per workgroup, so that small maps do not pay
+  // for a full grid of partial gradients
+  const int64_t blocks = (d->pixels + 31) / 32, need = (blocks + 15) / 16;
+  if (need < grid) grid = (int)need;
+  const size_t part = decoder_partial_bytes(d->in_dim, d->target_dtype);
+  if (workspace_bytes < part + decoder_sign_bytes(d->pixels)) return FE_ERR_WORKSPACE_TOO_SMALL;
+  char* ws = static_cast<char*>(workspace);
+  return hip_status(launch_decoder_l1(d, grid, reinterpret_cast<float*>(ws), ws + part,
+                                      static_cast<hipStream_t>(stream)));
+}
+
 fe_status fe_read_report(const void* state, size_t state_bytes, fe_report* out, void* stream) {
   if (!state || !out || state_bytes < sizeof(unsigned long long) * kRepWords) return FE_ERR_INVALID_ARG;
   unsigned long long w[kRepWords];

@@ -192,6 +192,12 @@ int composite_bwd_persistent_grid(const fe_config* cfg);
 hipError_t launch_composite_bwd_persistent(const fe_config* cfg, const void* records, const TileQueue& q,
                                            int grid, hipStream_t s);
 
+// ---- semantic decoder + feature loss ----
+int decoder_grid_size(int in_dim, int target_dtype);
+size_t decoder_partial_floats(int in_dim);
+size_t decoder_sign_bytes(int64_t pixels);
+hipError_t launch_decoder_l1(const fe_decoder* d, int grid, float* partial, void* signs, hipStream_t s);
+
 // ---- small device helpers ----
 // Workgroups of a launch are handed to the eight XCDs in turn (workgroup b
 // runs on XCD b % 8), and each XCD has its own L2.  Tiles are dealt to the

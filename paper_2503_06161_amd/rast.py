@@ -68,6 +68,12 @@ class fe_report(C.Structure):
                 ("n_visible", C.c_int64), ("n_culled_nonfinite", C.c_int64), ("rows_needed", C.c_int64)]
 
 
+class fe_decoder(C.Structure):
+    _fields_ = [("in_dim", C.c_int32), ("target_dtype", C.c_int32), ("pixels", C.c_int64), ("feat", C.c_void_p),
+                ("weight", C.c_void_p), ("bias", C.c_void_p), ("target", C.c_void_p), ("loss", C.c_void_p),
+                ("d_feat", C.c_void_p), ("d_weight", C.c_void_p), ("d_bias", C.c_void_p), ("decoded", C.c_void_p)]
+
+
 class fe_state_layout(C.Structure):
     _fields_ = [(k, C.c_size_t) for k in ("total", "xy", "conic_opacity", "rgb", "box", "depth_key",
                                           "tile_count", "sorted_gauss", "ranges", "report")]
@@ -99,6 +105,8 @@ EXPORTS = {
     "fe_batch_launch": (C.c_int, [C.c_void_p, C.c_void_p]),
     "fe_batch_read_report": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(fe_report), C.c_void_p]),
     "fe_batch_plan_destroy": (None, [C.c_void_p]),
+    "fe_decoder_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int64]),
+    "fe_decoder_l1": (C.c_int, [C.POINTER(fe_decoder), C.c_void_p, C.c_size_t, C.c_void_p]),
 }
 
 _lib = None
@@ -116,7 +124,7 @@ def load_library(path: str = LIB_PATH):
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
-    if lib.fe_abi_version() != 4:
+    if lib.fe_abi_version() != 5:
         raise ImportError("libfe4dgs_rast.so ABI version mismatch")
     _lib = lib
     return lib
@@ -421,3 +429,74 @@ class RasterizeFE(torch.autograd.Function):
 def rasterize(means, scales, quats, opacity, sh, feat, cam, st: Settings):
     """Differentiable render; returns (rgb, feat, depth, final_T, n_contrib)."""
     return RasterizeFE.apply(means, scales, quats, opacity, sh, feat, cam, st)
+
+
+# ---------------------------------------------------------------------------
+# Semantic decoder + L1 feature loss (Sec. 3.3, eq. 10)
+
+DECODER_CHANNELS = 256
+
+
+def decoder_workspace_bytes(in_dim: int, pixels: int) -> int:
+    return int(load_library().fe_decoder_workspace_bytes(int(in_dim), int(pixels)))
+
+
+def decoder_l1(feat, weight, bias, target, d_feat: bool = True, decoded: bool = False, workspace=None,
+               stream=None) -> dict:
+    """fe_decoder_l1: feat [D,H,W] float32, weight [256,D] float32, bias
+    [256] float32, target [256,H,W] float32 or bfloat16 (all on the GPU).
+    Returns loss [1] and d_weight [256,D], d_bias [256], plus d_feat [D,H,W]
+    and decoded [256,H,W] when asked for (float32 tensors)."""
+    lib = load_library()
+    if feat.dim() != 3:
+        raise ValueError("feat must be [D, H, W]")
+    D, H, W = feat.shape
+    _req(feat, torch.float32, (D, H, W), "feat")
+    _req(weight, torch.float32, (DECODER_CHANNELS, D), "weight")
+    _req(bias, torch.float32, (DECODER_CHANNELS,), "bias")
+    if target.dtype not in (torch.float32, torch.bfloat16):
+        raise ValueError("target must be float32 or bfloat16")
+    _req(target, target.dtype, (DECODER_CHANNELS, H, W), "target")
+    dev = feat.device
+    out = dict(loss=torch.empty(1, device=dev), d_weight=torch.empty(DECODER_CHANNELS, D, device=dev),
+               d_bias=torch.empty(DECODER_CHANNELS, device=dev))
+    if d_feat:
+        out["d_feat"] = torch.empty(D, H, W, device=dev)
+    if decoded:
+        out["decoded"] = torch.empty(DECODER_CHANNELS, H, W, device=dev)
+    need = decoder_workspace_bytes(D, H * W)
+    if need == 0:
+        raise RasterError(FE_ERR_UNSUPPORTED, "fe_decoder_workspace_bytes")
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    d = fe_decoder(D, FE_BF16 if target.dtype == torch.bfloat16 else FE_F32, H * W, feat.data_ptr(),
+                   weight.data_ptr(), bias.data_ptr(), target.data_ptr(), out["loss"].data_ptr(),
+                   _ptr(out.get("d_feat")), out["d_weight"].data_ptr(), out["d_bias"].data_ptr(),
+                   _ptr(out.get("decoded")))
+    _check(lib.fe_decoder_l1(C.byref(d), C.c_void_p(workspace.data_ptr()), workspace.numel(),
+                             C.c_void_p(_stream_handle(stream))), "fe_decoder_l1")
+    return out
+
+
+class DecoderL1(torch.autograd.Function):
+    """L_feat(feat, weight, bias; target) as a differentiable scalar: the
+    fused call computes the loss and its gradients together; backward scales
+    them by the incoming gradient."""
+
+    @staticmethod
+    def forward(ctx, feat, weight, bias, target):
+        r = decoder_l1(feat.contiguous().float(), weight.contiguous().float(), bias.contiguous().float(),
+                       target.contiguous())
+        ctx.save_for_backward(r["d_feat"], r["d_weight"], r["d_bias"])
+        ctx.dtypes = (feat.dtype, weight.dtype, bias.dtype)
+        return r["loss"][0]
+
+    @staticmethod
+    def backward(ctx, g):
+        df, dw, db = ctx.saved_tensors
+        return (df * g).to(ctx.dtypes[0]), (dw * g).to(ctx.dtypes[1]), (db * g).to(ctx.dtypes[2]), None
+
+
+def decoder_loss(feat, weight, bias, target):
+    """Differentiable L_feat of a rendered feature map (eq. 10)."""
+    return DecoderL1.apply(feat, weight, bias, target)

@@ -181,3 +181,23 @@ def batched_frames(seed: int = 4, n_frames: int = 16, pool: int = 200_000, base:
         m = sc.means[:nk].astype(np.float64) + amp * np.sin(2 * np.pi * t + phase[:nk])
         frames.append(dict(t=t, n=nk, means=m.astype(np.float32)))
     return sc, frames
+
+
+def decoder_inputs(seed: int, feat_dim: int, height: int, width: int, channels: int = 256,
+                   target_dtype: str = "f32"):
+    """Inputs of the semantic decoder and feature loss (Sec. 3.3, eq. 10):
+    a rendered feature map z [D,H,W] ~ N(0, 0.5), the 1x1-convolution weight
+    W [C,D] ~ N(0, 1/D) (fan-in scaled) and bias b [C] ~ N(0, 0.1), and a
+    stand-in for the segmentation model's feature map t [C,H,W] ~ N(0, 0.5),
+    already at the render resolution (the model and its images are not
+    available).  Drawn in that order in float64, cast to float32; with
+    ``target_dtype="bf16"`` the target is rounded to bfloat16 (returned as
+    float32 values that bfloat16 holds exactly)."""
+    rng = np.random.default_rng(seed)
+    z = rng.normal(0.0, 0.5, (feat_dim, height, width)).astype(np.float32)
+    w = (rng.normal(0.0, 1.0, (channels, feat_dim)) / np.sqrt(feat_dim)).astype(np.float32)
+    b = rng.normal(0.0, 0.1, channels).astype(np.float32)
+    t = rng.normal(0.0, 0.5, (channels, height, width)).astype(np.float32)
+    if target_dtype == "bf16":
+        t = bf16_round(t)
+    return z, w, b, t
