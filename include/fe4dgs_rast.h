@@ -278,7 +278,7 @@ fe_status fe_render_backward_noalloc(const fe_config* cfg, const fe_camera* cam,
  * `decoded` (optional) receives z'.  Products are taken from bf16 parts of
  * the float32 operands (about 16 significant bits per product), sums in
  * float32.  in_dim is 32, 64 or 128 (else FE_ERR_UNSUPPORTED); target_dtype
- * FE_F32 or FE_BF16; 1 <= pixels <= 2^26; weight 16-byte aligned (else
+ * FE_F32 or FE_BF16; 1 <= pixels <= 2^24; weight 16-byte aligned (else
  * FE_ERR_INVALID_ARG).  All pointers are device memory; d_feat and decoded may
  * be NULL; no output may overlap an input.  Launches asynchronously on
  * `stream`; results are ready when the stream reaches the end of the call.  The workspace (256-byte aligned, >= fe_decoder_workspace_bytes;

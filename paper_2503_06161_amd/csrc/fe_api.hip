@@ -397,7 +397,7 @@ fe_status fe_decoder_l1(const fe_decoder* d, void* workspace, size_t workspace_b
   if (!d || !workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return FE_ERR_INVALID_ARG;
   if (d->in_dim != 32 && d->in_dim != 64 && d->in_dim != 128) return FE_ERR_UNSUPPORTED;
   if (d->target_dtype != FE_F32 && d->target_dtype != FE_BF16) return FE_ERR_INVALID_ARG;
-  if (d->pixels < 1 || d->pixels > ((int64_t)1 << 26)) return FE_ERR_INVALID_ARG;
+  if (d->pixels < 1 || d->pixels > ((int64_t)1 << 24)) return FE_ERR_INVALID_ARG;
   if (!d->feat || !d->weight || !d->bias || !d->target || !d->loss || !d->d_weight || !d->d_bias)
     return FE_ERR_INVALID_ARG;
   if (reinterpret_cast<uintptr_t>(d->weight) % 16 != 0) return FE_ERR_INVALID_ARG;
