@@ -11,7 +11,9 @@ Every function follows the paper's definitions in plain PyTorch CPU float64:
 * eq. (9)  Sigma' = J W Sigma W^T J^T (affine approximation of projection);
 * eqs. (7)-(8) front-to-back blending of colour and semantic features with
   the same weights alpha_i prod_{j<i} (1 - alpha_j);
-* eq. (10) the pointwise-convolution decoder and its per-pixel L1 loss.
+* eq. (10) the pointwise-convolution decoder and its per-pixel L1 loss;
+* eqs. (4)-(6) the FST deformation module (HexPlane, F_out, the four
+  branches and the semantic updater) that produces G_t.
 The discrete rules the paper leaves open (tile binning, alpha clamp, skip and
 stop thresholds, SH convention, pixel centres) are the readings listed in the
 design notes; each is restated where it is used.
@@ -26,7 +28,9 @@ from .raster import (bin_gaussians, composite, render_forward, brute_force_rende
                      TileLists)
 from .grad import render_backward, fd_gradient
 from .decoder import decoder_l1
+from .deform import deform_gaussians, hexplane_features, deform_mlp
 
 __all__ = ["sh_basis", "sh_coeff_count", "project", "OracleCamera", "OracleConfig",
            "bin_gaussians", "composite", "render_forward", "brute_force_render",
-           "TileLists", "render_backward", "fd_gradient", "decoder_l1"]
+           "TileLists", "render_backward", "fd_gradient", "decoder_l1", "deform_gaussians", "hexplane_features",
+           "deform_mlp"]

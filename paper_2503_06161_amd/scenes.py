@@ -201,3 +201,62 @@ def decoder_inputs(seed: int, feat_dim: int, height: int, width: int, channels: 
     if target_dtype == "bf16":
         t = bf16_round(t)
     return z, w, b, t
+
+
+DEFORM_PAIRS = ((0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3))
+
+
+def deform_inputs(seed: int, n: int, channels: int = 32, width: int = 64, feat_dim: int = 128,
+                  base_res=(64, 64, 64, 100), levels=(1, 2, 4, 8), xy: float = 1.0, z=(2.0, 6.0),
+                  logs=(-3.5, 0.4)):
+    """Inputs of the FST deformation module (Sec. 3.2, eqs. 4-6) with
+    synthetic weights (trained ones are not available):
+
+    * canonical Gaussians in the optimiser's parameters: means uniform in
+      [-xy, xy]^2 x z, log-scales ~ N(logs), quaternions normalised N(0, I4),
+      opacity logits ~ N(0, 1), features [n, feat_dim] ~ N(0, 1);
+    * the box [lo, hi] of the means;
+    * HexPlane grids: for each level multiplier m and coordinate pair (a, b)
+      of (x, y, z, t) in DEFORM_PAIRS order, a [res_b, res_a, channels]
+      array (res = base_res[k] m for space, base_res[3] for time), space-only
+      planes ~ U(0.1, 0.5), planes with time ~ U(0.5, 1.5);
+    * affine layers (weight [out, in], bias [out]) ~ U(-1/sqrt(in),
+      1/sqrt(in)): 'out' (4 channels -> width, then 7 x width -> width),
+      'branch_<g>' (width -> width -> width/2), 'head_<g>' (width/2 -> d_g,
+      d = 3, 4, 3, 1 for mu, rot, scale, opacity), 'sem' (2 width -> width
+      -> feat_dim).
+    Drawn in that order in float64 and cast to float32."""
+    rng = np.random.default_rng(seed)
+    f32 = lambda a: np.asarray(a, dtype=np.float32)
+    means = np.empty((n, 3))
+    means[:, 0] = rng.uniform(-xy, xy, n)
+    means[:, 1] = rng.uniform(-xy, xy, n)
+    means[:, 2] = rng.uniform(z[0], z[1], n)
+    log_s = rng.normal(logs[0], logs[1], (n, 3))
+    q = rng.normal(0.0, 1.0, (n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    op_logit = rng.normal(0.0, 1.0, n)
+    feat = rng.normal(0.0, 1.0, (n, feat_dim))
+    lo = np.array([-xy, -xy, z[0]])
+    hi = np.array([xy, xy, z[1]])
+    planes = []
+    for m in levels:
+        res = [base_res[k] * m for k in range(3)] + [base_res[3]]
+        lvl = []
+        for a, b in DEFORM_PAIRS:
+            lo_v, hi_v = (0.5, 1.5) if b == 3 else (0.1, 0.5)
+            lvl.append(f32(rng.uniform(lo_v, hi_v, (res[b], res[a], channels))))
+        planes.append(lvl)
+
+    def affine(n_in, n_out):
+        k = 1.0 / np.sqrt(n_in)
+        return f32(rng.uniform(-k, k, (n_out, n_in))), f32(rng.uniform(-k, k, n_out))
+
+    layers = {"out": [affine(4 * channels, width)] + [affine(width, width) for _ in range(7)]}
+    for g, d in (("mu", 3), ("rot", 4), ("scale", 3), ("opacity", 1)):
+        layers["branch_" + g] = (affine(width, width), affine(width, width // 2))
+        layers["head_" + g] = affine(width // 2, d)
+    layers["sem"] = (affine(2 * width, width), affine(width, feat_dim))
+    return dict(means=f32(means), log_scales=f32(log_s), quats=f32(q), logit_opacity=f32(op_logit), feat=f32(feat),
+                lo=f32(lo), hi=f32(hi), planes=planes, layers=layers, channels=channels, width=width,
+                feat_dim=feat_dim, base_res=tuple(base_res), levels=tuple(levels))

@@ -64,6 +64,20 @@ MUTATIONS = [
     ("decoder.py", "d_feat=(Wt.T @ s)", "d_feat=(Wt.T @ (r / P))", "L2 gradient instead of the L1 subgradient"),
     ("decoder.py", "dec = Wt @ zf + b[:, None]", "dec = Wt @ zf", "decoder bias dropped"),
     ("decoder.py", "d_weight=(s @ zf.T)", "d_weight=(s @ zf.T).T.T * 0.5", "weight gradient halved"),
+    ("deform.py", "PLANE_PAIRS = ((0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3))",
+     "PLANE_PAIRS = ((0, 1), (0, 3), (0, 2), (1, 2), (1, 3), (2, 3))", "HexPlane pairs out of order"),
+    ("deform.py", "wx * (1 - wy) * g[y0, x0 + 1]", "wx * (1 - wy) * g[y0 + 1, x0]", "bilinear taps transposed"),
+    ("deform.py", "x = (ua + 1.0) / 2.0 * (ra - 1)", "x = (ua + 1.0) / 2.0 * ra", "grid end points off the box"),
+    ("deform.py", "2.0 * float(t) - 1.0", "float(t)", "time not mapped to [-1, 1]"),
+    ("deform.py", "prod = s if prod is None else prod * s", "prod = s if prod is None else prod + s",
+     "planes summed instead of multiplied"),
+    ("deform.py", "return base[coord] * level_mult if coord < 3 else base[coord]", "return base[coord] * level_mult",
+     "time resolution refined with the levels"),
+    ("deform.py", "x = _affine(x if i == 0 else torch.relu(x), layer)", "x = _affine(x, layer)",
+     "no ReLU between the decoder layers"),
+    ("deform.py", "u_all = torch.cat(hg, 1)", "u_all = torch.cat(hg[::-1], 1)", "branch features concatenated reversed"),
+    ("deform.py", "opacity=torch.sigmoid(T(logit_opacity) + r[\"d_opacity\"][:, 0])",
+     "opacity=torch.sigmoid(T(logit_opacity)) + r[\"d_opacity\"][:, 0]", "opacity update after the activation"),
 ]
 
 
