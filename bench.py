@@ -14,8 +14,9 @@ the FP64 oracle (at the stored BF16 values and at the FP32 originals).
 Also reported (untimed by the headline): a sweep of the feature width
 (16..256), the 1280x1024 frame with 1M Gaussians, the 100k-Gaussian FP32
 frame, 16 timestamps as one graph replay and as 16 separate calls, the
-fused semantic decoder + L1 feature loss on the frame's feature map, and the
-bandwidth of a plain device copy.
+fused semantic decoder + L1 feature loss on the frame's feature map, the FST
+deformation module on the frame's Gaussian count, and the bandwidth of a
+plain device copy.
 
 Prints one JSON line.  Stage durations come from HIP events that the library
 records on the stream around each stage.
@@ -62,6 +63,7 @@ def _parse():
     ap.add_argument("--no-sweep", action="store_true", help="skip the feature-width sweep")
     ap.add_argument("--no-configs", action="store_true", help="skip the large and mid frames")
     ap.add_argument("--no-decoder", action="store_true", help="skip the semantic decoder + feature loss")
+    ap.add_argument("--no-deform", action="store_true", help="skip the FST deformation module")
     return ap.parse_args()
 
 
@@ -440,6 +442,47 @@ def decoder_frame(steps, warmup):
             "results": out}
 
 
+def deform_frame(steps, warmup, n=300_000):
+    """The FST deformation module on the metric frame's Gaussian count:
+    n canonical Gaussians -> G_t (HexPlane widths 32 and 64 at the paper's
+    grid sizes, W = 64, 128 feature channels, float32 output), one
+    fe_deform_forward call timed with HIP events on its stream.  Algorithmic
+    bytes: the Gaussians read and written (means, quaternion, log-scales,
+    opacity logit, 128 features; the HexPlane taps and the weights are cache
+    traffic); algorithmic flops: 2 x the multiply-adds of the 22 affine
+    layers."""
+    import numpy as np
+    import torch
+    from paper_2503_06161_amd import rast
+    from paper_2503_06161_amd.scenes import deform_inputs
+    res = {}
+    for C in (32, 64):
+        d = deform_inputs(5, n, channels=C)
+        net = rast.DeformNet(d["planes"], d["layers"], d["lo"], d["hi"], C, 64, 128)
+        T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        args = [T(d[k]) for k in ("means", "quats", "log_scales", "logit_opacity", "feat")]
+        out = rast.deform_forward(net, *args, 0.3)
+        for _ in range(warmup):
+            rast.deform_forward(net, *args, 0.3, out=out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            rast.deform_forward(net, *args, 0.3, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        per_g_bytes = 2 * (3 + 4 + 3 + 1 + 128) * 4
+        macs = 4 * C * 64 + 7 * 64 * 64 + 4 * (64 * 64 + 64 * 32) + 32 * (3 + 4 + 3 + 1) + 128 * 64 + 64 * 128
+        by, fl = n * per_g_bytes, 2 * n * macs
+        res[f"C{C}"] = {"ms": round(ms, 4), "gaussians_per_s": round(n / (ms * 1e-3), 1),
+                        "algorithmic_bytes": by, "hbm_gb_s": round(by / (ms * 1e-3) / 1e9, 1),
+                        "algorithmic_flops": fl, "tflop_s": round(fl / (ms * 1e-3) / 1e12, 2)}
+        del net, args, out
+    return {"workload": f"{n} canonical Gaussians at t = 0.3, HexPlane [64,64,64,100] x [1,2,4,8] with C channels, "
+                        "F_out W=64 depth 8, four branches, semantic updater to 128 channels", "results": res}
+
+
 def copy_bandwidth():
     """Achievable HBM bandwidth: a plain 256 MiB device-to-device copy
     (read + write bytes over its event-timed duration, best of 10)."""
@@ -563,6 +606,9 @@ def main():
     if not args.no_decoder:
         _log("semantic decoder + feature loss")
         line["decoder_l1"] = decoder_frame(max(5, args.steps), 3)
+    if not args.no_deform:
+        _log("FST deformation")
+        line["deform"] = deform_frame(max(5, args.steps // 2), 2)
     if not args.no_batched:
         _log("16 timestamps")
         try:

@@ -57,7 +57,7 @@
 extern "C" {
 #endif
 
-#define FE4DGS_ABI_VERSION 5
+#define FE4DGS_ABI_VERSION 6
 
 typedef enum fe_status {
   FE_OK = 0,
@@ -302,6 +302,76 @@ typedef struct fe_decoder {
 
 size_t    fe_decoder_workspace_bytes(int32_t in_dim, int64_t pixels);
 fe_status fe_decoder_l1(const fe_decoder* d, void* workspace, size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * FST deformation module (Sec. 3.2, eqs. 4-6; appendix "FST Deformation
+ * Module"): G_t from the canonical Gaussians at time t, as the rasterizer's
+ * input.  Per Gaussian:
+ *   f  = HexPlane(mu, t): the coordinates (x, y, z, t) are mapped to [-1, 1]
+ *        (space by the box [lo, hi], time by 2t - 1) and clamped; for each of
+ *        the four levels the six coordinate-pair planes (x,y), (x,z), (x,t),
+ *        (y,z), (y,t), (z,t) are sampled bilinearly (grid end points on -1
+ *        and 1) and multiplied channel by channel; the levels' products are
+ *        concatenated (f has 4C entries);
+ *   h  = F_out(f): eight affine layers of width W, ReLU between them;
+ *   h_g = B2(relu(B1(relu(h)))) (W -> W -> W/2) and
+ *   dg = H(relu(h_g)) (W/2 -> d_g) for g = mu, rot, scale, opacity
+ *        (d = 3, 4, 3, 1);
+ *   dz = E2(relu(E1([h_mu | h_rot | h_scale | h_opacity]))) (2W -> W -> N);
+ *   G_t = (mu + dmu, q + dq, exp(log s + ds), sigmoid(logit o + do), z + dz).
+ * Grid points of coordinate k at level l: base_res[k] * level_mult[l] for
+ * space, base_res[3] for time.  HexPlane arithmetic in float32 (coordinates
+ * and interpolation weights in float64); the affine layers on the matrix
+ * cores from two-part bf16 splits of activations and weights (products of
+ * order <= 1, about 16 significant bits) with float32 accumulation.
+ * Supported: channels 32 or 64, width 64, feat_dim a multiple of 16 up to
+ * 256 (else FE_ERR_UNSUPPORTED).
+ * ---------------------------------------------------------------------- */
+typedef struct fe_deform_net {
+  int32_t channels;              /* C, channels of every HexPlane plane         */
+  int32_t width;                 /* W of F_out                                  */
+  int32_t feat_dim;              /* N, channels of the semantic update          */
+  int32_t base_res[4];           /* grid points of x, y, z, t at multiplier 1   */
+  int32_t level_mult[4];         /* spatial multipliers of the four levels      */
+  float lo[3];                   /* box of the spatial coordinates              */
+  float hi[3];                   /* (hi > lo on every axis)                     */
+  const float* planes;           /* device, fe_deform_plane_floats() floats:
+                                    level by level, pairs in the order above,
+                                    each plane [res_b][res_a][C]               */
+  const float* weights;          /* device, fe_deform_weight_floats() floats:
+                                    layers F_out 1..8, then per branch g (mu,
+                                    rot, scale, opacity) B1, B2, H, then E1, E2;
+                                    each layer weight [out][in] row-major, then
+                                    bias [out]                                 */
+} fe_deform_net;
+
+typedef struct fe_deform_io {
+  int64_t n;                     /* Gaussians, >= 0                             */
+  float t;                       /* time in [0, 1] (clamped)                    */
+  int32_t out_feat_dtype;        /* fe_dtype of out_feat                        */
+  const float* means;            /* [n][3]                                      */
+  const float* quats;            /* [n][4] (w, x, y, z)                         */
+  const float* log_scales;       /* [n][3]                                      */
+  const float* logit_opacity;    /* [n]                                         */
+  const float* feat;             /* [n][N] float32                              */
+  float* out_means;              /* [n][3]                                      */
+  float* out_quats;              /* [n][4], not normalised                      */
+  float* out_scales;             /* [n][3], linear                              */
+  float* out_opacity;            /* [n], in (0, 1)                              */
+  void* out_feat;                /* [n][N] of out_feat_dtype                    */
+} fe_deform_io;
+
+/* Sizes of the flat parameter arrays (host only; 0 if unsupported). */
+size_t fe_deform_plane_floats(const fe_deform_net* net);
+size_t fe_deform_weight_floats(const fe_deform_net* net);
+/* Workspace of fe_deform_forward: the weights split into bf16 parts. */
+size_t fe_deform_workspace_bytes(const fe_deform_net* net);
+
+/* G_t for io->n Gaussians at time io->t.  All arrays are device memory; the
+ * workspace (256-byte aligned) is overwritten; outputs must not overlap
+ * inputs.  Enqueued on `stream`. */
+fe_status fe_deform_forward(const fe_deform_net* net, const fe_deform_io* io, void* workspace,
+                            size_t workspace_bytes, void* stream);
 
 /* Copy the device report of `state` to the host.  Synchronises `stream`.
  * Returns report->status as the call's status (FE_ERR_KEY_OVERFLOW when the

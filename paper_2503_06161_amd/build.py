@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfe4dgs_rast.so")
 SOURCES = ["fe_api.hip", "fe_project.hip", "fe_sort.hip", "fe_composite.hip", "fe_composite_mfma.hip", "fe_backward_mfma.hip",
-           "fe_noalloc.hip", "fe_decoder.hip"]
+           "fe_noalloc.hip", "fe_decoder.hip", "fe_deform.hip"]
 ARCH = os.environ.get("FE4DGS_ARCH", "gfx950")
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

@@ -74,6 +74,19 @@ class fe_decoder(C.Structure):
                 ("d_feat", C.c_void_p), ("d_weight", C.c_void_p), ("d_bias", C.c_void_p), ("decoded", C.c_void_p)]
 
 
+class fe_deform_net(C.Structure):
+    _fields_ = [("channels", C.c_int32), ("width", C.c_int32), ("feat_dim", C.c_int32),
+                ("base_res", C.c_int32 * 4), ("level_mult", C.c_int32 * 4), ("lo", C.c_float * 3),
+                ("hi", C.c_float * 3), ("planes", C.c_void_p), ("weights", C.c_void_p)]
+
+
+class fe_deform_io(C.Structure):
+    _fields_ = [("n", C.c_int64), ("t", C.c_float), ("out_feat_dtype", C.c_int32), ("means", C.c_void_p),
+                ("quats", C.c_void_p), ("log_scales", C.c_void_p), ("logit_opacity", C.c_void_p),
+                ("feat", C.c_void_p), ("out_means", C.c_void_p), ("out_quats", C.c_void_p),
+                ("out_scales", C.c_void_p), ("out_opacity", C.c_void_p), ("out_feat", C.c_void_p)]
+
+
 class fe_state_layout(C.Structure):
     _fields_ = [(k, C.c_size_t) for k in ("total", "xy", "conic_opacity", "rgb", "box", "depth_key",
                                           "tile_count", "sorted_gauss", "ranges", "report")]
@@ -107,6 +120,11 @@ EXPORTS = {
     "fe_batch_plan_destroy": (None, [C.c_void_p]),
     "fe_decoder_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int64]),
     "fe_decoder_l1": (C.c_int, [C.POINTER(fe_decoder), C.c_void_p, C.c_size_t, C.c_void_p]),
+    "fe_deform_plane_floats": (C.c_size_t, [C.POINTER(fe_deform_net)]),
+    "fe_deform_weight_floats": (C.c_size_t, [C.POINTER(fe_deform_net)]),
+    "fe_deform_workspace_bytes": (C.c_size_t, [C.POINTER(fe_deform_net)]),
+    "fe_deform_forward": (C.c_int, [C.POINTER(fe_deform_net), C.POINTER(fe_deform_io), C.c_void_p, C.c_size_t,
+                                    C.c_void_p]),
 }
 
 _lib = None
@@ -124,7 +142,7 @@ def load_library(path: str = LIB_PATH):
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
-    if lib.fe_abi_version() != 5:
+    if lib.fe_abi_version() != 6:
         raise ImportError("libfe4dgs_rast.so ABI version mismatch")
     _lib = lib
     return lib
@@ -500,3 +518,73 @@ class DecoderL1(torch.autograd.Function):
 def decoder_loss(feat, weight, bias, target):
     """Differentiable L_feat of a rendered feature map (eq. 10)."""
     return DecoderL1.apply(feat, weight, bias, target)
+
+
+# ---------------------------------------------------------------------------
+# FST deformation module (Sec. 3.2, eqs. 4-6)
+
+DEFORM_BRANCHES = ("mu", "rot", "scale", "opacity")
+
+
+class DeformNet:
+    """Device copy of the deformation parameters in the library's flat
+    layout: ``planes[l][p]`` ([res_b, res_a, C] arrays, levels and
+    coordinate pairs in the header's order) and ``layers`` (weight [out, in],
+    bias [out] pairs under 'out', 'branch_<g>', 'head_<g>', 'sem')."""
+
+    def __init__(self, planes, layers, lo, hi, channels, width, feat_dim, base_res=(64, 64, 64, 100),
+                 levels=(1, 2, 4, 8), device="cuda"):
+        lib = load_library()
+        self.net = fe_deform_net()
+        self.net.channels, self.net.width, self.net.feat_dim = int(channels), int(width), int(feat_dim)
+        self.net.base_res[:] = [int(r) for r in base_res]
+        self.net.level_mult[:] = [int(m) for m in levels]
+        self.net.lo[:] = [float(v) for v in lo]
+        self.net.hi[:] = [float(v) for v in hi]
+        n_planes = lib.fe_deform_plane_floats(C.byref(self.net))
+        n_weights = lib.fe_deform_weight_floats(C.byref(self.net))
+        if n_planes == 0 or n_weights == 0:
+            raise RasterError(FE_ERR_UNSUPPORTED, "fe_deform_net")
+        flat = [np.ascontiguousarray(p, dtype=np.float32).ravel() for lvl in planes for p in lvl]
+        order = list(layers["out"])
+        for g in DEFORM_BRANCHES:
+            order += list(layers["branch_" + g]) + [layers["head_" + g]]
+        order += list(layers["sem"])
+        wflat = [np.ascontiguousarray(a, dtype=np.float32).ravel() for w, b in order for a in (w, b)]
+        pf, wf = np.concatenate(flat), np.concatenate(wflat)
+        if pf.size != n_planes or wf.size != n_weights:
+            raise ValueError(f"parameter sizes {pf.size}/{wf.size} do not match the layout {n_planes}/{n_weights}")
+        self.planes = torch.from_numpy(pf).to(device)
+        self.weights = torch.from_numpy(wf).to(device)
+        self.net.planes, self.net.weights = self.planes.data_ptr(), self.weights.data_ptr()
+        self.workspace = torch.empty(lib.fe_deform_workspace_bytes(C.byref(self.net)), dtype=torch.uint8,
+                                     device=device)
+        self.feat_dim = int(feat_dim)
+
+
+def deform_forward(net: DeformNet, means, quats, log_scales, logit_opacity, feat, t: float, out_feat_dtype="f32",
+                   out=None, stream=None) -> dict:
+    """fe_deform_forward: G_t (means, quats, scales, opacity, feat) of n
+    canonical Gaussians at time t.  Inputs are float32 CUDA tensors; feat is
+    [n, N].  ``out`` may hold preallocated output tensors."""
+    lib = load_library()
+    n = means.shape[0]
+    N = net.feat_dim
+    _req(means, torch.float32, (n, 3), "means")
+    _req(quats, torch.float32, (n, 4), "quats")
+    _req(log_scales, torch.float32, (n, 3), "log_scales")
+    _req(logit_opacity, torch.float32, (n,), "logit_opacity")
+    _req(feat, torch.float32, (n, N), "feat")
+    dev = means.device
+    fdt = torch.bfloat16 if out_feat_dtype == "bf16" else torch.float32
+    if out is None:
+        out = dict(means=torch.empty(n, 3, device=dev), quats=torch.empty(n, 4, device=dev),
+                   scales=torch.empty(n, 3, device=dev), opacity=torch.empty(n, device=dev),
+                   feat=torch.empty(n, N, dtype=fdt, device=dev))
+    io = fe_deform_io(n, float(t), FE_BF16 if fdt == torch.bfloat16 else FE_F32, means.data_ptr(), quats.data_ptr(),
+                      log_scales.data_ptr(), logit_opacity.data_ptr(), feat.data_ptr(), out["means"].data_ptr(),
+                      out["quats"].data_ptr(), out["scales"].data_ptr(), out["opacity"].data_ptr(),
+                      out["feat"].data_ptr())
+    _check(lib.fe_deform_forward(C.byref(net.net), C.byref(io), C.c_void_p(net.workspace.data_ptr()),
+                                 net.workspace.numel(), C.c_void_p(_stream_handle(stream))), "fe_deform_forward")
+    return out
