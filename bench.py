@@ -25,7 +25,6 @@ from __future__ import annotations
 
 import argparse
 import ctypes as C
-import hashlib
 import json
 import os
 import sys
@@ -64,6 +63,8 @@ def _parse():
     ap.add_argument("--no-configs", action="store_true", help="skip the large and mid frames")
     ap.add_argument("--no-decoder", action="store_true", help="skip the semantic decoder + feature loss")
     ap.add_argument("--no-deform", action="store_true", help="skip the FST deformation module")
+    ap.add_argument("--only", default=None, choices=["decoder", "deform"],
+                    help="time only this section and print its record (for profiling runs)")
     return ap.parse_args()
 
 
@@ -502,23 +503,17 @@ def copy_bandwidth():
     return {"bytes": 2 * n, "gb_per_s": round(2 * n / (best * 1e-3) / 1e9, 1)}
 
 
-def _kernel_source_hash():
-    h = hashlib.sha1()
-    csrc = os.path.join(ROOT, "paper_2503_06161_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        h.update(open(os.path.join(csrc, f), "rb").read())
-    return h.hexdigest()[:12]
-
-
 def _traffic(stage):
-    """HBM traffic from the committed rocprofv3 counter summary, if it was taken
-    on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"{stage}_metric_pmc.json")
+    """HBM bytes per launch of the stage's dominant kernel from the committed
+    rocprofv3 counter record (FETCH_SIZE + WRITE_SIZE scaled by a plain copy),
+    if it was taken on the current sources of that kernel."""
+    path = os.path.join(ROOT, "profiles", "traffic_metric_bf16.json")
     try:
-        d = json.load(open(path))
-    except (OSError, ValueError):
+        d = json.load(open(path))["stages"][stage]
+    except (OSError, ValueError, KeyError):
         return None
-    if d.get("source_hash") != _kernel_source_hash():
+    from paper_2503_06161_amd.profiling import kernel_source_hash
+    if d.get("source_hash") != kernel_source_hash(stage):
         return None
     return d.get("bytes_per_launch")
 
@@ -544,6 +539,12 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.only == "decoder":
+        print(json.dumps({"decoder_l1": decoder_frame(args.steps, args.warmup)}), flush=True)
+        return
+    if args.only == "deform":
+        print(json.dumps({"deform": deform_frame(args.steps, args.warmup)}), flush=True)
+        return
     sc = make_scene(WORKLOAD)
     keep = not (args.no_accuracy or args.no_cpu_baseline)
     res = {}

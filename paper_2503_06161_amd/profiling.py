@@ -16,6 +16,7 @@ from __future__ import annotations
 import argparse
 import csv
 import glob
+import hashlib
 import json
 import os
 import re
@@ -23,6 +24,35 @@ import sys
 from collections import defaultdict
 
 COPY_BYTES = 256 << 20      # bench.py --calibrate-copy
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+
+# the sources each frame stage's kernels are built from, and the kernels
+STAGE_SOURCES = {
+    "composite": ("fe_composite_mfma.hip", "fe_common.h"),
+    "composite_bwd": ("fe_backward_mfma.hip", "fe_common.h"),
+    "project": ("fe_project.hip", "fe_common.h"),
+    "project_bwd": ("fe_project.hip", "fe_common.h"),
+    "sort": ("fe_sort.hip", "fe_common.h"),
+    "reduce": ("fe_backward_mfma.hip", "fe_common.h"),
+}
+STAGE_KERNELS = {
+    "composite": r"^composite_fwd",
+    "composite_bwd": r"^composite_bwd",
+    "project": r"^project_fwd",
+    "project_bwd": r"^project_bwd",
+    "sort": r"^(bin_count|bin_offsets|bin_place|tile_sort|zero_u32)",
+    "reduce": r"^(reduce_rows|backward_prep)",
+}
+
+
+def kernel_source_hash(stage: str) -> str:
+    """Hash of the sources of one stage's kernels: a traffic record taken on
+    other sources is stale."""
+    h = hashlib.sha1()
+    for f in STAGE_SOURCES[stage]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:12]
 
 
 def _csv_rows(root: str, suffix: str):
@@ -92,7 +122,30 @@ def main(argv=None):
     p.add_argument("dirs", nargs="+")
     p.add_argument("--match", default=".")
     p.add_argument("--json", default=None, help="print the traffic record of the first kernel matching this regex")
+    tr = sub.add_parser("traffic", help="per-stage HBM bytes per launch (FETCH_SIZE run, WRITE_SIZE run)")
+    tr.add_argument("fetch_dir")
+    tr.add_argument("write_dir")
+    tr.add_argument("--command", default="", help="the rocprofv3 command the runs came from")
     a = ap.parse_args(argv)
+    if a.cmd == "traffic":
+        cnt = counters([a.fetch_dir, a.write_dir])
+        fs, ws = copy_scale([a.fetch_dir, a.write_dir])
+        if not (fs and ws):
+            print("no calibration copy in these runs", file=sys.stderr)
+            return 1
+        stages = {}
+        for st, rx in STAGE_KERNELS.items():
+            ks = [k for k in cnt if re.search(rx, k)]
+            if not ks:
+                continue
+            rd = sum(cnt[k].get("FETCH_SIZE", 0.0) for k in ks) * fs
+            wr = sum(cnt[k].get("WRITE_SIZE", 0.0) for k in ks) * ws
+            stages[st] = {"kernels": sorted(ks), "source_files": list(STAGE_SOURCES[st]),
+                          "source_hash": kernel_source_hash(st), "read_bytes": round(rd), "write_bytes": round(wr),
+                          "bytes_per_launch": round(rd + wr)}
+        print(json.dumps({"workload": "640x512, 300k Gaussians, SH 3, D=128, BF16 storage, MFMA kernels, 16x16 tiles",
+                          "fetch_scale": fs, "write_scale": ws, "command": a.command, "stages": stages}, indent=1))
+        return 0
     if a.cmd == "trace":
         kt = kernel_times(a.dir)
         print("| kernel | dispatches | avg µs | grid | block | LDS B | VGPR | AGPR | scratch |")
