@@ -35,7 +35,7 @@ constexpr int kPlanes = 24;       // 4 levels x 6 pairs
 constexpr int kBranchDim[4] = {3, 4, 3, 1};
 constexpr int kDOff[4] = {0, 3, 7, 10};   // columns of the head outputs
 constexpr int kLdA = kW + 4;              // padded LDS rows
-constexpr int kLdU = 2 * kW + 4;
+constexpr int kLdG = kW / 2 + 4;
 constexpr int kLdD = 12;
 
 __host__ __device__ constexpr int pair_a(int p) { return p < 3 ? 0 : (p < 5 ? 1 : 2); }
@@ -86,8 +86,11 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Weights of every layer into bf16 hi / lo parts, [out_pad][in] per layer
-// (rows past `out` are zero).
+// Weights of every layer into bf16 hi / lo parts in the order the MFMA B
+// operand is read: 512-element blocks of 16 outputs x 32 inputs, block
+// (output tile tb, input step kb) at (tb * in / 32 + kb) * 512, lane l of a
+// block holding outputs 16 tb + l % 16, inputs 32 kb + 8 (l / 16) .. + 7 as
+// 8 consecutive elements (rows past `out` are zero).
 __global__ __launch_bounds__(256) void deform_prep_kernel(DeformArgs a, int64_t total) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= total) return;
@@ -95,7 +98,9 @@ __global__ __launch_bounds__(256) void deform_prep_kernel(DeformArgs a, int64_t 
   while (l + 1 < kLayers && i >= a.layer[l + 1].p_off) ++l;
   const LayerDesc L = a.layer[l];
   const int64_t e = i - L.p_off;
-  const int n = (int)(e / L.in), k = (int)(e % L.in);
+  const int blk = (int)(e / 512), w = (int)(e % 512), ln = w / 8, j = w % 8;
+  const int tb = blk / (L.in / 32), kb = blk % (L.in / 32);
+  const int n = 16 * tb + (ln & 15), k = 32 * kb + 8 * (ln >> 4) + j;
   const float v = n < L.out ? a.weights[L.w_off + (int64_t)n * L.in + k] : 0.f;
   __bf16 hi, lo;
   split2(v, hi, lo);
@@ -103,15 +108,17 @@ __global__ __launch_bounds__(256) void deform_prep_kernel(DeformArgs a, int64_t 
   const_cast<__bf16*>(a.wlo)[i] = lo;
 }
 
-// acc[nt] (16 x 16 tiles of columns n0 + 16 nt ..) = act(X rows of this
-// wave) W^T over K inputs.
+// acc[nt] (16 x 16 tiles of columns n0 + 16 nt ..) += act(X rows of this
+// wave) W[:, k0 .. k0 + K)^T: K of the layer's inputs, starting at input k0.
 template <int K, int NT, bool RELU>
 __device__ __forceinline__ void dense(const float* X, int ldx, const DeformArgs& a, const LayerDesc& L, int n0,
-                                      f32x4 (&acc)[NT], int lane, int wave) {
-#pragma unroll
-  for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{};
+                                      int k0, f32x4 (&acc)[NT], int lane, int wave) {
   const int r = 16 * wave + (lane & 15);
   const int kq = 8 * (lane >> 4);
+  const __bf16* bh0 = a.whi + L.p_off + 8 * lane;
+  const __bf16* bl0 = a.wlo + L.p_off + 8 * lane;
+  const int bstride = (L.in / 32) * 512;          // one output tile
+  const int boff = (n0 / 16) * bstride + (k0 / 32) * 512;
 #pragma unroll
   for (int ks = 0; ks < K / 32; ++ks) {
     const float* xp = X + r * ldx + 32 * ks + kq;
@@ -128,9 +135,9 @@ __device__ __forceinline__ void dense(const float* X, int ldx, const DeformArgs&
     }
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
-      const int64_t e = L.p_off + (int64_t)(n0 + 16 * nt + (lane & 15)) * K + 32 * ks + kq;
-      const bf16x8 bh = *reinterpret_cast<const bf16x8*>(a.whi + e);
-      const bf16x8 bl = *reinterpret_cast<const bf16x8*>(a.wlo + e);
+      const int e = boff + nt * bstride + ks * 512;
+      const bf16x8 bh = *reinterpret_cast<const bf16x8*>(bh0 + e);
+      const bf16x8 bl = *reinterpret_cast<const bf16x8*>(bl0 + e);
       acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[nt], 0, 0, 0);
       acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[nt], 0, 0, 0);
       acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[nt], 0, 0, 0);
@@ -138,17 +145,28 @@ __device__ __forceinline__ void dense(const float* X, int ldx, const DeformArgs&
   }
 }
 
-// Y[rows of this wave][n0 + ...] = acc + bias, for the layer's real outputs.
+// acc[nt] = the bias of the lane's output column (the products are added to it).
 template <int NT>
-__device__ __forceinline__ void store_rows(float* Y, int ldy, const DeformArgs& a, const LayerDesc& L, int n0,
-                                           const f32x4 (&acc)[NT], int lane, int wave) {
+__device__ __forceinline__ void init_bias(f32x4 (&acc)[NT], const DeformArgs& a, const LayerDesc& L, int n0,
+                                          int lane) {
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    const int n = n0 + 16 * nt + (lane & 15);
+    const float b = n < L.out ? a.weights[L.b_off + n] : 0.f;
+    acc[nt] = f32x4{b, b, b, b};
+  }
+}
+
+// Y[rows of this wave][n0 + ...] = acc, for the layer's real outputs.
+template <int NT>
+__device__ __forceinline__ void store_rows(float* Y, int ldy, const LayerDesc& L, int n0, const f32x4 (&acc)[NT],
+                                           int lane, int wave) {
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) {
     const int n = n0 + 16 * nt + (lane & 15);
     if (n < L.out) {
-      const float b = a.weights[L.b_off + n];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) Y[(16 * wave + 4 * (lane >> 4) + v) * ldy + (n - n0) + 0] = acc[nt][v] + b;
+      for (int v = 0; v < 4; ++v) Y[(16 * wave + 4 * (lane >> 4) + v) * ldy + (n - n0)] = acc[nt][v];
     }
   }
 }
@@ -158,22 +176,23 @@ __device__ __forceinline__ void layer(const float* X, int ldx, float* Y, int ldy
                                       int lane, int wave) {
   const LayerDesc L = a.layer[l];
   f32x4 acc[NT];
-  dense<K, NT, RELU>(X, ldx, a, L, 0, acc, lane, wave);
-  store_rows<NT>(Y, ldy, a, L, 0, acc, lane, wave);
+  init_bias<NT>(acc, a, L, 0, lane);
+  dense<K, NT, RELU>(X, ldx, a, L, 0, 0, acc, lane, wave);
+  store_rows<NT>(Y, ldy, L, 0, acc, lane, wave);
   wave_sync();
 }
 
 template <int C>
 __global__ __launch_bounds__(kThreads) void deform_kernel(DeformArgs a) {
   constexpr int LDX = 4 * C + 4;
-  constexpr int R1 = (kRows * LDX > kRows * (kLdA + kLdU + kLdD)) ? kRows * LDX : kRows * (kLdA + kLdU + kLdD);
+  constexpr int R1 = (kRows * LDX > kRows * (kLdA + kLdG + kLdD)) ? kRows * LDX : kRows * (kLdA + kLdG + kLdD);
   __shared__ double s_u[kRows][4];
   __shared__ __attribute__((aligned(16))) float s_a[kRows * kLdA];
   __shared__ __attribute__((aligned(16))) float s_r[R1];
   float* s_x = s_r;                          // HexPlane features (until the first layer is done)
   float* s_b = s_r;                          // then: h and the F_out ping-pong buffer
-  float* s_uall = s_r + kRows * kLdA;        // [h_mu | h_rot | h_scale | h_opacity]
-  float* s_d = s_uall + kRows * kLdU;        // head outputs
+  float* s_hg = s_r + kRows * kLdA;          // the current branch's h_g
+  float* s_d = s_hg + kRows * kLdG;          // head outputs
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -238,8 +257,9 @@ __global__ __launch_bounds__(kThreads) void deform_kernel(DeformArgs a) {
   {
     const LayerDesc L0 = a.layer[0];
     f32x4 acc[4];
-    dense<4 * C, 4, false>(s_x, LDX, a, L0, 0, acc, lane, wave);
-    store_rows<4>(s_a, kLdA, a, L0, 0, acc, lane, wave);
+    init_bias<4>(acc, a, L0, 0, lane);
+    dense<4 * C, 4, false>(s_x, LDX, a, L0, 0, 0, acc, lane, wave);
+    store_rows<4>(s_a, kLdA, L0, 0, acc, lane, wave);
   }
   __syncthreads();   // every wave is done with the features before s_r is reused
   float* src = s_a;
@@ -251,35 +271,59 @@ __global__ __launch_bounds__(kThreads) void deform_kernel(DeformArgs a) {
     src = dst;
     dst = t;
   }
-  // h is in src (= s_b); s_a is free for the branch temporaries
+  // h is in src (= s_b); s_a is free for the branch temporaries.  E1 acts on
+  // u_all = [h_mu | h_rot | h_scale | h_opacity]: it is accumulated branch by
+  // branch from each h_g (E1's input columns 32g..), so u_all is never stored.
   float* h = src;
   float* tmp = dst;
+  // the canonical features this lane adds its updates to (first 128 columns),
+  // loaded now so that their latency hides behind the branches
+  constexpr int kZPre = 2;   // 64-column chunks
+  float zpre[kZPre][4][4];
+#pragma unroll
+  for (int c = 0; c < kZPre; ++c)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int n = 64 * c + 16 * nt + (lane & 15);
+        const int64_t g = g0 + 16 * wave + 4 * (lane >> 4) + v;
+        zpre[c][nt][v] = (n < a.N && g < a.n) ? a.feat[g * a.N + n] : 0.f;
+      }
+  f32x4 e1[4];
+  init_bias<4>(e1, a, a.layer[20], 0, lane);
 #pragma unroll 1
   for (int g = 0; g < 4; ++g) {
     const int l = 8 + 3 * g;
     layer<kW, 4, true>(h, kLdA, tmp, kLdA, a, l, lane, wave);
-    layer<kW, 2, true>(tmp, kLdA, s_uall + (kW / 2) * g, kLdU, a, l + 1, lane, wave);
-    layer<kW / 2, 1, true>(s_uall + (kW / 2) * g, kLdU, s_d + kDOff[g], kLdD, a, l + 2, lane, wave);
+    layer<kW, 2, true>(tmp, kLdA, s_hg, kLdG, a, l + 1, lane, wave);
+    layer<kW / 2, 1, true>(s_hg, kLdG, s_d + kDOff[g], kLdD, a, l + 2, lane, wave);
+    dense<kW / 2, 4, false>(s_hg, kLdG, a, a.layer[20], 0, (kW / 2) * g, e1, lane, wave);
+    wave_sync();   // s_hg is rewritten by the next branch
   }
-  layer<2 * kW, 4, false>(s_uall, kLdU, tmp, kLdA, a, 20, lane, wave);
+  store_rows<4>(tmp, kLdA, a.layer[20], 0, e1, lane, wave);
+  wave_sync();
 
   // 3. semantic update, written as z + dz, 64 columns at a time
   {
     const LayerDesc L = a.layer[21];
-#pragma unroll 1
-    for (int n0 = 0; n0 < a.N; n0 += 64) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int n0 = 64 * c;
+      if (n0 >= a.N) break;
       f32x4 acc[4];
-      dense<kW, 4, true>(tmp, kLdA, a, L, n0, acc, lane, wave);
+      init_bias<4>(acc, a, L, n0, lane);
+      dense<kW, 4, true>(tmp, kLdA, a, L, n0, 0, acc, lane, wave);
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt) {
         const int n = n0 + 16 * nt + (lane & 15);
         if (n < a.N) {
-          const float b = a.weights[L.b_off + n];
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int64_t g = g0 + 16 * wave + 4 * (lane >> 4) + v;
             if (g < a.n) {
-              const float z = a.feat[g * a.N + n] + (acc[nt][v] + b);
+              const float z0 = c < kZPre ? zpre[c < kZPre ? c : 0][nt][v] : a.feat[g * a.N + n];
+              const float z = z0 + acc[nt][v];
               if (a.out_bf16)
                 static_cast<__bf16*>(a.out_feat)[g * a.N + n] = (__bf16)z;
               else
