@@ -35,7 +35,6 @@ constexpr int kPlanes = 24;       // 4 levels x 6 pairs
 constexpr int kBranchDim[4] = {3, 4, 3, 1};
 constexpr int kDOff[4] = {0, 3, 7, 10};   // columns of the head outputs
 constexpr int kLdA = kW + 4;              // padded LDS rows
-constexpr int kLdG = kW / 2 + 4;
 constexpr int kLdD = 12;
 
 __host__ __device__ constexpr int pair_a(int p) { return p < 3 ? 0 : (p < 5 ? 1 : 2); }
@@ -182,17 +181,57 @@ __device__ __forceinline__ void layer(const float* X, int ldx, float* Y, int ldy
   wave_sync();
 }
 
+// acc[nt] += (A operands held in registers, K = 32 KS) W[:, 0 .. K)^T.
+template <int KS, int NT>
+__device__ __forceinline__ void dense_regs(const bf16x8 (&ah)[KS], const bf16x8 (&al)[KS], const DeformArgs& a,
+                                           const LayerDesc& L, f32x4 (&acc)[NT], int lane) {
+  const __bf16* bh0 = a.whi + L.p_off + 8 * lane;
+  const __bf16* bl0 = a.wlo + L.p_off + 8 * lane;
+  const int bstride = (L.in / 32) * 512;
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int e = nt * bstride + ks * 512;
+      const bf16x8 bh = *reinterpret_cast<const bf16x8*>(bh0 + e);
+      const bf16x8 bl = *reinterpret_cast<const bf16x8*>(bl0 + e);
+      acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[ks], bh, acc[nt], 0, 0, 0);
+      acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[ks], bl, acc[nt], 0, 0, 0);
+      acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[ks], bh, acc[nt], 0, 0, 0);
+    }
+}
+
+// A operands (hi / lo, optionally after ReLU) of this wave's 16 rows of X,
+// K = 32 KS inputs.
+template <int KS, bool RELU>
+__device__ __forceinline__ void load_a(const float* X, int ldx, bf16x8 (&ah)[KS], bf16x8 (&al)[KS], int lane,
+                                       int wave) {
+  const float* xp = X + (16 * wave + (lane & 15)) * ldx + 8 * (lane >> 4);
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const float4 x0 = *reinterpret_cast<const float4*>(xp + 32 * ks);
+    const float4 x1 = *reinterpret_cast<const float4*>(xp + 32 * ks + 4);
+    const float xs[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      __bf16 hi, lo;
+      split2(RELU ? fmaxf(xs[j], 0.f) : xs[j], hi, lo);
+      ah[ks][j] = hi;
+      al[ks][j] = lo;
+    }
+  }
+}
+
+// The MLP keeps one LDS buffer, the HexPlane features' [64][4C + 4]: wave w
+// owns rows 16w..16w+15, and every layer reads its input rows (all of them,
+// into registers) before it writes its output rows in place.
 template <int C>
 __global__ __launch_bounds__(kThreads) void deform_kernel(DeformArgs a) {
   constexpr int LDX = 4 * C + 4;
-  constexpr int R1 = (kRows * LDX > kRows * (kLdA + kLdG + kLdD)) ? kRows * LDX : kRows * (kLdA + kLdG + kLdD);
+  constexpr int KS0 = 4 * C / 32;            // k steps of the first layer
   __shared__ double s_u[kRows][4];
-  __shared__ __attribute__((aligned(16))) float s_a[kRows * kLdA];
-  __shared__ __attribute__((aligned(16))) float s_r[R1];
-  float* s_x = s_r;                          // HexPlane features (until the first layer is done)
-  float* s_b = s_r;                          // then: h and the F_out ping-pong buffer
-  float* s_hg = s_r + kRows * kLdA;          // the current branch's h_g
-  float* s_d = s_hg + kRows * kLdG;          // head outputs
+  __shared__ __attribute__((aligned(16))) float s_x[kRows * LDX];
+  __shared__ float s_d[kRows * kLdD];        // head outputs
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -247,35 +286,42 @@ __global__ __launch_bounds__(kThreads) void deform_kernel(DeformArgs a) {
         prod.y *= s.y;
         prod.z *= s.z;
         prod.w *= s.w;
+        if (p == 2) __builtin_amdgcn_sched_barrier(0);   // at most three planes' taps in flight
       }
       *reinterpret_cast<float4*>(&s_x[gi * LDX + lvl * C + 4 * chunk]) = prod;
     }
   }
   __syncthreads();
 
-  // 2. the affine layers; wave w owns rows 16w..16w+15 of every buffer
+  // 2. the affine layers, in place in s_x
   {
+    bf16x8 ah[KS0], al[KS0];
+    load_a<KS0, false>(s_x, LDX, ah, al, lane, wave);
     const LayerDesc L0 = a.layer[0];
     f32x4 acc[4];
     init_bias<4>(acc, a, L0, 0, lane);
-    dense<4 * C, 4, false>(s_x, LDX, a, L0, 0, 0, acc, lane, wave);
-    store_rows<4>(s_a, kLdA, L0, 0, acc, lane, wave);
+    dense_regs<KS0, 4>(ah, al, a, L0, acc, lane);
+    store_rows<4>(s_x, LDX, L0, 0, acc, lane, wave);
+    wave_sync();
   }
-  __syncthreads();   // every wave is done with the features before s_r is reused
-  float* src = s_a;
-  float* dst = s_b;
 #pragma unroll 1
   for (int l = 1; l < 8; ++l) {
-    layer<kW, 4, true>(src, kLdA, dst, kLdA, a, l, lane, wave);
-    float* t = src;
-    src = dst;
-    dst = t;
+    bf16x8 ah[2], al[2];
+    load_a<2, true>(s_x, LDX, ah, al, lane, wave);
+    const LayerDesc L = a.layer[l];
+    f32x4 acc[4];
+    init_bias<4>(acc, a, L, 0, lane);
+    dense_regs<2, 4>(ah, al, a, L, acc, lane);
+    store_rows<4>(s_x, LDX, L, 0, acc, lane, wave);
+    wave_sync();
   }
-  // h is in src (= s_b); s_a is free for the branch temporaries.  E1 acts on
-  // u_all = [h_mu | h_rot | h_scale | h_opacity]: it is accumulated branch by
-  // branch from each h_g (E1's input columns 32g..), so u_all is never stored.
-  float* h = src;
-  float* tmp = dst;
+  // h = F_out(f); the A operands of relu(h) stay in registers for the four
+  // branches.  E1 acts on u_all = [h_mu | h_rot | h_scale | h_opacity]: it is
+  // accumulated branch by branch from each h_g (E1's input columns 32g..), so
+  // u_all is never stored.
+  bf16x8 hh[2], hl[2];
+  load_a<2, true>(s_x, LDX, hh, hl, lane, wave);
+  float* tmp = s_x;
   // the canonical features this lane adds its updates to (first 128 columns),
   // loaded now so that their latency hides behind the branches
   constexpr int kZPre = 2;   // 64-column chunks
@@ -295,13 +341,19 @@ __global__ __launch_bounds__(kThreads) void deform_kernel(DeformArgs a) {
 #pragma unroll 1
   for (int g = 0; g < 4; ++g) {
     const int l = 8 + 3 * g;
-    layer<kW, 4, true>(h, kLdA, tmp, kLdA, a, l, lane, wave);
-    layer<kW, 2, true>(tmp, kLdA, s_hg, kLdG, a, l + 1, lane, wave);
-    layer<kW / 2, 1, true>(s_hg, kLdG, s_d + kDOff[g], kLdD, a, l + 2, lane, wave);
-    dense<kW / 2, 4, false>(s_hg, kLdG, a, a.layer[20], 0, (kW / 2) * g, e1, lane, wave);
-    wave_sync();   // s_hg is rewritten by the next branch
+    {
+      f32x4 acc[4];
+      init_bias<4>(acc, a, a.layer[l], 0, lane);
+      dense_regs<2, 4>(hh, hl, a, a.layer[l], acc, lane);
+      store_rows<4>(s_x, LDX, a.layer[l], 0, acc, lane, wave);
+      wave_sync();
+    }
+    layer<kW, 2, true>(s_x, LDX, s_x, LDX, a, l + 1, lane, wave);          // h_g, in place
+    layer<kW / 2, 1, true>(s_x, LDX, s_d + kDOff[g], kLdD, a, l + 2, lane, wave);
+    dense<kW / 2, 4, false>(s_x, LDX, a, a.layer[20], 0, (kW / 2) * g, e1, lane, wave);
+    wave_sync();   // h_g is overwritten by the next branch
   }
-  store_rows<4>(tmp, kLdA, a.layer[20], 0, e1, lane, wave);
+  store_rows<4>(s_x, LDX, a.layer[20], 0, e1, lane, wave);
   wave_sync();
 
   // 3. semantic update, written as z + dz, 64 columns at a time
@@ -313,7 +365,7 @@ __global__ __launch_bounds__(kThreads) void deform_kernel(DeformArgs a) {
       if (n0 >= a.N) break;
       f32x4 acc[4];
       init_bias<4>(acc, a, L, n0, lane);
-      dense<kW, 4, true>(tmp, kLdA, a, L, n0, 0, acc, lane, wave);
+      dense<kW, 4, true>(tmp, LDX, a, L, n0, 0, acc, lane, wave);
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt) {
         const int n = n0 + 16 * nt + (lane & 15);
