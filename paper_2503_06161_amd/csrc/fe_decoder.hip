@@ -95,10 +95,15 @@ __global__ __launch_bounds__(kP1Threads) void decoder_pass1_kernel(DecArgs a) {
   constexpr int NQ = KIN * kPB / 4;   // 2x2 (channel, pixel) quads of a z block
   constexpr int ZQ = (NQ + kP1Threads - 1) / kP1Threads;
   static_assert(NQ % 64 == 0, "whole waves of quads");
+  // with 128 input channels the low parts of W live in LDS, which leaves
+  // registers for the next block's target values
+  constexpr bool kLoLds = KIN > 64;
+  constexpr int WL = kLoLds ? KIN + 8 : 8;
   typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
   __shared__ __attribute__((aligned(16))) __bf16 s_zc[2][KIN][ZR];   // z[c][px], hi / lo
   __shared__ __attribute__((aligned(16))) __bf16 s_zt[2][kPB][ZT];   // z[px][c], hi / lo
   __shared__ __attribute__((aligned(16))) __bf16 s_sc[kC][SR];       // sign[c][px] (each wave its own rows)
+  __shared__ __attribute__((aligned(16))) __bf16 s_wlo[kLoLds ? kC : 1][WL];  // low parts of W
   __shared__ float s_bias[kC];
   __shared__ float s_red[kP1Threads / 64];
 
@@ -113,7 +118,7 @@ __global__ __launch_bounds__(kP1Threads) void decoder_pass1_kernel(DecArgs a) {
   for (int c = threadIdx.x; c < kC; c += kP1Threads) s_bias[c] = a.bias[c];
 
   // W rows of this wave (decode A operand: row 32 wave + px, k = 16 ks + 8 h + j), hi / lo
-  bf16x8 wa[KS][2];
+  bf16x8 wa[KS][kLoLds ? 1 : 2];
   {
     const float* wr = a.weight + (int64_t)(32 * wave + px) * KIN + 8 * h;
 #pragma unroll
@@ -121,13 +126,18 @@ __global__ __launch_bounds__(kP1Threads) void decoder_pass1_kernel(DecArgs a) {
       const float4 x0 = *reinterpret_cast<const float4*>(wr + 16 * ks);
       const float4 x1 = *reinterpret_cast<const float4*>(wr + 16 * ks + 4);
       const float xs[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+      bf16x8 lo8;
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         __bf16 hi, lo;
         split2(xs[j], hi, lo);
         wa[ks][0][j] = hi;
-        wa[ks][1][j] = lo;
+        lo8[j] = lo;
       }
+      if constexpr (kLoLds)
+        *reinterpret_cast<bf16x8*>(&s_wlo[32 * wave + px][16 * ks + 8 * h]) = lo8;
+      else
+        wa[ks][kLoLds ? 0 : 1] = lo8;
     }
   }
   bf16x8 ones;
@@ -167,7 +177,7 @@ __global__ __launch_bounds__(kP1Threads) void decoder_pass1_kernel(DecArgs a) {
       }
     }
   };
-  // target of this lane's 16 (row, pixel) entries: rows 32 wave + 8 (v / 4)
+  // target of this lane's 16 (row, pixel) entries, one block ahead: rows 32 wave + 8 (v / 4)
   // + 4 h + v % 4, pixel px; lanes past the last pixel read that pixel (and
   // contribute nothing)
   float tv[16];
@@ -186,10 +196,10 @@ __global__ __launch_bounds__(kP1Threads) void decoder_pass1_kernel(DecArgs a) {
     }
   };
   load_z(blockIdx.x);
-  __syncthreads();   // s_bias
+  load_t(blockIdx.x);
+  __syncthreads();   // s_bias, s_wlo
   for (int64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
     const int64_t p0 = blk * kPB;
-    load_t(blk);
     // z block to LDS in both layouts, hi / lo parts; the next block's loads go out
 #pragma unroll
     for (int i = 0; i < ZQ; ++i) {
@@ -219,7 +229,12 @@ __global__ __launch_bounds__(kP1Threads) void decoder_pass1_kernel(DecArgs a) {
       const bf16x8 zl = *reinterpret_cast<const bf16x8*>(&s_zt[1][px][kc]);
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa[ks][0], zh, acc, 0, 0, 0);
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa[ks][0], zl, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa[ks][1], zh, acc, 0, 0, 0);
+      bf16x8 wl;
+      if constexpr (kLoLds)
+        wl = *reinterpret_cast<const bf16x8*>(&s_wlo[32 * wave + px][kc]);
+      else
+        wl = wa[ks][kLoLds ? 0 : 1];
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wl, zh, acc, 0, 0, 0);
       __builtin_amdgcn_sched_barrier(0);
     }
     // residual, loss and sign of each (row, pixel); bit v of nzb / ngb: the
@@ -242,6 +257,7 @@ __global__ __launch_bounds__(kP1Threads) void decoder_pass1_kernel(DecArgs a) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) dr[(uint32_t)(8 * (v >> 2) + 4 * h + (v & 3)) * Pu + (uint32_t)px] = acc[v];
     }
+    if (blk + gridDim.x < nblocks) load_t(blk + gridDim.x);
     // the pixel's 32-row masks: bits 0..15 from this lane, 16..31 from lane + 32
     const uint32_t onz = (uint32_t)__shfl_xor((int)nzb, 32, 64), ong = (uint32_t)__shfl_xor((int)ngb, 32, 64);
     if (h == 0) a.signs[(blk * 8 + wave) * kPB + px] = make_uint2(nzb | (onz << 16), ngb | (ong << 16));
