@@ -163,17 +163,18 @@ __global__ __launch_bounds__(kP1Threads) void decoder_pass1_kernel(DecArgs a) {
     const int64_t p0 = blk * kPB;
     const int last = (int)(P - 1 - p0 < kPB ? P - 1 - p0 : kPB - 1);
     const int x0 = zx < last ? zx : last, x1 = zx + 1 < last ? zx + 1 : last;
-    const float k0 = zx <= last ? 1.f : 0.f, k1 = zx + 1 <= last ? 1.f : 0.f;
     const uint32_t r0 = (uint32_t)(zc0 - 8 * wave) * Pu * 4u, r1 = r0 + 4u * Pu;
+    // raw values: the pixels past the last one are zeroed when staged, so
+    // that nothing waits on these loads before then
 #pragma unroll
     for (int i = 0; i < ZQ; ++i) {
       if (threadIdx.x + kP1Threads * i < NQ) {
         const char* base =
             reinterpret_cast<const char*>(a.feat + (int64_t)(8 * wave_u + 2 * (kP1Threads / 16) * i) * P + p0);
-        zn[i][0] = k0 * *reinterpret_cast<const float*>(base + r0 + 4u * (uint32_t)x0);
-        zn[i][1] = k1 * *reinterpret_cast<const float*>(base + r0 + 4u * (uint32_t)x1);
-        zn[i][2] = k0 * *reinterpret_cast<const float*>(base + r1 + 4u * (uint32_t)x0);
-        zn[i][3] = k1 * *reinterpret_cast<const float*>(base + r1 + 4u * (uint32_t)x1);
+        zn[i][0] = *reinterpret_cast<const float*>(base + r0 + 4u * (uint32_t)x0);
+        zn[i][1] = *reinterpret_cast<const float*>(base + r0 + 4u * (uint32_t)x1);
+        zn[i][2] = *reinterpret_cast<const float*>(base + r1 + 4u * (uint32_t)x0);
+        zn[i][3] = *reinterpret_cast<const float*>(base + r1 + 4u * (uint32_t)x1);
       }
     }
   };
@@ -207,7 +208,10 @@ __global__ __launch_bounds__(kP1Threads) void decoder_pass1_kernel(DecArgs a) {
         const int c = zc0 + 2 * (kP1Threads / 16) * i;
         __bf16 hi[4], lo[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) split2(zn[i][e], hi[e], lo[e]);
+        for (int e = 0; e < 4; ++e) {
+          const bool in = p0 + zx + (e & 1) < P;
+          split2(in ? zn[i][e] : 0.f, hi[e], lo[e]);
+        }
         *reinterpret_cast<bf16x2*>(&s_zc[0][c][zx]) = bf16x2{hi[0], hi[1]};
         *reinterpret_cast<bf16x2*>(&s_zc[0][c + 1][zx]) = bf16x2{hi[2], hi[3]};
         *reinterpret_cast<bf16x2*>(&s_zc[1][c][zx]) = bf16x2{lo[0], lo[1]};
