@@ -33,6 +33,8 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kNB = 32;
 
@@ -613,7 +615,7 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
   __shared__ __attribute__((aligned(16))) unsigned char s_raw[kShared];
   float (*s_g)[GROW] = reinterpret_cast<float (*)[GROW]>(s_raw);
   __bf16 (*s_w)[NW][2][kNB][WROW] = reinterpret_cast<__bf16 (*)[NW][2][kNB][WROW]>(s_raw);   // [2]
-  __shared__ float s_gr[4][NT];
+  __shared__ __attribute__((aligned(16))) float s_gr[4][NT];
   __shared__ bf16x8 s_grb[NW][2][2][64];
 
   const bool walker = (int)threadIdx.x < NT;
@@ -825,6 +827,22 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
     load_ids(2);
   }
   __syncthreads();   // gradient slices consumed (the region now holds W), batch 0 staged
+  // The colour/depth gradient of each walker pixel as two-part bf16 (hi at
+  // .xy, lo at .zw) in the space of s_gr, which no one reads any more: one
+  // more k block of the GEMM1 pixel operand (see the colour step there).
+  uint4* const s_gc = reinterpret_cast<uint4*>(&s_gr[0][0]);
+  if (walker) {
+    const f32x2 g01 = {gr0, gr1}, g23 = {gr2, gr3};
+    const bf16x2 h01 = __builtin_convertvector(g01, bf16x2), h23 = __builtin_convertvector(g23, bf16x2);
+    const bf16x2 l01 = __builtin_convertvector(g01 - __builtin_convertvector(h01, f32x2), bf16x2);
+    const bf16x2 l23 = __builtin_convertvector(g23 - __builtin_convertvector(h23, f32x2), bf16x2);
+    s_gc[q] = make_uint4(__builtin_bit_cast(uint32_t, h01), __builtin_bit_cast(uint32_t, h23),
+                         __builtin_bit_cast(uint32_t, l01), __builtin_bit_cast(uint32_t, l23));
+    // each wave reads the entries of its own 64 pixels only
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
 
   // The two roles run separate loops with the same number of barriers, so
   // that the registers of one role are not live in the other's loop.
@@ -852,6 +870,29 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
               s1[pb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[0], g1(pb, s, 0), s1[pb], 0, 0, 0);
               s1[pb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[0], g1(pb, s, 1), s1[pb], 0, 0, 0);
               if constexpr (F32) s1[pb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[1], g1(pb, s, 0), s1[pb], 0, 0, 0);
+            }
+          }
+          // colour step: one more k block adds the colour and depth term
+          // c_i . (dL/dC, dL/dD) of every pair to S.  Gaussian row i holds
+          // (c_hi, c_lo) at k 0-7 and (c_hi, 0) at k 8-15, the pixel column
+          // (g_hi, g_hi) and (g_lo, 0), so the block sums c_hi g_hi + c_lo g_hi
+          // + c_hi g_lo, the two-part product without its smallest term.
+          {
+            const bool khi = lane >= 32;
+            const float4 c = s_rgb[b2][lane & 31];
+            const f32x2 c01 = {c.x, c.y}, c23 = {c.z, c.w};
+            const bf16x2 h01 = __builtin_convertvector(c01, bf16x2), h23 = __builtin_convertvector(c23, bf16x2);
+            const bf16x2 l01 = __builtin_convertvector(c01 - __builtin_convertvector(h01, f32x2), bf16x2);
+            const bf16x2 l23 = __builtin_convertvector(c23 - __builtin_convertvector(h23, f32x2), bf16x2);
+            const uint4 av = make_uint4(__builtin_bit_cast(uint32_t, h01), __builtin_bit_cast(uint32_t, h23),
+                                        khi ? 0u : __builtin_bit_cast(uint32_t, l01),
+                                        khi ? 0u : __builtin_bit_cast(uint32_t, l23));
+#pragma unroll
+            for (int pb = 0; pb < 2; ++pb) {
+              const uint4 g = s_gc[64 * wave + 32 * pb + (lane & 31)];
+              const uint4 bv = khi ? make_uint4(g.z, g.w, 0u, 0u) : make_uint4(g.x, g.y, g.x, g.y);
+              s1[pb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av),
+                                                               __builtin_bit_cast(bf16x8, bv), s1[pb], 0, 0, 0);
             }
           }
           float S[kNB];
@@ -894,23 +935,25 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
               float wg[GR];
 #pragma unroll
               for (int u = GR - 1; u >= 0; --u) {
-                const int i = gi * GR + u;
-                const float4 c = s_rgb[b2][i];
-                const float sv = S[i] + (((gr0 * c.x + gr1 * c.y) + gr2 * c.z) + gr3 * c.w);
+                const float sv = S[gi * GR + u];   // dL/d(c_i, f_i) . (c_i, f_i) at this pixel
                 const float Tn = T * inv[u];
                 const float w = al[u] * Tn;
-                const float da = Tn * sv - acc * inv[u];
+                const float da = inv[u] * __builtin_fmaf(T, sv, -acc);   // (T sv - acc) / (1 - alpha)
                 T = Tn;
                 acc = __builtin_fmaf(w, sv, acc);
                 wg[u] = w;
                 s_xm[wave][gq * GR + u][lane] = gx[u] * da;   // X = G dL/dalpha at this pixel
               }
+              // two-part bf16 split of the weights, two pairs per conversion
 #pragma unroll
-              for (int u = 0; u < GR; ++u) {
-                __bf16 wh, wl;
-                split2(wg[u], wh, wl);
-                s_w[b2][wave][0][gi * GR + u][lane] = wh;
-                s_w[b2][wave][1][gi * GR + u][lane] = wl;
+              for (int u = 0; u < GR; u += 2) {
+                const f32x2 w2 = {wg[u], wg[u + 1]};
+                const bf16x2 h2 = __builtin_convertvector(w2, bf16x2);
+                const bf16x2 l2 = __builtin_convertvector(w2 - __builtin_convertvector(h2, f32x2), bf16x2);
+                s_w[b2][wave][0][gi * GR + u][lane] = h2[0];
+                s_w[b2][wave][0][gi * GR + u + 1][lane] = h2[1];
+                s_w[b2][wave][1][gi * GR + u][lane] = l2[0];
+                s_w[b2][wave][1][gi * GR + u + 1][lane] = l2[1];
               }
             }
             // six pixel moments of X per Gaussian of the half: lane l sums 16
