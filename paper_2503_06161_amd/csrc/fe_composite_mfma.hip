@@ -361,6 +361,10 @@ void composite_fwd_mfma_kernel(MfmaArgs a) {
 // on the matrix cores and stage batch k+1.  Accumulator wave w owns the 64
 // pixels of walker wave w and all channel blocks, so every weight is split
 // into its three exact bf16 parts once, by the one wave that consumes it.
+// Colour and depth (eq. 7) ride along as one more channel block: its rows
+// 0-3, 4-7 and 8-11 hold the three exact bf16 parts of (r, g, b, depth) of
+// each Gaussian, so the block's three row groups sum to C = sum_i w_i c_i
+// with every product exact and float32 accumulation.
 // The roles need about half the registers each, so two waves share a SIMD.
 // One barrier per batch (the early-termination count); weights and records
 // are double-buffered, feature rows triple-buffered.
@@ -373,10 +377,11 @@ __device__ __forceinline__ void fwd_ws_tile(const MfmaArgs& a, const int tile) {
   __shared__ float2 s_xy[2][kNB];
   __shared__ float4 s_co[2][kNB];
   __shared__ float s_tg[2][kNB];
-  __shared__ float4 s_rgb[2][kNB];
   __shared__ uint2 s_box[2][kNB];             // packed (origin, extent)
+  // feature rows: channels 0..DP-1, then the colour block (12 used columns)
   __shared__ __attribute__((aligned(16))) __bf16 s_f[3][kNB][FROW];
   __shared__ __attribute__((aligned(16))) float s_w[2][NT][WROW];
+  __shared__ float s_T[NT];                    // final transmittance of each pixel
   __shared__ int s_any[2][NW][2];              // the chunk has a nonzero weight in the k step
   __shared__ int s_maxlast;
 
@@ -435,8 +440,15 @@ __device__ __forceinline__ void fwd_ws_tile(const MfmaArgs& a, const int tile) {
       const float4 cs = scale_conic(p_co);
       s_co[b2][q] = make_float4(cs.x, cs.y, cs.z, q < nb ? p_co.w : 0.f);
       s_tg[b2][q] = blend_cut(q < nb ? p_co.w : 0.f);
-      s_rgb[b2][q] = p_rgb;
       s_box[b2][q] = pack_box(p_box);
+      // colour block: exact three-part split of (r, g, b, depth)
+      uint32_t h0, m0, l0, h1, m1, l1;
+      split3_pair(p_rgb.x, p_rgb.y, h0, m0, l0);
+      split3_pair(p_rgb.z, p_rgb.w, h1, m1, l1);
+      __bf16* row = &s_f[b3][q][DP];
+      *reinterpret_cast<uint2*>(row) = make_uint2(h0, h1);
+      *reinterpret_cast<uint2*>(row + 4) = make_uint2(m0, m1);
+      *reinterpret_cast<uint2*>(row + 8) = make_uint2(l0, l1);
     }
 #pragma unroll
     for (int j = 0; j < FI; ++j) {
@@ -450,6 +462,7 @@ __device__ __forceinline__ void fwd_ws_tile(const MfmaArgs& a, const int tile) {
     }
   };
 
+  float colv[2][4];   // accumulators: colour and depth of pixels lane (< 32) of each 32-pixel block
   if (walker) {
     // ================= walkers =================
     // T < 0 marks a finished pixel (|T| is its final transmittance), and a
@@ -457,7 +470,6 @@ __device__ __forceinline__ void fwd_ws_tile(const MfmaArgs& a, const int tile) {
     // leaves T, the colour and the weights unchanged with no per-pair mask
     // logic, so the front-to-back chain is a few dependent VALU operations.
     float T = inside ? 1.0f : -1.0f;
-    float C0 = 0.f, C1 = 0.f, C2 = 0.f, C3 = 0.f;   // colour, depth
     int last = 0;
     for (int kk = 0;; ++kk) {
       const int k = __builtin_amdgcn_readfirstlane(kk);   // scalar: keeps the barrier loop uniform
@@ -496,11 +508,6 @@ __device__ __forceinline__ void fwd_ws_tile(const MfmaArgs& a, const int tile) {
             const bool stop = Tn < kTStop;             // also true once T < 0
             const float w = stop ? 0.f : al[u] * T;
             T = stop ? -fabsf(T) : Tn;
-            const float4 c = s_rgb[b2][16 * s + u];
-            C0 = __builtin_fmaf(w, c.x, C0);
-            C1 = __builtin_fmaf(w, c.y, C1);
-            C2 = __builtin_fmaf(w, c.z, C2);
-            C3 = __builtin_fmaf(w, c.w, C3);
             wv[u] = w;
             lrel = w != 0.f ? u + 1 : lrel;
           }
@@ -516,23 +523,22 @@ __device__ __forceinline__ void fwd_ws_tile(const MfmaArgs& a, const int tile) {
       }
     }
     T = fabsf(T);
-    const int64_t HW = (int64_t)a.W * a.H;
+    s_T[q] = T;
     if (inside) {
       const int64_t p = (int64_t)py * a.W + px;
-      a.out_rgb[p] = __builtin_fmaf(T, a.bg[0], C0);
-      a.out_rgb[HW + p] = __builtin_fmaf(T, a.bg[1], C1);
-      a.out_rgb[2 * HW + p] = __builtin_fmaf(T, a.bg[2], C2);
-      if (a.out_depth) a.out_depth[p] = C3;
       a.out_T[p] = T;
       a.out_n[p] = last;
     }
     if (last > 0) atomicMax(&s_maxlast, last);
   } else {
     // ================= accumulators =================
-    // acc[c][pb]: channels 32 c.. x pixels 64 wave + 32 pb..
-    f32x16 acc[CB][2];
+    // acc[c][pb]: channels 32 c.. x pixels 64 wave + 32 pb.. (c = CB: colour)
+    f32x16 acc[CB + 1][2];
 #pragma unroll
-    for (int c = 0; c < CB; ++c) acc[c][0] = acc[c][1] = f32x16{};
+    for (int c = 0; c <= CB; ++c) acc[c][0] = acc[c][1] = f32x16{};
+    // unused columns of the colour block: zero once (the staging writes 12)
+    for (int e = q; e < 3 * kNB * 5; e += NT)
+      *reinterpret_cast<uint2*>(&s_f[e / (5 * kNB)][(e / 5) % kNB][DP + 12 + 4 * (e % 5)]) = make_uint2(0u, 0u);
     load_ids(0);
     load_data();
     load_ids(1);
@@ -552,9 +558,9 @@ __device__ __forceinline__ void fwd_ws_tile(const MfmaArgs& a, const int tile) {
         for (int s = 0; s < kNB / 16; ++s) {
           // the flag is wave-uniform: a scalar branch keeps the barrier loop uniform
           if (!__builtin_amdgcn_readfirstlane(s_any[b2][wave][s])) continue;
-          bf16x8 fa[CB];
+          bf16x8 fa[CB + 1];
 #pragma unroll
-          for (int c = 0; c < CB; ++c) fa[c] = load_a_tr<FROW>(&s_f[b3][0][0], 16 * s, 32 * c, lane);
+          for (int c = 0; c <= CB; ++c) fa[c] = load_a_tr<FROW>(&s_f[b3][0][0], 16 * s, 32 * c, lane);
 #pragma unroll
           for (int pb = 0; pb < 2; ++pb) {
             const float* wr = &s_w[b2][64 * wave + 32 * pb + (lane & 31)][16 * s + 8 * (lane >> 5)];
@@ -571,7 +577,7 @@ __device__ __forceinline__ void fwd_ws_tile(const MfmaArgs& a, const int tile) {
               bw[2][j] = l;
             }
 #pragma unroll
-            for (int c = 0; c < CB; ++c) {
+            for (int c = 0; c <= CB; ++c) {
               f32x16 z = acc[c][pb];
 #pragma unroll
               for (int t = 0; t < 3; ++t)
@@ -606,12 +612,41 @@ __device__ __forceinline__ void fwd_ws_tile(const MfmaArgs& a, const int tile) {
           }
       }
     }
+    // colour block: rows 0-3 (c_hi parts) sit in v 0-3 of lanes 0-31, rows
+    // 4-7 (c_mid) in v 0-3 of lanes 32-63, rows 8-11 (c_lo) in v 4-7 of lanes 0-31
+#pragma unroll
+    for (int pb = 0; pb < 2; ++pb)
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        const float mid = __shfl_xor(acc[CB][pb][n], 32, 64);
+        colv[pb][n] = acc[CB][pb][n] + (mid + acc[CB][pb][4 + n]);
+      }
   }
-  // per-tile walk length (used by the backward to size its partial rows)
+  // per-tile walk length (used by the backward to size its partial rows);
+  // the walkers' final transmittance is in s_T
   __syncthreads();
   if (threadIdx.x == 0) {
     a.tile_maxlast[tile] = (uint32_t)s_maxlast;
     if (s_maxlast > 0) atomicAdd(&a.report[kRepRows], (unsigned long long)s_maxlast);
+  }
+  if (!walker) {
+    // colour image (the background behind the final transmittance)
+    const int64_t HW = (int64_t)a.W * a.H;
+#pragma unroll
+    for (int pb = 0; pb < 2; ++pb) {
+      const float* col = colv[pb];
+      const int lpo = 64 * wave + 32 * pb + (lane & 31);
+      const int ox = (tile % a.tiles_x) * a.tile_w + lpo % a.tile_w;
+      const int oy = (tile / a.tiles_x) * tile_h + lpo / a.tile_w;
+      if (lane < 32 && ox < a.W && oy < a.H) {
+        const int64_t p = (int64_t)oy * a.W + ox;
+        const float Tf = s_T[lpo];
+        a.out_rgb[p] = __builtin_fmaf(Tf, a.bg[0], col[0]);
+        a.out_rgb[HW + p] = __builtin_fmaf(Tf, a.bg[1], col[1]);
+        a.out_rgb[2 * HW + p] = __builtin_fmaf(Tf, a.bg[2], col[2]);
+        if (a.out_depth) a.out_depth[p] = col[3];
+      }
+    }
   }
 }
 
