@@ -48,11 +48,12 @@ __device__ __forceinline__ bool in_box(u16x2 p, uint2 box) {
   return __builtin_bit_cast(uint32_t, __builtin_elementwise_sub_sat(d, __builtin_bit_cast(u16x2, box.y))) == 0u;
 }
 
-// Binning: 256 threads x 4 Gaussians per workgroup; per-tile counters in
+// Binning: 1024 threads x 1 Gaussian per workgroup (16 waves, so that the
+// LDS-atomic -> store chains of the pair loop overlap); per-tile counters in
 // LDS up to kBinLdsTiles tiles; one workgroup of kBinOffThreads for the
 // offsets.
-constexpr int kBinThreads = 256;
-constexpr int kBinItems = 4;
+constexpr int kBinThreads = 1024;
+constexpr int kBinItems = 1;
 constexpr int kBinChunk = kBinThreads * kBinItems;      // 1024
 constexpr int kBinLdsTiles = 12288;
 constexpr int kBinOffThreads = 1024;
