@@ -40,6 +40,7 @@ bool compute_layout(const fe_config* cfg, const fe_camera* cam, int64_t n, Layou
   L->rel = take(L->tiles <= kBinLdsTiles ? 4 * (size_t)L->nblk * (size_t)L->tiles : 0);
   L->blk_sum = take(4 * (size_t)L->nblk);
   L->blk_off = take(4 * (size_t)L->nblk);
+  L->blk_vis = take(4 * (size_t)L->nblk);
   L->keys = take(8 * (size_t)L->cap);
   L->keys_b = take(8 * (size_t)L->cap);
   L->gauss = take(4 * (size_t)L->cap);
@@ -64,6 +65,7 @@ StateView make_view(const Layout& L, void* base) {
   v.rel = reinterpret_cast<uint32_t*>(b + L.rel);
   v.blk_sum = reinterpret_cast<uint32_t*>(b + L.blk_sum);
   v.blk_off = reinterpret_cast<uint32_t*>(b + L.blk_off);
+  v.blk_vis = reinterpret_cast<uint32_t*>(b + L.blk_vis);
   v.keys = reinterpret_cast<unsigned long long*>(b + L.keys);
   v.keys_b = reinterpret_cast<unsigned long long*>(b + L.keys_b);
   v.gauss = reinterpret_cast<uint32_t*>(b + L.gauss);

@@ -249,7 +249,6 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(ProjArgs a) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const bool in = i < a.n;
   bool nonfinite = false;
-  bool vis = false;
   if (in) {
     const CamConst& cc = a.cc;
     const float* mp = a.means + 3 * i;
@@ -310,7 +309,6 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(ProjArgs a) {
             const int ty0 = jj0 / a.tile_h, ty1 = jj1 / a.tile_h;
             count = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
             dkey = __float_as_uint((float)G.tz);
-            vis = true;
           }
         }
       }
@@ -322,13 +320,10 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(ProjArgs a) {
     a.v.dkey[i] = dkey;
     a.v.count[i] = count;
   }
-  // wave-aggregated report counters
-  const unsigned long long mv = __ballot(vis);
+  // wave-aggregated count of culled non-finite Gaussians (an atomic only
+  // where there are any); the visible count comes from the binning
   const unsigned long long mn = __ballot(nonfinite);
-  if (__lane_id() == 0) {
-    if (mv) atomicAdd(&a.v.report[kRepVisible], (unsigned long long)__popcll(mv));
-    if (mn) atomicAdd(&a.v.report[kRepNonFinite], (unsigned long long)__popcll(mn));
-  }
+  if (__lane_id() == 0 && mn) atomicAdd(&a.v.report[kRepNonFinite], (unsigned long long)__popcll(mn));
 }
 
 struct ProjBwdArgs {

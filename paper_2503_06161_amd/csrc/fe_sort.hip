@@ -6,8 +6,10 @@
 //   1. count: a workgroup takes 1024 consecutive Gaussians, counts the pairs
 //      it adds to every tile in LDS and reserves its share of each tile it
 //      touches with one global atomic; it also sums its Gaussians' pair
-//      counts;
-//   2. offsets (one workgroup): the key total and the capacity check, tile
+//      counts and counts its visible Gaussians;
+//   2. offsets (one workgroup): the visible and key totals (plain stores:
+//      thousands of atomics on one report word from every wave of the
+//      projection would serialise), the capacity check, tile
 //      starts (exclusive scan of the tile counts -> [start, end) ranges) and
 //      workgroup starts in the emit order (exclusive scan of the sums);
 //   3. place: the pair of Gaussian g and tile t gets the 64-bit key
@@ -114,6 +116,7 @@ struct BinArgs {
   uint32_t* rel;                // [nblk][tiles] a workgroup's first slot in a tile, from the tile start
   uint32_t* blk_sum;            // [nblk] pairs of a workgroup's Gaussians
   uint32_t* blk_off;            // [nblk] their first emit position
+  uint32_t* blk_vis;            // [nblk] their Gaussians with at least one pair
   uint2* ranges;                // [tiles]
   unsigned long long* report;
   unsigned long long* keys;     // [cap]
@@ -208,7 +211,13 @@ __global__ __launch_bounds__(kBinThreads) void bin_count_kernel(BinArgs a) {
     for (int t = threadIdx.x; t < a.tiles; t += kBinThreads) s_tile[t] = 0u;
   uint32_t c[kBinItems];
   const uint32_t total = bin_stage(a, s_off, s_rx, s_ry, s_warp, c, (int)blockIdx.x);   // its barriers order the zeroing
-  if (threadIdx.x == 0) a.blk_sum[blockIdx.x] = total;
+  uint32_t nvis = 0;
+#pragma unroll
+  for (int k = 0; k < kBinItems; ++k) nvis += (uint32_t)__syncthreads_count(c[k] != 0u);
+  if (threadIdx.x == 0) {
+    a.blk_sum[blockIdx.x] = total;
+    a.blk_vis[blockIdx.x] = nvis;
+  }
   bin_walk(s_off, s_rx, s_ry, total, a.tiles_x, [&](int, int t, uint32_t) {
     if constexpr (kLds)
       atomicAdd(&s_tile[t], 1u);
@@ -240,19 +249,31 @@ __global__ __launch_bounds__(kBinThreads) void bin_count_kernel(BinArgs a) {
 __global__ __launch_bounds__(kBinOffThreads) void bin_offsets_kernel(BinArgs a) {
   constexpr int NW = kBinOffThreads / 64;
   __shared__ uint32_t s_warp[NW];
-  __shared__ unsigned long long s_part[NW];
-  // key total over the tiles, in 64 bits (a tile count is at most n)
-  unsigned long long part = 0;
+  __shared__ unsigned long long s_part[NW], s_vpart[NW];
+  // key total over the tiles, in 64 bits (a tile count is at most n), and
+  // the visible Gaussians over the binning workgroups
+  unsigned long long part = 0, vpart = 0;
   for (int t = threadIdx.x; t < a.tiles; t += kBinOffThreads) part += a.tile_cnt[t];
-  for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
-  if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = part;
+  for (int b = threadIdx.x; b < a.nblk; b += kBinOffThreads) vpart += a.blk_vis[b];
+  for (int o = 32; o > 0; o >>= 1) {
+    part += __shfl_xor(part, o, 64);
+    vpart += __shfl_xor(vpart, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s_part[threadIdx.x >> 6] = part;
+    s_vpart[threadIdx.x >> 6] = vpart;
+  }
   __syncthreads();
-  unsigned long long tot64 = 0;
+  unsigned long long tot64 = 0, vis64 = 0;
 #pragma unroll
-  for (int w = 0; w < NW; ++w) tot64 += s_part[w];
+  for (int w = 0; w < NW; ++w) {
+    tot64 += s_part[w];
+    vis64 += s_vpart[w];
+  }
   tot64 = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(tot64 >> 32)) << 32) |
           __builtin_amdgcn_readfirstlane((uint32_t)tot64);
   if (threadIdx.x == 0) {
+    a.report[kRepVisible] = vis64;
     a.report[kRepKeys] = tot64;
     if (tot64 > (unsigned long long)a.cap) a.report[kRepStatus] = (unsigned long long)FE_ERR_KEY_OVERFLOW;
   }
@@ -696,6 +717,7 @@ hipError_t launch_sort_and_bin(const fe_config* cfg, const StateView& v, hipStre
   a.rel = v.rel;
   a.blk_sum = v.blk_sum;
   a.blk_off = v.blk_off;
+  a.blk_vis = v.blk_vis;
   a.ranges = v.ranges;
   a.report = v.report;
   a.keys = v.keys;
