@@ -90,6 +90,8 @@ def compare_projection(gs, orc, n):
     np.testing.assert_allclose(gs["conic_o"][vis, :3], con[vis], rtol=2e-7, atol=0)
     np.testing.assert_array_equal(gs["conic_o"][vis, 3], p["opacity"].numpy().astype(np.float32)[vis])
     np.testing.assert_allclose(gs["rgb"][vis, :3], rgb[vis], rtol=1e-6, atol=1e-7)
+    # the report's visible count (summed over the binning workgroups)
+    assert gs["report"]["n_visible"] == int(vis.sum()), (gs["report"]["n_visible"], int(vis.sum()))
     return int(vis.sum())
 
 
