@@ -350,10 +350,66 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjBwdArgs a) {
   if (i >= a.n) return;
   constexpr int K = (L + 1) * (L + 1);
   double gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gop = 0.0;
-  double gsh[K * 3];
-  for (int k = 0; k < K * 3; ++k) gsh[k] = 0.0;
+  // dL/dsh[k][ch] = Y_k * gact[ch] (zero for a culled Gaussian), formed at the store
+  double Y[16], gact[3] = {0.0, 0.0, 0.0};
+  for (int k = 0; k < 16; ++k) Y[k] = 0.0;
   double gu = 0.0, gv = 0.0;
-  if (a.count[i] > 0) {
+  auto put = [&](float* p, double val) {
+    if (a.accumulate) *p += (float)val; else *p = (float)val;
+  };
+  const bool active = a.count[i] > 0;
+  if (active) {
+    const CamConst& cc = a.cc;
+    const float* mp = a.means + 3 * i;
+    const float* g2 = a.grad2d + 12 * i;
+    const double gcol[3] = {g2[6], g2[7], g2[8]};
+    // colour first (the view direction does not need the geometry), so
+    // that its registers are free before the geometry's
+    const double dx = (double)mp[0] - cc.campos[0];
+    const double dy = (double)mp[1] - cc.campos[1];
+    const double dz = (double)mp[2] - cc.campos[2];
+    const double dn = sqrt(((dx * dx + dy * dy) + dz * dz));
+    const double ux = dx / dn, uy = dy / dn, uz = dz / dn;
+    sh_basis<L>(ux, uy, uz, Y);
+    float shr[3 * K];
+    load_sh_row<L, ShT>(a.sh, i, shr);
+    // the clamp at 0 passes the gradient of a channel whose raw value is >= 0
+    for (int ch = 0; ch < 3; ++ch) {
+      double raw = 0.0;
+      for (int k = 0; k < K; ++k) raw += (double)shr[k * 3 + ch] * Y[k];
+      raw += 0.5;
+      gact[ch] = raw >= 0.0 ? gcol[ch] : 0.0;
+    }
+    // direction gradient of sum_ch gact_ch raw_ch: one basis derivative of
+    // the channel-combined coefficients
+    double cf[16];
+    for (int k = 0; k < 16; ++k) cf[k] = 0.0;
+    for (int k = 0; k < K; ++k)
+      cf[k] = (gact[0] * (double)shr[k * 3] + gact[1] * (double)shr[k * 3 + 1]) + gact[2] * (double)shr[k * 3 + 2];
+    double gdx, gdy, gdz;
+    sh_basis_grad<L>(ux, uy, uz, cf, gdx, gdy, gdz);
+    const double dd = ux * gdx + uy * gdy + uz * gdz;
+    const double idn = 1.0 / dn;
+    gm[0] += (gdx - ux * dd) * idn;
+    gm[1] += (gdy - uy * dd) * idn;
+    gm[2] += (gdz - uz * dd) * idn;
+  }
+  if constexpr (L == 3) {
+    float4* q = reinterpret_cast<float4*>(a.g_sh + i * K * 3);
+    auto gsh = [&](int e) { return (float)(Y[e / 3] * gact[e % 3]); };
+#pragma unroll
+    for (int v = 0; v < K * 3 / 4; ++v) {
+      float4 o = make_float4(gsh(4 * v), gsh(4 * v + 1), gsh(4 * v + 2), gsh(4 * v + 3));
+      if (a.accumulate) {
+        const float4 p = q[v];
+        o.x += p.x; o.y += p.y; o.z += p.z; o.w += p.w;
+      }
+      q[v] = o;
+    }
+  } else {
+    for (int k = 0; k < K * 3; ++k) put(a.g_sh + i * K * 3 + k, Y[k / 3] * gact[k % 3]);
+  }
+  if (active) {
     const CamConst& cc = a.cc;
     const float* mp = a.means + 3 * i;
     const float* sp = a.scales + 3 * i;
@@ -363,12 +419,12 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjBwdArgs a) {
     gv = g2[1];
     const double gA = g2[2], gB = g2[3], gC = g2[4];
     gop = g2[5];
-    const double gcol[3] = {g2[6], g2[7], g2[8]};
     Geo G;
     geometry(cc, mp, sp, qp, G);
     // conic -> Sigma':  dL/dSigma' = -M GM M  with M the conic matrix and
     // GM the symmetric gradient (off-diagonal gB / 2)
-    const double A = G.c / G.det, B = -G.b / G.det, C = G.a / G.det;
+    const double idet = 1.0 / G.det;
+    const double A = G.c * idet, B = -G.b * idet, C = G.a * idet;
     const double hB = 0.5 * gB;
     const double P00 = gA * A + hB * B, P01 = gA * B + hB * C;
     const double P10 = hB * A + gC * B, P11 = hB * B + gC * C;
@@ -396,32 +452,32 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjBwdArgs a) {
       return dT[r * 3 + 0] * cc.R[b * 3 + 0] + dT[r * 3 + 1] * cc.R[b * 3 + 1] + dT[r * 3 + 2] * cc.R[b * 3 + 2];
     };
     const double dj00 = dJ(0, 0), dj02 = dJ(0, 2), dj11 = dJ(1, 1), dj12 = dJ(1, 2);
-    const double tz = G.tz, tz2 = tz * tz, tz3 = tz2 * tz;
+    const double itz = 1.0 / G.tz, itz2 = itz * itz, itz3 = itz2 * itz;
     double gtx = 0.0, gty = 0.0, gtz = 0.0;
-    gtz += -cc.fx / tz2 * dj00 - cc.fy / tz2 * dj11;
+    gtz += -cc.fx * itz2 * dj00 - cc.fy * itz2 * dj11;
     if (!G.clampx) {
-      gtx += -cc.fx / tz2 * dj02;
-      gtz += 2.0 * cc.fx * G.tx / tz3 * dj02;
+      gtx += -cc.fx * itz2 * dj02;
+      gtz += 2.0 * cc.fx * G.tx * itz3 * dj02;
     } else {
       const double xc = fmin(fmax(G.xr, -cc.limx), cc.limx);
-      gtz += cc.fx * xc / tz2 * dj02;
+      gtz += cc.fx * xc * itz2 * dj02;
     }
     if (!G.clampy) {
-      gty += -cc.fy / tz2 * dj12;
-      gtz += 2.0 * cc.fy * G.ty / tz3 * dj12;
+      gty += -cc.fy * itz2 * dj12;
+      gtz += 2.0 * cc.fy * G.ty * itz3 * dj12;
     } else {
       const double yc = fmin(fmax(G.yr, -cc.limy), cc.limy);
-      gtz += cc.fy * yc / tz2 * dj12;
+      gtz += cc.fy * yc * itz2 * dj12;
     }
     // pixel position
-    gtx += cc.fx / tz * gu;
-    gtz += -cc.fx * G.tx / tz2 * gu;
-    gty += cc.fy / tz * gv;
-    gtz += -cc.fy * G.ty / tz2 * gv;
+    gtx += cc.fx * itz * gu;
+    gtz += -cc.fx * G.tx * itz2 * gu;
+    gty += cc.fy * itz * gv;
+    gtz += -cc.fy * G.ty * itz2 * gv;
     // depth image: d(depth)/d(tz) = 1
     gtz += (double)g2[9];
     // t = W mu + t_c
-    for (int k = 0; k < 3; ++k) gm[k] = cc.R[0 * 3 + k] * gtx + cc.R[1 * 3 + k] * gty + cc.R[2 * 3 + k] * gtz;
+    for (int k = 0; k < 3; ++k) gm[k] += cc.R[0 * 3 + k] * gtx + cc.R[1 * 3 + k] * gty + cc.R[2 * 3 + k] * gtz;
     // Sigma = M M^T, M = R diag(s):  dM = 2 dSigma M
     const double* R = G.R;
     double M[9];
@@ -445,64 +501,16 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjBwdArgs a) {
     const double gz = 2.0 * (-2.0 * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.0 * z * dR[4] +
                              y * dR[5] + x * dR[6] + y * dR[7]);
     const double dot = w * gw + x * gx + y * gy + z * gz;
-    gq[0] = (gw - w * dot) / G.qn;
-    gq[1] = (gx - x * dot) / G.qn;
-    gq[2] = (gy - y * dot) / G.qn;
-    gq[3] = (gz - z * dot) / G.qn;
-    // colour
-    const double dx = (double)mp[0] - cc.campos[0];
-    const double dy = (double)mp[1] - cc.campos[1];
-    const double dz = (double)mp[2] - cc.campos[2];
-    const double dn = sqrt(((dx * dx + dy * dy) + dz * dz));
-    const double ux = dx / dn, uy = dy / dn, uz = dz / dn;
-    double Y[16];
-    sh_basis<L>(ux, uy, uz, Y);
-    float shr[3 * K];
-    load_sh_row<L, ShT>(a.sh, i, shr);
-    double gdx = 0.0, gdy = 0.0, gdz = 0.0;
-    for (int ch = 0; ch < 3; ++ch) {
-      double raw = 0.0;
-      double cf[16];
-      for (int k = 0; k < K; ++k) {
-        cf[k] = shr[k * 3 + ch];
-        raw += cf[k] * Y[k];
-      }
-      raw += 0.5;
-      if (raw >= 0.0 && gcol[ch] != 0.0) {
-        for (int k = 0; k < K; ++k) gsh[k * 3 + ch] = Y[k] * gcol[ch];
-        double ex, ey, ez;
-        sh_basis_grad<L>(ux, uy, uz, cf, ex, ey, ez);
-        gdx += gcol[ch] * ex;
-        gdy += gcol[ch] * ey;
-        gdz += gcol[ch] * ez;
-      }
-    }
-    const double dd = ux * gdx + uy * gdy + uz * gdz;
-    gm[0] += (gdx - ux * dd) / dn;
-    gm[1] += (gdy - uy * dd) / dn;
-    gm[2] += (gdz - uz * dd) / dn;
+    const double iqn = 1.0 / G.qn;
+    gq[0] = (gw - w * dot) * iqn;
+    gq[1] = (gx - x * dot) * iqn;
+    gq[2] = (gy - y * dot) * iqn;
+    gq[3] = (gz - z * dot) * iqn;
   }
-  auto put = [&](float* p, double val) {
-    if (a.accumulate) *p += (float)val; else *p = (float)val;
-  };
   for (int k = 0; k < 3; ++k) put(a.g_means + 3 * i + k, gm[k]);
   for (int k = 0; k < 3; ++k) put(a.g_scales + 3 * i + k, gs[k]);
   for (int k = 0; k < 4; ++k) put(a.g_quats + 4 * i + k, gq[k]);
   put(a.g_opacity + i, gop);
-  if constexpr (L == 3) {
-    float4* q = reinterpret_cast<float4*>(a.g_sh + i * K * 3);
-#pragma unroll
-    for (int v = 0; v < K * 3 / 4; ++v) {
-      float4 o = make_float4((float)gsh[4 * v], (float)gsh[4 * v + 1], (float)gsh[4 * v + 2], (float)gsh[4 * v + 3]);
-      if (a.accumulate) {
-        const float4 p = q[v];
-        o.x += p.x; o.y += p.y; o.z += p.z; o.w += p.w;
-      }
-      q[v] = o;
-    }
-  } else {
-    for (int k = 0; k < K * 3; ++k) put(a.g_sh + i * K * 3 + k, gsh[k]);
-  }
   if (a.g_means2d) {
     put(a.g_means2d + 2 * i, gu);
     put(a.g_means2d + 2 * i + 1, gv);
