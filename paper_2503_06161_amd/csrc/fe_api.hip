@@ -48,6 +48,7 @@ bool compute_layout(const fe_config* cfg, const fe_camera* cam, int64_t n, Layou
   L->gofe = take(4 * (size_t)L->cap);
   L->epos = take(4 * (size_t)L->cap);
   L->eoff = take(4 * n);
+  L->tile_order = take(4 * (size_t)L->tiles);
   L->total = o;
   return true;
 }
@@ -75,6 +76,7 @@ StateView make_view(const Layout& L, void* base) {
   v.gofe = reinterpret_cast<uint32_t*>(b + L.gofe);
   v.epos = reinterpret_cast<uint32_t*>(b + L.epos);
   v.eoff = reinterpret_cast<uint32_t*>(b + L.eoff);
+  v.tile_order = reinterpret_cast<uint32_t*>(b + L.tile_order);
   v.n = L.n;
   v.cap = L.cap;
   v.tiles_x = L.tiles_x;

@@ -81,6 +81,7 @@ struct StateView {
   uint32_t* blk_sum;        // [nblk]
   uint32_t* blk_off;        // [nblk]
   uint32_t* blk_vis;        // [nblk] Gaussians of a binning workgroup with at least one key
+  uint32_t* tile_order;     // [tiles] tiles by list length, longest first (the per-tile sort's launch order)
   unsigned long long* keys;     // [cap] depth bits << 32 | emit position
   unsigned long long* keys_b;   // [cap] merge buffer of the per-tile sort
   uint32_t* gauss;          // [cap] Gaussian index of each sorted pair
@@ -100,7 +101,7 @@ struct StateView {
 struct Layout {
   size_t total;
   size_t report, tile_cnt, ranges, xy, conic_o, rgb, box, dkey, count, rel, blk_sum, blk_off, blk_vis;
-  size_t keys, keys_b, gauss, tile_maxlast, gofe, epos, eoff;
+  size_t keys, keys_b, gauss, tile_maxlast, gofe, epos, eoff, tile_order;
   int64_t n, cap;
   int32_t tiles_x, tiles_y, tiles, nblk;
 };

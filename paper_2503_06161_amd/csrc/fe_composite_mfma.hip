@@ -488,7 +488,7 @@ __device__ __forceinline__ void fwd_ws_tile(const MfmaArgs& a, const int tile) {
         if (wave_live) {
           // alpha of the 16 pairs, independent of each other (padding
           // entries of the batch carry opacity 0 and are skipped here)
-          float al[16];
+          float al[16], om[16];
 #pragma unroll
           for (int u = 0; u < 16; ++u) {
             const int i = 16 * s + u;
@@ -499,14 +499,16 @@ __device__ __forceinline__ void fwd_ws_tile(const MfmaArgs& a, const int tile) {
             const bool inb = in_box(pp, s_box[b2][i]);
             const float alpha = fminf(kAlphaMax, co.w * __builtin_amdgcn_exp2f(qs));
             al[u] = (inb & (qs >= s_tg[b2][i])) ? alpha : 0.f;
+            om[u] = 1.0f - al[u];
           }
           // front-to-back transmittance chain
 #pragma unroll
           for (int u = 0; u < 16; ++u) {
-            const float w0 = al[u] * T;
-            const float Tn = T - w0;                   // T (1 - alpha)
+            // T (1 - alpha) as every forward kernel forms it, so that the stop
+            // decisions, final_T and n_contrib are the same in all of them
+            const float Tn = T * om[u];
             const bool stop = Tn < kTStop;             // also true once T < 0
-            const float w = stop ? 0.f : w0;
+            const float w = stop ? 0.f : al[u] * T;
             T = stop ? -fabsf(T) : Tn;
             wv[u] = w;
             lrel = w != 0.f ? u + 1 : lrel;

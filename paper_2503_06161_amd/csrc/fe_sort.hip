@@ -117,6 +117,7 @@ struct BinArgs {
   uint32_t* blk_sum;            // [nblk] pairs of a workgroup's Gaussians
   uint32_t* blk_off;            // [nblk] their first emit position
   uint32_t* blk_vis;            // [nblk] their Gaussians with at least one pair
+  uint32_t* tile_order;         // [tiles] tiles by list length, longest first
   uint2* ranges;                // [tiles]
   unsigned long long* report;
   unsigned long long* keys;     // [cap]
@@ -278,7 +279,13 @@ __global__ __launch_bounds__(kBinOffThreads) void bin_offsets_kernel(BinArgs a) 
     if (tot64 > (unsigned long long)a.cap) a.report[kRepStatus] = (unsigned long long)FE_ERR_KEY_OVERFLOW;
   }
   if (tot64 > (unsigned long long)a.cap) return;   // ranges stay empty; nothing is placed
-  // tile ranges; the tile counts become the tiles' first free slots
+  // tile ranges; the tile counts become the tiles' first free slots.  The
+  // lengths are also counted by floor(log2) class (class 0: empty) for the
+  // launch order of the per-tile sort
+  __shared__ uint32_t s_cls[33];
+  if (threadIdx.x < 33) s_cls[threadIdx.x] = 0u;
+  __syncthreads();
+  auto len_class = [](uint32_t c) { return c ? 32 - __clz((int)c) : 0; };
   constexpr int per = 4;
   uint32_t carry = 0;
   for (int base = 0; base < a.tiles; base += kBinOffThreads * per) {
@@ -296,10 +303,26 @@ __global__ __launch_bounds__(kBinOffThreads) void bin_offsets_kernel(BinArgs a) 
       if (i0 + k < a.tiles) {
         a.ranges[i0 + k] = make_uint2(o, o + c[k]);
         a.tile_cnt[i0 + k] = o;
+        atomicAdd(&s_cls[len_class(c[k])], 1u);
       }
       o += c[k];
     }
     carry += step;
+  }
+  // longest class first: a class's first slot is the count of the longer classes
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (int b = 32; b >= 0; --b) {
+      const uint32_t cb = s_cls[b];
+      s_cls[b] = acc;
+      acc += cb;
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < a.tiles; t += kBinOffThreads) {
+    const uint2 r = a.ranges[t];   // written above by this workgroup
+    a.tile_order[atomicAdd(&s_cls[len_class(r.y - r.x)], 1u)] = (uint32_t)t;
   }
   // first emit position of each workgroup's Gaussians
   carry = 0;
@@ -454,6 +477,7 @@ struct TileSortArgs {
   unsigned long long* keys_b;   // [cap] merge buffer for lists longer than kTsCap
   const uint32_t* gofe;
   const uint2* ranges;
+  const uint32_t* order;        // [tiles] launch order (longest lists first)
   const unsigned long long* report;
   uint32_t* gauss;              // [cap] Gaussian index of each sorted pair
   uint32_t* epos;               // [cap] its emit position
@@ -577,7 +601,9 @@ __global__ __launch_bounds__(kTsThreads, 4) void tile_sort_kernel(TileSortArgs a
   __shared__ uint32_t s_b[kTsCap / 4];
   __shared__ uint32_t s_red[4 * (kTsThreads / 64)];
   if (a.report[kRepKeys] > (unsigned long long)a.cap) return;
-  const uint2 rg = uniform_u2(a.ranges[blockIdx.x]);
+  // the longest lists are sorted first, so that they do not start last
+  const uint32_t tile = __builtin_amdgcn_readfirstlane(a.order[blockIdx.x]);
+  const uint2 rg = uniform_u2(a.ranges[tile]);
   const int n = (int)(rg.y - rg.x);
   if (n <= 0) return;
   unsigned long long* seg = a.keys + rg.x;
@@ -718,6 +744,7 @@ hipError_t launch_sort_and_bin(const fe_config* cfg, const StateView& v, hipStre
   a.blk_sum = v.blk_sum;
   a.blk_off = v.blk_off;
   a.blk_vis = v.blk_vis;
+  a.tile_order = v.tile_order;
   a.ranges = v.ranges;
   a.report = v.report;
   a.keys = v.keys;
@@ -741,7 +768,7 @@ hipError_t launch_sort_and_bin(const fe_config* cfg, const StateView& v, hipStre
     hipLaunchKernelGGL(bin_place_kernel<true>, dim3(v.nblk), dim3(kBinThreads), lds_bytes, s, a);
   else
     hipLaunchKernelGGL(bin_place_kernel<false>, dim3(v.nblk), dim3(kBinThreads), 0, s, a);
-  TileSortArgs t{v.keys, v.keys_b, v.gofe, v.ranges, v.report, v.gauss, v.epos, v.cap};
+  TileSortArgs t{v.keys, v.keys_b, v.gofe, v.ranges, v.tile_order, v.report, v.gauss, v.epos, v.cap};
   hipLaunchKernelGGL(tile_sort_kernel, dim3(v.tiles), dim3(kTsThreads), 0, s, t);
   return hipGetLastError();
 }

@@ -37,7 +37,13 @@ def test_candidates_agree_and_choice_is_cached(tmp_path, monkeypatch):
         f = rast.render_forward(d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["feat"], cam, s2)
         if ref is None:
             ref = f
-        assert torch.equal(f.rgb, ref.rgb) and torch.equal(f.final_T, ref.final_T)
+        # the transmittance chain is bit-identical in every form (n_contrib is a
+        # position in the tile's list, so it depends on the tile shape); the
+        # wave-specialized forward sums colour and features on the matrix cores
+        # (each product exact, float32 sums in the hardware's order), so those
+        # agree with the vector-ALU sums to rounding
+        assert torch.equal(f.final_T, ref.final_T)
+        torch.testing.assert_close(f.rgb, ref.rgb, rtol=0, atol=2e-6)
         torch.testing.assert_close(f.feat, ref.feat, rtol=0, atol=2e-6)
     g_rgb = torch.zeros(3, 64, 96, device="cuda")
     g_feat = torch.full((32, 64, 96), 1e-3, device="cuda")
