@@ -1013,14 +1013,24 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
               mom[4] = __builtin_fmaf(ya, ma, yb * mb);
               mom[5] = __builtin_fmaf(ya * ya, r0[0], yb * yb * r0[1]);
             }
+            // sums over the wave's four 16-lane quarters with lane swaps: the
+            // 32-lane swap of (moment k, moment k + 3) leaves the half sums of
+            // k in lanes 0-31 and of k + 3 in lanes 32-63; the 16-lane swap of
+            // two such registers finishes four moments, one per 16-lane row
+            float R[3];
 #pragma unroll
-            for (int k = 0; k < 6; ++k) {
-              mom[k] += __shfl_xor(mom[k], 16, 64);
-              mom[k] += __shfl_xor(mom[k], 32, 64);
+            for (int k = 0; k < 3; ++k) {
+              const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(mom[k]), __float_as_uint(mom[k + 3]),
+                                                              false, false);
+              R[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
             }
-            if (lane < 16)
-#pragma unroll
-              for (int k = 0; k < 6; ++k) s_mom[b2][wave][k][16 * h + lane] = mom[k];
+            const auto p01 = __builtin_amdgcn_permlane16_swap(__float_as_uint(R[0]), __float_as_uint(R[1]), false, false);
+            const auto p22 = __builtin_amdgcn_permlane16_swap(__float_as_uint(R[2]), __float_as_uint(R[2]), false, false);
+            const float mA = __uint_as_float(p01[0]) + __uint_as_float(p01[1]);   // rows: moments 0, 1, 3, 4
+            const float mB = __uint_as_float(p22[0]) + __uint_as_float(p22[1]);   // rows 0-1: moment 2; 2-3: 5
+            const int row = lane >> 4;
+            s_mom[b2][wave][row < 2 ? row : row + 1][16 * h + (lane & 15)] = mA;
+            if ((lane & 16) == 0) s_mom[b2][wave][row == 0 ? 2 : 5][16 * h + (lane & 15)] = mB;
             // s_xm is rewritten by the next half only after every lane has read it
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
