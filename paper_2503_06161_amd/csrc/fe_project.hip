@@ -12,7 +12,7 @@
 // in a fixed order with contraction disabled, so the keys are reproducible
 // bit for bit by any implementation that evaluates the same expressions.
 //
-// Backward (one thread per Gaussian, float64): chain rule from the
+// Backward (one thread per Gaussian, float32): chain rule from the
 // screen-space gradients (u, v, conic, opacity, colour) through the conic
 // inverse, eq. (9), eq. (2), the quaternion normalisation and the SH basis.
 // The skip/stop decisions and the sort order are piecewise constant; the
@@ -39,73 +39,72 @@ constexpr double kC3g = 0.4570457994644658;   // sqrt(21 / (2 pi)) / 4
 constexpr double kC3h = 0.3731763325901154;   // sqrt(7 / pi) / 4
 constexpr double kC3i = 1.445305721320277;    // sqrt(105 / pi) / 4
 
-template <int L>
-__device__ __forceinline__ void sh_basis(double x, double y, double z, double* Y) {
-  Y[0] = kC0;
+template <int L, typename T>
+__device__ __forceinline__ void sh_basis(T x, T y, T z, T* Y) {
+  Y[0] = T(kC0);
   if constexpr (L >= 1) {
-    Y[1] = kC1 * y;
-    Y[2] = kC1 * z;
-    Y[3] = kC1 * x;
+    Y[1] = T(kC1) * y;
+    Y[2] = T(kC1) * z;
+    Y[3] = T(kC1) * x;
   }
   if constexpr (L >= 2) {
-    const double xx = x * x, yy = y * y, zz = z * z;
-    Y[4] = kC2a * (x * y);
-    Y[5] = kC2a * (y * z);
-    Y[6] = kC2b * (3.0 * zz - 1.0);
-    Y[7] = kC2a * (x * z);
-    Y[8] = kC2c * (xx - yy);
+    const T xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = T(kC2a) * (x * y);
+    Y[5] = T(kC2a) * (y * z);
+    Y[6] = T(kC2b) * (T(3.0) * zz - T(1.0));
+    Y[7] = T(kC2a) * (x * z);
+    Y[8] = T(kC2c) * (xx - yy);
     if constexpr (L >= 3) {
-      Y[9] = kC3e * y * (3.0 * xx - yy);
-      Y[10] = kC3f * x * y * z;
-      Y[11] = kC3g * y * (5.0 * zz - 1.0);
-      Y[12] = kC3h * z * (5.0 * zz - 3.0);
-      Y[13] = kC3g * x * (5.0 * zz - 1.0);
-      Y[14] = kC3i * z * (xx - yy);
-      Y[15] = kC3e * x * (xx - 3.0 * yy);
+      Y[9] = T(kC3e) * y * (T(3.0) * xx - yy);
+      Y[10] = T(kC3f) * x * y * z;
+      Y[11] = T(kC3g) * y * (T(5.0) * zz - T(1.0));
+      Y[12] = T(kC3h) * z * (T(5.0) * zz - T(3.0));
+      Y[13] = T(kC3g) * x * (T(5.0) * zz - T(1.0));
+      Y[14] = T(kC3i) * z * (xx - yy);
+      Y[15] = T(kC3e) * x * (xx - T(3.0) * yy);
     }
   }
 }
 
 // Gradient of sum_k c_k Y_k with respect to the direction components,
 // accumulated into (gx, gy, gz).
-template <int L>
-__device__ __forceinline__ void sh_basis_grad(double x, double y, double z, const double* c,
-                                              double& gx, double& gy, double& gz) {
-  gx = 0.0;
-  gy = 0.0;
-  gz = 0.0;
+template <int L, typename T>
+__device__ __forceinline__ void sh_basis_grad(T x, T y, T z, const T* c, T& gx, T& gy, T& gz) {
+  gx = T(0.0);
+  gy = T(0.0);
+  gz = T(0.0);
   if constexpr (L >= 1) {
-    gy += kC1 * c[1];
-    gz += kC1 * c[2];
-    gx += kC1 * c[3];
+    gy += T(kC1) * c[1];
+    gz += T(kC1) * c[2];
+    gx += T(kC1) * c[3];
   }
   if constexpr (L >= 2) {
-    gx += kC2a * y * c[4];
-    gy += kC2a * x * c[4];
-    gy += kC2a * z * c[5];
-    gz += kC2a * y * c[5];
-    gz += 6.0 * kC2b * z * c[6];
-    gx += kC2a * z * c[7];
-    gz += kC2a * x * c[7];
-    gx += 2.0 * kC2c * x * c[8];
-    gy -= 2.0 * kC2c * y * c[8];
+    gx += T(kC2a) * y * c[4];
+    gy += T(kC2a) * x * c[4];
+    gy += T(kC2a) * z * c[5];
+    gz += T(kC2a) * y * c[5];
+    gz += T(6.0) * T(kC2b) * z * c[6];
+    gx += T(kC2a) * z * c[7];
+    gz += T(kC2a) * x * c[7];
+    gx += T(2.0) * T(kC2c) * x * c[8];
+    gy -= T(2.0) * T(kC2c) * y * c[8];
     if constexpr (L >= 3) {
-      const double xx = x * x, yy = y * y, zz = z * z;
-      gx += 6.0 * kC3e * x * y * c[9];
-      gy += kC3e * (3.0 * xx - 3.0 * yy) * c[9];
-      gx += kC3f * y * z * c[10];
-      gy += kC3f * x * z * c[10];
-      gz += kC3f * x * y * c[10];
-      gy += kC3g * (5.0 * zz - 1.0) * c[11];
-      gz += 10.0 * kC3g * y * z * c[11];
-      gz += kC3h * (15.0 * zz - 3.0) * c[12];
-      gx += kC3g * (5.0 * zz - 1.0) * c[13];
-      gz += 10.0 * kC3g * x * z * c[13];
-      gx += 2.0 * kC3i * x * z * c[14];
-      gy -= 2.0 * kC3i * y * z * c[14];
-      gz += kC3i * (xx - yy) * c[14];
-      gx += kC3e * (3.0 * xx - 3.0 * yy) * c[15];
-      gy -= 6.0 * kC3e * x * y * c[15];
+      const T xx = x * x, yy = y * y, zz = z * z;
+      gx += T(6.0) * T(kC3e) * x * y * c[9];
+      gy += T(kC3e) * (T(3.0) * xx - T(3.0) * yy) * c[9];
+      gx += T(kC3f) * y * z * c[10];
+      gy += T(kC3f) * x * z * c[10];
+      gz += T(kC3f) * x * y * c[10];
+      gy += T(kC3g) * (T(5.0) * zz - T(1.0)) * c[11];
+      gz += T(10.0) * T(kC3g) * y * z * c[11];
+      gz += T(kC3h) * (T(15.0) * zz - T(3.0)) * c[12];
+      gx += T(kC3g) * (T(5.0) * zz - T(1.0)) * c[13];
+      gz += T(10.0) * T(kC3g) * x * z * c[13];
+      gx += T(2.0) * T(kC3i) * x * z * c[14];
+      gy -= T(2.0) * T(kC3i) * y * z * c[14];
+      gz += T(kC3i) * (xx - yy) * c[14];
+      gx += T(kC3e) * (T(3.0) * xx - T(3.0) * yy) * c[15];
+      gy -= T(6.0) * T(kC3e) * x * y * c[15];
     }
   }
 }
@@ -156,44 +155,47 @@ struct ProjArgs {
   StateView v;
 };
 
-// Geometry shared by the forward and the backward; everything in float64.
-struct Geo {
-  double tx, ty, tz;
-  double qw, qx, qy, qz, qn;   // normalised quaternion and the input norm
-  double R[9];
-  double s[3];
-  double Sig[6];               // xx xy xz yy yz zz
-  double xr, yr;
+// Geometry shared by the forward (float64: it decides keys and boxes) and the
+// backward (float32: gradients only), in the same expressions.
+template <typename T>
+struct GeoT {
+  T tx, ty, tz;
+  T qw, qx, qy, qz, qn;   // normalised quaternion and the input norm
+  T R[9];
+  T s[3];
+  T Sig[6];               // xx xy xz yy yz zz
+  T xr, yr;
   bool clampx, clampy;
-  double j00, j02, j11, j12;
-  double Tm[6];                // 2x3 row-major
-  double a, b, c;              // Sigma' (dilated)
-  double det;
-  double u, v;
+  T j00, j02, j11, j12;
+  T Tm[6];                // 2x3 row-major
+  T a, b, c;              // Sigma' (dilated)
+  T det;
+  T u, v;
 };
 
+template <typename T>
 __device__ __forceinline__ void geometry(const CamConst& cc, const float* mp, const float* sp,
-                                         const float* qp, Geo& G) {
-  const double x = mp[0], y = mp[1], z = mp[2];
-  G.tx = ((cc.R[0] * x + cc.R[1] * y) + cc.R[2] * z) + cc.t[0];
-  G.ty = ((cc.R[3] * x + cc.R[4] * y) + cc.R[5] * z) + cc.t[1];
-  G.tz = ((cc.R[6] * x + cc.R[7] * y) + cc.R[8] * z) + cc.t[2];
-  const double w0 = qp[0], x0 = qp[1], y0 = qp[2], z0 = qp[3];
+                                         const float* qp, GeoT<T>& G) {
+  const T x = mp[0], y = mp[1], z = mp[2];
+  G.tx = ((T(cc.R[0]) * x + T(cc.R[1]) * y) + T(cc.R[2]) * z) + T(cc.t[0]);
+  G.ty = ((T(cc.R[3]) * x + T(cc.R[4]) * y) + T(cc.R[5]) * z) + T(cc.t[1]);
+  G.tz = ((T(cc.R[6]) * x + T(cc.R[7]) * y) + T(cc.R[8]) * z) + T(cc.t[2]);
+  const T w0 = qp[0], x0 = qp[1], y0 = qp[2], z0 = qp[3];
   G.qn = sqrt(((w0 * w0 + x0 * x0) + y0 * y0) + z0 * z0);
-  const double w = w0 / G.qn, qx = x0 / G.qn, qy = y0 / G.qn, qz = z0 / G.qn;
+  const T w = w0 / G.qn, qx = x0 / G.qn, qy = y0 / G.qn, qz = z0 / G.qn;
   G.qw = w; G.qx = qx; G.qy = qy; G.qz = qz;
-  double* R = G.R;
-  R[0] = 1.0 - 2.0 * (qy * qy + qz * qz);
-  R[1] = 2.0 * (qx * qy - w * qz);
-  R[2] = 2.0 * (qx * qz + w * qy);
-  R[3] = 2.0 * (qx * qy + w * qz);
-  R[4] = 1.0 - 2.0 * (qx * qx + qz * qz);
-  R[5] = 2.0 * (qy * qz - w * qx);
-  R[6] = 2.0 * (qx * qz - w * qy);
-  R[7] = 2.0 * (qy * qz + w * qx);
-  R[8] = 1.0 - 2.0 * (qx * qx + qy * qy);
+  T* R = G.R;
+  R[0] = T(1.0) - T(2.0) * (qy * qy + qz * qz);
+  R[1] = T(2.0) * (qx * qy - w * qz);
+  R[2] = T(2.0) * (qx * qz + w * qy);
+  R[3] = T(2.0) * (qx * qy + w * qz);
+  R[4] = T(1.0) - T(2.0) * (qx * qx + qz * qz);
+  R[5] = T(2.0) * (qy * qz - w * qx);
+  R[6] = T(2.0) * (qx * qz - w * qy);
+  R[7] = T(2.0) * (qy * qz + w * qx);
+  R[8] = T(1.0) - T(2.0) * (qx * qx + qy * qy);
   G.s[0] = sp[0]; G.s[1] = sp[1]; G.s[2] = sp[2];
-  double M[9];
+  T M[9];
   for (int a = 0; a < 3; ++a)
     for (int k = 0; k < 3; ++k) M[a * 3 + k] = R[a * 3 + k] * G.s[k];
   auto sig = [&](int a, int b) {
@@ -203,26 +205,26 @@ __device__ __forceinline__ void geometry(const CamConst& cc, const float* mp, co
   G.Sig[3] = sig(1, 1); G.Sig[4] = sig(1, 2); G.Sig[5] = sig(2, 2);
   G.xr = G.tx / G.tz;
   G.yr = G.ty / G.tz;
-  double xc = G.xr, yc = G.yr;
+  T xc = G.xr, yc = G.yr;
   G.clampx = false;
   G.clampy = false;
-  if (cc.limx > 0.0) {
-    G.clampx = (G.xr < -cc.limx) || (G.xr > cc.limx);
-    G.clampy = (G.yr < -cc.limy) || (G.yr > cc.limy);
-    xc = fmin(fmax(G.xr, -cc.limx), cc.limx);
-    yc = fmin(fmax(G.yr, -cc.limy), cc.limy);
+  if (T(cc.limx) > T(0.0)) {
+    G.clampx = (G.xr < -T(cc.limx)) || (G.xr > T(cc.limx));
+    G.clampy = (G.yr < -T(cc.limy)) || (G.yr > T(cc.limy));
+    xc = fmin(fmax(G.xr, -T(cc.limx)), T(cc.limx));
+    yc = fmin(fmax(G.yr, -T(cc.limy)), T(cc.limy));
   }
-  G.j00 = cc.fx / G.tz;
-  G.j02 = (-cc.fx * xc) / G.tz;
-  G.j11 = cc.fy / G.tz;
-  G.j12 = (-cc.fy * yc) / G.tz;
+  G.j00 = T(cc.fx) / G.tz;
+  G.j02 = (-T(cc.fx) * xc) / G.tz;
+  G.j11 = T(cc.fy) / G.tz;
+  G.j12 = (-T(cc.fy) * yc) / G.tz;
   for (int k = 0; k < 3; ++k) {
-    G.Tm[k] = G.j00 * cc.R[0 * 3 + k] + G.j02 * cc.R[2 * 3 + k];
-    G.Tm[3 + k] = G.j11 * cc.R[1 * 3 + k] + G.j12 * cc.R[2 * 3 + k];
+    G.Tm[k] = G.j00 * T(cc.R[0 * 3 + k]) + G.j02 * T(cc.R[2 * 3 + k]);
+    G.Tm[3 + k] = G.j11 * T(cc.R[1 * 3 + k]) + G.j12 * T(cc.R[2 * 3 + k]);
   }
-  const double S[9] = {G.Sig[0], G.Sig[1], G.Sig[2], G.Sig[1], G.Sig[3], G.Sig[4],
+  const T S[9] = {G.Sig[0], G.Sig[1], G.Sig[2], G.Sig[1], G.Sig[3], G.Sig[4],
                        G.Sig[2], G.Sig[4], G.Sig[5]};
-  double U[6];
+  T U[6];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 3; ++b)
       U[a * 3 + b] = (G.Tm[a * 3 + 0] * S[0 * 3 + b] + G.Tm[a * 3 + 1] * S[1 * 3 + b]) +
@@ -230,13 +232,15 @@ __device__ __forceinline__ void geometry(const CamConst& cc, const float* mp, co
   auto c2 = [&](int a, int b) {
     return (U[a * 3 + 0] * G.Tm[b * 3 + 0] + U[a * 3 + 1] * G.Tm[b * 3 + 1]) + U[a * 3 + 2] * G.Tm[b * 3 + 2];
   };
-  G.a = c2(0, 0) + cc.dilation;
+  G.a = c2(0, 0) + T(cc.dilation);
   G.b = c2(0, 1);
-  G.c = c2(1, 1) + cc.dilation;
+  G.c = c2(1, 1) + T(cc.dilation);
   G.det = G.a * G.c - G.b * G.b;
-  G.u = cc.fx * G.xr + cc.cx;
-  G.v = cc.fy * G.yr + cc.cy;
+  G.u = T(cc.fx) * G.xr + T(cc.cx);
+  G.v = T(cc.fy) * G.yr + T(cc.cy);
 }
+
+using Geo = GeoT<double>;
 
 __device__ __forceinline__ bool all_finite(const float* p, int k) {
   bool ok = true;
@@ -346,15 +350,18 @@ struct ProjBwdArgs {
 
 template <int L, typename ShT>
 __global__ __launch_bounds__(256) void project_bwd_kernel(ProjBwdArgs a) {
+  // the chain rule in float32: the gradients need no float64 (the decisions
+  // that must match the forward exactly were taken there)
+  typedef float T;
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   constexpr int K = (L + 1) * (L + 1);
-  double gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gop = 0.0;
+  T gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gop = T(0.0);
   // dL/dsh[k][ch] = Y_k * gact[ch] (zero for a culled Gaussian), formed at the store
-  double Y[16], gact[3] = {0.0, 0.0, 0.0};
-  for (int k = 0; k < 16; ++k) Y[k] = 0.0;
-  double gu = 0.0, gv = 0.0;
-  auto put = [&](float* p, double val) {
+  T Y[16], gact[3] = {T(0.0), T(0.0), T(0.0)};
+  for (int k = 0; k < 16; ++k) Y[k] = T(0.0);
+  T gu = T(0.0), gv = T(0.0);
+  auto put = [&](float* p, T val) {
     if (a.accumulate) *p += (float)val; else *p = (float)val;
   };
   const bool active = a.count[i] > 0;
@@ -362,34 +369,34 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjBwdArgs a) {
     const CamConst& cc = a.cc;
     const float* mp = a.means + 3 * i;
     const float* g2 = a.grad2d + 12 * i;
-    const double gcol[3] = {g2[6], g2[7], g2[8]};
+    const T gcol[3] = {g2[6], g2[7], g2[8]};
     // colour first (the view direction does not need the geometry), so
     // that its registers are free before the geometry's
-    const double dx = (double)mp[0] - cc.campos[0];
-    const double dy = (double)mp[1] - cc.campos[1];
-    const double dz = (double)mp[2] - cc.campos[2];
-    const double dn = sqrt(((dx * dx + dy * dy) + dz * dz));
-    const double ux = dx / dn, uy = dy / dn, uz = dz / dn;
+    const T dx = (T)mp[0] - T(cc.campos[0]);
+    const T dy = (T)mp[1] - T(cc.campos[1]);
+    const T dz = (T)mp[2] - T(cc.campos[2]);
+    const T dn = sqrt(((dx * dx + dy * dy) + dz * dz));
+    const T ux = dx / dn, uy = dy / dn, uz = dz / dn;
     sh_basis<L>(ux, uy, uz, Y);
     float shr[3 * K];
     load_sh_row<L, ShT>(a.sh, i, shr);
     // the clamp at 0 passes the gradient of a channel whose raw value is >= 0
     for (int ch = 0; ch < 3; ++ch) {
-      double raw = 0.0;
-      for (int k = 0; k < K; ++k) raw += (double)shr[k * 3 + ch] * Y[k];
-      raw += 0.5;
-      gact[ch] = raw >= 0.0 ? gcol[ch] : 0.0;
+      T raw = T(0.0);
+      for (int k = 0; k < K; ++k) raw += (T)shr[k * 3 + ch] * Y[k];
+      raw += T(0.5);
+      gact[ch] = raw >= T(0.0) ? gcol[ch] : T(0.0);
     }
     // direction gradient of sum_ch gact_ch raw_ch: one basis derivative of
     // the channel-combined coefficients
-    double cf[16];
-    for (int k = 0; k < 16; ++k) cf[k] = 0.0;
+    T cf[16];
+    for (int k = 0; k < 16; ++k) cf[k] = T(0.0);
     for (int k = 0; k < K; ++k)
-      cf[k] = (gact[0] * (double)shr[k * 3] + gact[1] * (double)shr[k * 3 + 1]) + gact[2] * (double)shr[k * 3 + 2];
-    double gdx, gdy, gdz;
+      cf[k] = (gact[0] * (T)shr[k * 3] + gact[1] * (T)shr[k * 3 + 1]) + gact[2] * (T)shr[k * 3 + 2];
+    T gdx, gdy, gdz;
     sh_basis_grad<L>(ux, uy, uz, cf, gdx, gdy, gdz);
-    const double dd = ux * gdx + uy * gdy + uz * gdz;
-    const double idn = 1.0 / dn;
+    const T dd = ux * gdx + uy * gdy + uz * gdz;
+    const T idn = T(1.0) / dn;
     gm[0] += (gdx - ux * dd) * idn;
     gm[1] += (gdy - uy * dd) * idn;
     gm[2] += (gdz - uz * dd) * idn;
@@ -417,91 +424,91 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjBwdArgs a) {
     const float* g2 = a.grad2d + 12 * i;
     gu = g2[0];
     gv = g2[1];
-    const double gA = g2[2], gB = g2[3], gC = g2[4];
+    const T gA = g2[2], gB = g2[3], gC = g2[4];
     gop = g2[5];
-    Geo G;
-    geometry(cc, mp, sp, qp, G);
+    GeoT<T> G;
+    geometry<T>(cc, mp, sp, qp, G);
     // conic -> Sigma':  dL/dSigma' = -M GM M  with M the conic matrix and
     // GM the symmetric gradient (off-diagonal gB / 2)
-    const double idet = 1.0 / G.det;
-    const double A = G.c * idet, B = -G.b * idet, C = G.a * idet;
-    const double hB = 0.5 * gB;
-    const double P00 = gA * A + hB * B, P01 = gA * B + hB * C;
-    const double P10 = hB * A + gC * B, P11 = hB * B + gC * C;
-    const double S00 = -(A * P00 + B * P10);
-    const double S01 = -(A * P01 + B * P11);
-    const double S11 = -(B * P01 + C * P11);
-    const double GS[4] = {S00, S01, S01, S11};
+    const T idet = T(1.0) / G.det;
+    const T A = G.c * idet, B = -G.b * idet, C = G.a * idet;
+    const T hB = T(0.5) * gB;
+    const T P00 = gA * A + hB * B, P01 = gA * B + hB * C;
+    const T P10 = hB * A + gC * B, P11 = hB * B + gC * C;
+    const T S00 = -(A * P00 + B * P10);
+    const T S01 = -(A * P01 + B * P11);
+    const T S11 = -(B * P01 + C * P11);
+    const T GS[4] = {S00, S01, S01, S11};
     // Sigma' = Tm Sigma Tm^T:  dSigma = Tm^T GS Tm,  dTm = 2 GS Tm Sigma
-    const double* T = G.Tm;
-    const double Sg[9] = {G.Sig[0], G.Sig[1], G.Sig[2], G.Sig[1], G.Sig[3], G.Sig[4],
+    const T* Tg = G.Tm;
+    const T Sg[9] = {G.Sig[0], G.Sig[1], G.Sig[2], G.Sig[1], G.Sig[3], G.Sig[4],
                           G.Sig[2], G.Sig[4], G.Sig[5]};
-    double GT[6];   // GS Tm  (2x3)
+    T GT[6];   // GS Tm  (2x3)
     for (int r = 0; r < 2; ++r)
-      for (int k = 0; k < 3; ++k) GT[r * 3 + k] = GS[r * 2 + 0] * T[0 * 3 + k] + GS[r * 2 + 1] * T[1 * 3 + k];
-    double dSig[9];
+      for (int k = 0; k < 3; ++k) GT[r * 3 + k] = GS[r * 2 + 0] * Tg[0 * 3 + k] + GS[r * 2 + 1] * Tg[1 * 3 + k];
+    T dSig[9];
     for (int p = 0; p < 3; ++p)
-      for (int q = 0; q < 3; ++q) dSig[p * 3 + q] = T[0 * 3 + p] * GT[0 * 3 + q] + T[1 * 3 + p] * GT[1 * 3 + q];
-    double dT[6];
+      for (int q = 0; q < 3; ++q) dSig[p * 3 + q] = Tg[0 * 3 + p] * GT[0 * 3 + q] + Tg[1 * 3 + p] * GT[1 * 3 + q];
+    T dT[6];
     for (int r = 0; r < 2; ++r)
       for (int k = 0; k < 3; ++k)
-        dT[r * 3 + k] = 2.0 * (GT[r * 3 + 0] * Sg[0 * 3 + k] + GT[r * 3 + 1] * Sg[1 * 3 + k] +
+        dT[r * 3 + k] = T(2.0) * (GT[r * 3 + 0] * Sg[0 * 3 + k] + GT[r * 3 + 1] * Sg[1 * 3 + k] +
                                GT[r * 3 + 2] * Sg[2 * 3 + k]);
     // Tm = J W:  dJ = dT W^T
     auto dJ = [&](int r, int b) {
-      return dT[r * 3 + 0] * cc.R[b * 3 + 0] + dT[r * 3 + 1] * cc.R[b * 3 + 1] + dT[r * 3 + 2] * cc.R[b * 3 + 2];
+      return dT[r * 3 + 0] * T(cc.R[b * 3 + 0]) + dT[r * 3 + 1] * T(cc.R[b * 3 + 1]) + dT[r * 3 + 2] * T(cc.R[b * 3 + 2]);
     };
-    const double dj00 = dJ(0, 0), dj02 = dJ(0, 2), dj11 = dJ(1, 1), dj12 = dJ(1, 2);
-    const double itz = 1.0 / G.tz, itz2 = itz * itz, itz3 = itz2 * itz;
-    double gtx = 0.0, gty = 0.0, gtz = 0.0;
-    gtz += -cc.fx * itz2 * dj00 - cc.fy * itz2 * dj11;
+    const T dj00 = dJ(0, 0), dj02 = dJ(0, 2), dj11 = dJ(1, 1), dj12 = dJ(1, 2);
+    const T itz = T(1.0) / G.tz, itz2 = itz * itz, itz3 = itz2 * itz;
+    T gtx = T(0.0), gty = T(0.0), gtz = T(0.0);
+    gtz += -T(cc.fx) * itz2 * dj00 - T(cc.fy) * itz2 * dj11;
     if (!G.clampx) {
-      gtx += -cc.fx * itz2 * dj02;
-      gtz += 2.0 * cc.fx * G.tx * itz3 * dj02;
+      gtx += -T(cc.fx) * itz2 * dj02;
+      gtz += T(2.0) * T(cc.fx) * G.tx * itz3 * dj02;
     } else {
-      const double xc = fmin(fmax(G.xr, -cc.limx), cc.limx);
-      gtz += cc.fx * xc * itz2 * dj02;
+      const T xc = fmin(fmax(G.xr, -T(cc.limx)), T(cc.limx));
+      gtz += T(cc.fx) * xc * itz2 * dj02;
     }
     if (!G.clampy) {
-      gty += -cc.fy * itz2 * dj12;
-      gtz += 2.0 * cc.fy * G.ty * itz3 * dj12;
+      gty += -T(cc.fy) * itz2 * dj12;
+      gtz += T(2.0) * T(cc.fy) * G.ty * itz3 * dj12;
     } else {
-      const double yc = fmin(fmax(G.yr, -cc.limy), cc.limy);
-      gtz += cc.fy * yc * itz2 * dj12;
+      const T yc = fmin(fmax(G.yr, -T(cc.limy)), T(cc.limy));
+      gtz += T(cc.fy) * yc * itz2 * dj12;
     }
     // pixel position
-    gtx += cc.fx * itz * gu;
-    gtz += -cc.fx * G.tx * itz2 * gu;
-    gty += cc.fy * itz * gv;
-    gtz += -cc.fy * G.ty * itz2 * gv;
+    gtx += T(cc.fx) * itz * gu;
+    gtz += -T(cc.fx) * G.tx * itz2 * gu;
+    gty += T(cc.fy) * itz * gv;
+    gtz += -T(cc.fy) * G.ty * itz2 * gv;
     // depth image: d(depth)/d(tz) = 1
-    gtz += (double)g2[9];
+    gtz += (T)g2[9];
     // t = W mu + t_c
-    for (int k = 0; k < 3; ++k) gm[k] += cc.R[0 * 3 + k] * gtx + cc.R[1 * 3 + k] * gty + cc.R[2 * 3 + k] * gtz;
+    for (int k = 0; k < 3; ++k) gm[k] += T(cc.R[0 * 3 + k]) * gtx + T(cc.R[1 * 3 + k]) * gty + T(cc.R[2 * 3 + k]) * gtz;
     // Sigma = M M^T, M = R diag(s):  dM = 2 dSigma M
-    const double* R = G.R;
-    double M[9];
+    const T* R = G.R;
+    T M[9];
     for (int p = 0; p < 3; ++p)
       for (int k = 0; k < 3; ++k) M[p * 3 + k] = R[p * 3 + k] * G.s[k];
-    double dR[9];
+    T dR[9];
     for (int p = 0; p < 3; ++p)
       for (int k = 0; k < 3; ++k) {
-        const double dM = 2.0 * (dSig[p * 3 + 0] * M[0 * 3 + k] + dSig[p * 3 + 1] * M[1 * 3 + k] +
+        const T dM = T(2.0) * (dSig[p * 3 + 0] * M[0 * 3 + k] + dSig[p * 3 + 1] * M[1 * 3 + k] +
                                  dSig[p * 3 + 2] * M[2 * 3 + k]);
         dR[p * 3 + k] = dM * G.s[k];
         gs[k] += dM * R[p * 3 + k];
       }
     // rotation of the normalised quaternion
-    const double w = G.qw, x = G.qx, y = G.qy, z = G.qz;
-    const double gw = 2.0 * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
-    const double gx = 2.0 * (y * dR[1] + z * dR[2] + y * dR[3] - 2.0 * x * dR[4] - w * dR[5] + z * dR[6] +
-                             w * dR[7] - 2.0 * x * dR[8]);
-    const double gy = 2.0 * (-2.0 * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] +
-                             z * dR[7] - 2.0 * y * dR[8]);
-    const double gz = 2.0 * (-2.0 * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.0 * z * dR[4] +
+    const T w = G.qw, x = G.qx, y = G.qy, z = G.qz;
+    const T gw = T(2.0) * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+    const T gx = T(2.0) * (y * dR[1] + z * dR[2] + y * dR[3] - T(2.0) * x * dR[4] - w * dR[5] + z * dR[6] +
+                             w * dR[7] - T(2.0) * x * dR[8]);
+    const T gy = T(2.0) * (-T(2.0) * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] +
+                             z * dR[7] - T(2.0) * y * dR[8]);
+    const T gz = T(2.0) * (-T(2.0) * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - T(2.0) * z * dR[4] +
                              y * dR[5] + x * dR[6] + y * dR[7]);
-    const double dot = w * gw + x * gx + y * gy + z * gz;
-    const double iqn = 1.0 / G.qn;
+    const T dot = w * gw + x * gx + y * gy + z * gz;
+    const T iqn = T(1.0) / G.qn;
     gq[0] = (gw - w * dot) * iqn;
     gq[1] = (gx - x * dot) * iqn;
     gq[2] = (gy - y * dot) * iqn;
