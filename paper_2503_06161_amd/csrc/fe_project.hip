@@ -354,7 +354,7 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjBwdArgs a) {
   // that must match the forward exactly were taken there)
   typedef float T;
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
+  const bool valid = i < a.n;   // every lane stays to the wave's SH-gradient stores
   constexpr int K = (L + 1) * (L + 1);
   T gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gop = T(0.0);
   // dL/dsh[k][ch] = Y_k * gact[ch] (zero for a culled Gaussian), formed at the store
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjBwdArgs a) {
   auto put = [&](float* p, T val) {
     if (a.accumulate) *p += (float)val; else *p = (float)val;
   };
-  const bool active = a.count[i] > 0;
+  const bool active = valid && a.count[i] > 0;
   if (active) {
     const CamConst& cc = a.cc;
     const float* mp = a.means + 3 * i;
@@ -402,20 +402,49 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjBwdArgs a) {
     gm[2] += (gdz - uz * dd) * idn;
   }
   if constexpr (L == 3) {
-    float4* q = reinterpret_cast<float4*>(a.g_sh + i * K * 3);
+    // The wave's 48-float rows leave through LDS as contiguous float4 stores,
+    // half of the wave's Gaussians at a time (one row per lane would make
+    // every store instruction touch 64 separate 16-byte pieces)
+    static_assert(K * 3 == 48, "degree-3 rows");
+    __shared__ float4 s_gsh[4][32 * 13];                 // rows padded to 13 float4
+    const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
+    const int64_t w0 = i - lane;                         // the wave's first Gaussian
+    const int64_t nv = a.n - w0 < 64 ? a.n - w0 : 64;    // its Gaussians
     auto gsh = [&](int e) { return (float)(Y[e / 3] * gact[e % 3]); };
+    float4* base = reinterpret_cast<float4*>(a.g_sh) + w0 * 12;
 #pragma unroll
-    for (int v = 0; v < K * 3 / 4; ++v) {
-      float4 o = make_float4(gsh(4 * v), gsh(4 * v + 1), gsh(4 * v + 2), gsh(4 * v + 3));
-      if (a.accumulate) {
-        const float4 p = q[v];
-        o.x += p.x; o.y += p.y; o.z += p.z; o.w += p.w;
+    for (int hg = 0; hg < 2; ++hg) {
+      if ((lane >> 5) == hg) {
+#pragma unroll
+        for (int v = 0; v < 12; ++v)
+          s_gsh[wv][(lane & 31) * 13 + v] = make_float4(gsh(4 * v), gsh(4 * v + 1), gsh(4 * v + 2), gsh(4 * v + 3));
       }
-      q[v] = o;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const int e = c * 64 + lane, r = e / 12;
+        if (32 * hg + r < nv) {
+          float4 o = s_gsh[wv][r * 13 + e % 12];
+          float4* q = base + 32 * hg * 12 + e;
+          if (a.accumulate) {
+            const float4 p = *q;
+            o.x += p.x; o.y += p.y; o.z += p.z; o.w += p.w;
+          }
+          *q = o;
+        }
+      }
+      // the next half rewrites the rows only after every lane has read them
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   } else {
-    for (int k = 0; k < K * 3; ++k) put(a.g_sh + i * K * 3 + k, Y[k / 3] * gact[k % 3]);
+    if (valid)
+      for (int k = 0; k < K * 3; ++k) put(a.g_sh + i * K * 3 + k, Y[k / 3] * gact[k % 3]);
   }
+  if (!valid) return;
   if (active) {
     const CamConst& cc = a.cc;
     const float* mp = a.means + 3 * i;
