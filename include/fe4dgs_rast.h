@@ -97,8 +97,7 @@ typedef struct fe_config {
                                     contractions), 2 * tile_w * tile_h (two
                                     per pixel: walker waves beside matrix-core
                                     waves; matrix-core variant, BF16 features,
-                                    feat_dim <= 128 and at least as many
-                                    32-channel blocks as 64-pixel groups), or
+                                    feat_dim <= 128), or
                                     0 = the two-per-pixel kernels wherever
                                     they exist; other values are
                                     FE_ERR_UNSUPPORTED                         */

@@ -295,13 +295,10 @@ fe_status fe_validate(const fe_config* cfg, const fe_camera* cam, int64_t n) {
   if (th < 1 || (nt != 64 && nt != 128 && nt != 256)) return FE_ERR_UNSUPPORTED;
   // threads per tile: 0 (library choice), one per pixel, or two per pixel
   // where the wave-specialized kernels exist in both directions (matrix-core
-  // variant, BF16 features, D <= 128, at least as many 32-channel blocks as
-  // 64-pixel chunks)
+  // variant, BF16 features, D <= 128)
   if (cfg->threads_per_tile != 0 && cfg->threads_per_tile != nt) {
     if (cfg->threads_per_tile != 2 * nt) return FE_ERR_UNSUPPORTED;
-    const int D = cfg->feat_dim;
-    const int dp = D <= 32 ? 32 : D <= 64 ? 64 : D <= 128 ? 128 : 256;
-    if (cfg->variant == FE_VARIANT_VALU || cfg->feat_dtype != FE_BF16 || dp > 128 || dp / 32 < nt / 64)
+    if (cfg->variant == FE_VARIANT_VALU || cfg->feat_dtype != FE_BF16 || cfg->feat_dim > 128)
       return FE_ERR_UNSUPPORTED;
   }
   if (cfg->sh_degree < 0) return FE_ERR_INVALID_ARG;

@@ -1362,24 +1362,35 @@ hipError_t launch_bwd_nt(int nt, const BwdArgs& a, int tiles, bool ws, hipStream
   return hipGetLastError();
 }
 
+// Feature width of the instantiation a backward launch uses: the next of 32,
+// 64, 128, 256 at or above D.  The wave-specialized form needs a 32-channel
+// block per contractor wave (NT / 64 of them), so narrower features take the
+// instantiation with that many blocks; their extra channels are zero (staged
+// as zeros, never stored).
+int bwd_width(int D, int nt, bool ws) {
+  int dp = D <= 32 ? 32 : D <= 64 ? 64 : D <= 128 ? 128 : 256;
+  if (ws && dp < 32 * (nt / 64)) dp = 32 * (nt / 64);
+  return dp;
+}
+
 template <typename FT>
 hipError_t dispatch_bwd(int D, int nt, const BwdArgs& a, int tiles, bool ws, hipStream_t s) {
-  if (D <= 32) return launch_bwd_nt<32, FT>(nt, a, tiles, ws, s);
-  if (D <= 64) return launch_bwd_nt<64, FT>(nt, a, tiles, ws, s);
-  if (D <= 128) return launch_bwd_nt<128, FT>(nt, a, tiles, ws, s);
-  return launch_bwd_nt<256, FT>(nt, a, tiles, ws, s);
+  switch (bwd_width(D, nt, ws)) {
+    case 32: return launch_bwd_nt<32, FT>(nt, a, tiles, ws, s);
+    case 64: return launch_bwd_nt<64, FT>(nt, a, tiles, ws, s);
+    case 128: return launch_bwd_nt<128, FT>(nt, a, tiles, ws, s);
+    default: return launch_bwd_nt<256, FT>(nt, a, tiles, ws, s);
+  }
 }
 
 }  // namespace
 
-// Wave-specialized backward (2 NT threads per tile) where its kernel exists
-// (D <= 128 and at least as many 32-channel blocks as 64-pixel chunks) and
-// threads_per_tile asks for it or leaves the choice to the library.
+// Wave-specialized backward (2 NT threads per tile) for D <= 128 (narrower
+// features use a wider instantiation, see bwd_width) where threads_per_tile
+// asks for it or leaves the choice to the library.
 bool backward_wave_specialized(const fe_config* cfg) {
-  const int nt = cfg->tile_w * cfg->tile_h, D = cfg->feat_dim;
-  const int dp = D <= 32 ? 32 : D <= 64 ? 64 : D <= 128 ? 128 : 256;
-  const bool available = dp <= 128 && dp / 32 >= nt / 64;
-  return available && cfg->threads_per_tile != nt;
+  const int nt = cfg->tile_w * cfg->tile_h;
+  return cfg->feat_dim <= 128 && nt <= 256 && cfg->threads_per_tile != nt;
 }
 
 // Rows are padded to whole 128-byte lines: each 32-channel block of dF and
@@ -1470,9 +1481,10 @@ static int bwd_grid_nt(int nt, bool ws) {
 }
 
 int composite_bwd_persistent_grid(const fe_config* cfg) {
-  const int nt = cfg->tile_w * cfg->tile_h, D = cfg->feat_dim;
+  const int nt = cfg->tile_w * cfg->tile_h;
   const bool ws = backward_wave_specialized(cfg);
-  return D <= 32 ? bwd_grid_nt<32>(nt, ws) : D <= 64 ? bwd_grid_nt<64>(nt, ws) : bwd_grid_nt<128>(nt, ws);
+  const int dp = bwd_width(cfg->feat_dim, nt, ws);
+  return dp <= 32 ? bwd_grid_nt<32>(nt, ws) : dp <= 64 ? bwd_grid_nt<64>(nt, ws) : bwd_grid_nt<128>(nt, ws);
 }
 
 template <int DP, int NT>
@@ -1500,12 +1512,13 @@ static hipError_t bwd_persistent_nt(int nt, const BwdArgs* r, const TileQueue& q
 hipError_t launch_composite_bwd_persistent(const fe_config* cfg, const void* records, const TileQueue& q,
                                            int grid, hipStream_t s) {
   if (grid < 1) return hipErrorInvalidValue;
-  const int nt = cfg->tile_w * cfg->tile_h, D = cfg->feat_dim;
+  const int nt = cfg->tile_w * cfg->tile_h;
   const bool ws = backward_wave_specialized(cfg);
   const BwdArgs* r = static_cast<const BwdArgs*>(records);
-  return D <= 32 ? bwd_persistent_nt<32>(nt, r, q, grid, ws, s)
-                 : D <= 64 ? bwd_persistent_nt<64>(nt, r, q, grid, ws, s)
-                           : bwd_persistent_nt<128>(nt, r, q, grid, ws, s);
+  const int dp = bwd_width(cfg->feat_dim, nt, ws);
+  return dp <= 32 ? bwd_persistent_nt<32>(nt, r, q, grid, ws, s)
+                  : dp <= 64 ? bwd_persistent_nt<64>(nt, r, q, grid, ws, s)
+                             : bwd_persistent_nt<128>(nt, r, q, grid, ws, s);
 }
 
 hipError_t launch_reduce_rows(const fe_config* cfg, const StateView& v, const uint32_t* rowidx,

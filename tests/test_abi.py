@@ -117,7 +117,7 @@ def test_threads_per_tile_choices():
     assert v(feat_dim=128, threads_per_tile=256, **bf) == rast.FE_OK
     assert v(feat_dim=128, threads_per_tile=512, **bf) == rast.FE_OK
     assert v(feat_dim=64, tile_w=16, tile_h=8, threads_per_tile=256, **bf) == rast.FE_OK
-    assert v(feat_dim=32, threads_per_tile=512, **bf) == rast.FE_ERR_UNSUPPORTED      # 1 block < 4 pixel groups
+    assert v(feat_dim=32, threads_per_tile=512, **bf) == rast.FE_OK   # narrow features: the 128-channel kernel
     assert v(feat_dim=200, threads_per_tile=512, **bf) == rast.FE_ERR_UNSUPPORTED     # D > 128
     assert v(feat_dim=128, threads_per_tile=512, variant=rast.FE_VARIANT_MFMA) == rast.FE_ERR_UNSUPPORTED  # FP32
     assert v(feat_dim=128, threads_per_tile=512, sh_dtype="bf16", feat_dtype="bf16",

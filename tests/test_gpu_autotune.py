@@ -30,7 +30,7 @@ def test_candidates_agree_and_choice_is_cached(tmp_path, monkeypatch):
     # both thread counts are offered where the two-per-pixel kernels exist
     assert (8, 8, rast.FE_VARIANT_MFMA, 64) in cands and (8, 8, rast.FE_VARIANT_MFMA, 128) in cands
     assert (16, 16, rast.FE_VARIANT_MFMA, 256) in cands and (16, 16, rast.FE_VARIANT_MFMA, 0) in cands
-    assert (16, 16, rast.FE_VARIANT_MFMA, 512) not in cands      # D = 32: one channel block, four pixel groups
+    assert (16, 16, rast.FE_VARIANT_MFMA, 512) in cands          # D = 32 through the 128-channel kernel
     assert (16, 16, rast.FE_VARIANT_VALU, 512) not in cands and (16, 16, rast.FE_VARIANT_VALU, 256) in cands
     for tw, th, v, tpt in cands:
         s2 = rast.Settings(**{**st.__dict__, "tile_w": tw, "tile_h": th, "variant": v, "threads_per_tile": tpt})
