@@ -114,7 +114,7 @@ CamConst make_cam_const(const fe_camera* cam, const fe_config* cfg) {
 
 static fe_status hip_status(hipError_t e) { return e == hipSuccess ? FE_OK : FE_ERR_HIP; }
 
-// backward scratch: grad2d [n][12] | row_base [tiles] | rowidx [cap] | rows [row_cap][RS]
+// backward scratch: grad2d [n][12] | row_base [tiles + 1], tile order [tiles] | rowidx [cap] | rows [row_cap][RS]
 struct BwdScratch {
   size_t grad2d, row_base, rowidx, rows, total;
   int64_t row_cap;
@@ -134,7 +134,7 @@ static bool bwd_scratch_layout(const fe_config* cfg, const fe_camera* cam, int64
   b->row_base = b->rowidx = b->rows = o;
   if (cfg->variant != FE_VARIANT_VALU) {
     b->row_cap = cfg->row_capacity > 0 ? cfg->row_capacity : cfg->key_capacity;
-    b->row_base = take(sizeof(uint32_t) * ((size_t)L.tiles + 1));
+    b->row_base = take(sizeof(uint32_t) * (2 * (size_t)L.tiles + 1));   // row offsets, then the launch order
     b->rowidx = take(sizeof(uint32_t) * (((size_t)L.cap + 3) & ~(size_t)3));   // whole 16-byte groups
     b->rows = take(sizeof(float) * (size_t)backward_row_stride(cfg->feat_dim) * (size_t)b->row_cap);
   }

@@ -53,6 +53,7 @@ struct BwdArgs {
   const float* d_depth;      // [H][W] or null (no depth gradient)
   const uint32_t* tile_maxlast;
   const uint32_t* row_base;
+  const uint32_t* order;        // [tiles] launch order of the per-frame kernels (longest walks first)
   float* rows;
   int64_t row_cap;
   uint32_t* rowidx;          // [cap] 1 + row of each walked pair, by emit position (0: not walked)
@@ -1171,14 +1172,20 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
   }
 }
 
+// Tiles in the backward preparation's order (longest walks first), dealt to
+// the XCDs in runs as everywhere else.
+__device__ __forceinline__ int bwd_tile(const BwdArgs& a) {
+  return (int)__builtin_amdgcn_readfirstlane(a.order[xcd_tile((int)blockIdx.x, (int)gridDim.x)]);
+}
+
 template <int DP, typename FT, int NT>
 __global__ __launch_bounds__(NT) void composite_bwd_mfma_kernel(BwdArgs a) {
-  bwd_mfma_tile<DP, FT, NT, true>(a, xcd_tile((int)blockIdx.x, (int)gridDim.x));
+  bwd_mfma_tile<DP, FT, NT, true>(a, bwd_tile(a));
 }
 
 template <int DP, typename FT, int NT>
 __global__ __launch_bounds__(2 * NT) void composite_bwd_ws_kernel(BwdArgs a) {
-  bwd_ws_tile<DP, FT, NT, true>(a, xcd_tile((int)blockIdx.x, (int)gridDim.x));
+  bwd_ws_tile<DP, FT, NT, true>(a, bwd_tile(a));
 }
 
 // The wave-specialized form applies where contractor waves own whole channel
@@ -1417,6 +1424,7 @@ static BwdArgs make_bwd_args(const fe_config* cfg, const fe_camera* cam, const f
   a.d_depth = d_depth;
   a.tile_maxlast = v.tile_maxlast;
   a.row_base = row_base;
+  a.order = row_base + v.tiles + 1;   // written by the backward preparation
   a.rows = rows;
   a.row_cap = row_cap;
   a.rowidx = rowidx;

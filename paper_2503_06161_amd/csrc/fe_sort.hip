@@ -89,7 +89,10 @@ __device__ __forceinline__ void scan_small(const uint32_t* in, uint32_t* out, in
 }
 
 // Backward preparation in one launch: workgroup 0 clears the backward's
-// status word and scans the per-tile walk lengths into row offsets; the others
+// status word, scans the per-tile walk lengths into row offsets and orders
+// the tiles for the compositing backward by walk length, longest first (at
+// row_base + tiles + 1; classes of 8 positions, the top class open-ended),
+// so that the longest walks start in the first round; the others
 // clear the row index of every key of the frame (min(report keys, cap) words,
 // 16 bytes per store; nothing reads the words past the key count).
 __global__ __launch_bounds__(kScanWg) void backward_prep_kernel(const uint32_t* walk, uint32_t* row_base, int64_t tiles,
@@ -98,6 +101,24 @@ __global__ __launch_bounds__(kScanWg) void backward_prep_kernel(const uint32_t* 
   if (blockIdx.x == 0) {
     if (threadIdx.x == 0) report[kRepBwdStatus] = 0ull;
     scan_small(walk, row_base, tiles);
+    constexpr int kCls = 128;
+    __shared__ uint32_t s_cls[kCls];
+    auto wclass = [](uint32_t w) { return w >> 3 < (uint32_t)(kCls - 1) ? (int)(w >> 3) : kCls - 1; };
+    if (threadIdx.x < kCls) s_cls[threadIdx.x] = 0u;
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < tiles; t += kScanWg) atomicAdd(&s_cls[wclass(walk[t])], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t acc = 0;
+      for (int c = kCls - 1; c >= 0; --c) {
+        const uint32_t n = s_cls[c];
+        s_cls[c] = acc;
+        acc += n;
+      }
+    }
+    __syncthreads();
+    uint32_t* order = row_base + tiles + 1;
+    for (int64_t t = threadIdx.x; t < tiles; t += kScanWg) order[atomicAdd(&s_cls[wclass(walk[t])], 1u)] = (uint32_t)t;
     return;
   }
   const unsigned long long k = report[kRepKeys];
