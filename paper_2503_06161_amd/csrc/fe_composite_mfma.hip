@@ -53,6 +53,7 @@ struct MfmaArgs {
   int32_t* out_n;
   float* out_depth;              // [H][W] or null
   uint32_t* tile_maxlast;        // [tiles] largest n_contrib of the tile
+  const uint32_t* order;         // [tiles] tiles by list length, longest first (null: tile order)
   unsigned long long* report;
   float bg[3];
   int32_t W, H, tile_w, tiles_x;
@@ -61,6 +62,14 @@ struct MfmaArgs {
 };
 
 __device__ __forceinline__ float bf16_to_f32(__bf16 h) { return (float)h; }
+
+// The tile of a per-frame launch's workgroup: the binning's order (longest
+// lists first, so that they do not start in the last round), dealt to the
+// XCDs in runs as everywhere else.
+__device__ __forceinline__ int fwd_tile(const MfmaArgs& a) {
+  const int b = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+  return a.order ? (int)__builtin_amdgcn_readfirstlane(a.order[b]) : b;
+}
 
 // float32 -> three bf16 parts, hi + mid + lo == x exactly
 __device__ __forceinline__ void split3(float x, __bf16& hi, __bf16& mid, __bf16& lo) {
@@ -135,7 +144,7 @@ void composite_fwd_mfma_kernel(MfmaArgs a) {
   __shared__ __attribute__((aligned(16))) __bf16 s_f[NPL][kNB][FROW];
   __shared__ int s_maxlast;
 
-  const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+  const int tile = fwd_tile(a);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int tile_h = NT / a.tile_w;
@@ -654,7 +663,7 @@ __device__ __forceinline__ void fwd_ws_tile(const MfmaArgs& a, const int tile) {
 
 template <int DP, int NT>
 __global__ __launch_bounds__(2 * NT) void composite_fwd_ws_kernel(MfmaArgs a) {
-  fwd_ws_tile<DP, NT>(a, xcd_tile((int)blockIdx.x, (int)gridDim.x));
+  fwd_ws_tile<DP, NT>(a, fwd_tile(a));
 }
 
 // Persistent form over many frames: each workgroup takes (frame, tile) items
@@ -729,6 +738,7 @@ static MfmaArgs make_args(const fe_config* cfg, const fe_camera* cam, const fe_g
   a.out_n = out->n_contrib;
   a.out_depth = out->depth;
   a.tile_maxlast = v.tile_maxlast;
+  a.order = v.n > 0 ? v.tile_order : nullptr;   // the binning writes it whenever there are Gaussians
   a.report = v.report;
   for (int k = 0; k < 3; ++k) a.bg[k] = cfg->bg_rgb[k];
   a.W = cam->width;

@@ -299,7 +299,12 @@ __global__ __launch_bounds__(kBinOffThreads) void bin_offsets_kernel(BinArgs a) 
     a.report[kRepKeys] = tot64;
     if (tot64 > (unsigned long long)a.cap) a.report[kRepStatus] = (unsigned long long)FE_ERR_KEY_OVERFLOW;
   }
-  if (tot64 > (unsigned long long)a.cap) return;   // ranges stay empty; nothing is placed
+  if (tot64 > (unsigned long long)a.cap) {
+    // ranges stay empty and nothing is placed; the compositing still takes
+    // its tiles through the order
+    for (int t = threadIdx.x; t < a.tiles; t += kBinOffThreads) a.tile_order[t] = (uint32_t)t;
+    return;
+  }
   // tile ranges; the tile counts become the tiles' first free slots.  The
   // lengths are also counted by floor(log2) class (class 0: empty) for the
   // launch order of the per-tile sort
