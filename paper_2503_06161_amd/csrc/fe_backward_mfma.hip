@@ -896,6 +896,35 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
                                                                __builtin_bit_cast(bf16x8, bv), s1[pb], 0, 0, 0);
             }
           }
+          // pairs at list positions >= min(last, pos0 + nb) are not walked for this pixel
+          const int lim = min(last, pos0 + nb) - pos0;
+          constexpr int GR = WS_GR;
+          // alpha, 1 / (1 - alpha) and G of the GR pairs of group gi, independent
+          // of each other; a pair that is not walked gets alpha 0 (and G 0),
+          // which leaves the chain below unchanged without per-pair selects
+          auto alpha_group = [&](int gi, float (&al)[GR], float (&inv)[GR], float (&gx)[GR]) {
+#pragma unroll
+            for (int u = 0; u < GR; ++u) {
+              const int i = gi * GR + u;
+              const float2 m = s_xy[b3][i];
+              const float4 co = s_cs[b3][i];
+              const float dx = fpx - m.x, dy = fpy - m.y;
+              const float qs = scaled_q(co, dx, dy);
+              const bool inb = in_box(pp, s_box[b2][i]);
+              const float G = __builtin_amdgcn_exp2f(qs);
+              const float opG = co.w * G;
+              const float alpha = fminf(kAlphaMax, opG);
+              const bool ct = (i < lim) & inb & (qs >= s_tg[b3][i]);
+              al[u] = ct ? alpha : 0.f;
+              inv[u] = __builtin_amdgcn_rcpf(1.0f - al[u]);
+              gx[u] = (ct & (opG <= kAlphaMax)) ? G : 0.f;
+            }
+          };
+          // the first group walked (the batch's last GR pairs) is evaluated while
+          // the matrix cores finish GEMM1: it does not need S
+          constexpr int kFirst = 2 * (16 / GR) - 1;
+          float al0[GR], inv0[GR], gx0[GR];
+          alpha_group(kFirst, al0, inv0, gx0);
           float S[kNB];
 #pragma unroll
           for (int v = 0; v < 16; ++v) {
@@ -904,33 +933,21 @@ __device__ __forceinline__ void bwd_ws_tile(const BwdArgs& a, const int tile) {
             S[8 * (v >> 2) + (v & 3)] = __uint_as_float(r[0]);
             S[8 * (v >> 2) + 4 + (v & 3)] = __uint_as_float(r[1]);
           }
-          // pairs at list positions >= min(last, pos0 + nb) are not walked for this pixel
-          const int lim = min(last, pos0 + nb) - pos0;
-          constexpr int GR = WS_GR;
 #pragma unroll
           for (int h = 1; h >= 0; --h) {
 #pragma unroll
             for (int gq = 16 / GR - 1; gq >= 0; --gq) {
               const int gi = (16 / GR) * h + gq;
-              // alpha, 1 / (1 - alpha) and G of GR pairs, independent of each other;
-              // a pair that is not walked gets alpha 0 (and G 0), which leaves the
-              // chain below unchanged without per-pair selects
               float al[GR], inv[GR], gx[GR];
+              if (gi == kFirst) {
 #pragma unroll
-              for (int u = 0; u < GR; ++u) {
-                const int i = gi * GR + u;
-                const float2 m = s_xy[b3][i];
-                const float4 co = s_cs[b3][i];
-                const float dx = fpx - m.x, dy = fpy - m.y;
-                const float qs = scaled_q(co, dx, dy);
-                const bool inb = in_box(pp, s_box[b2][i]);
-                const float G = __builtin_amdgcn_exp2f(qs);
-                const float opG = co.w * G;
-                const float alpha = fminf(kAlphaMax, opG);
-                const bool ct = (i < lim) & inb & (qs >= s_tg[b3][i]);
-                al[u] = ct ? alpha : 0.f;
-                inv[u] = __builtin_amdgcn_rcpf(1.0f - al[u]);
-                gx[u] = (ct & (opG <= kAlphaMax)) ? G : 0.f;
+                for (int u = 0; u < GR; ++u) {
+                  al[u] = al0[u];
+                  inv[u] = inv0[u];
+                  gx[u] = gx0[u];
+                }
+              } else {
+                alpha_group(gi, al, inv, gx);
               }
               // back-to-front recovery of T and the running colour/feature sum
               float wg[GR];
