@@ -33,8 +33,12 @@
  *     tz; background 0), final_T [H][W], n_contrib [H][W] (1 + list position
  *     of the last blended Gaussian in the pixel's tile list).
  *   - BF16 storage is accepted for sh and feat only (round-to-nearest-even
- *     bfloat16, passed as uint16 bit patterns); all arithmetic and every
- *     gradient are float32 (projection geometry in float64).
+ *     bfloat16, passed as uint16 bit patterns).  Blending, transmittance and
+ *     every accumulation are float32; the matrix-core contractions use exact
+ *     bf16 parts in the forward and two-part splits (about 16 significant
+ *     bits per product) in the backward; the forward projection geometry is
+ *     float64 (it decides keys and boxes), its backward float32; every
+ *     gradient is float32.
  *
  * Ownership and asynchrony
  *   - every pointer in the structs below is DEVICE memory owned by the caller;
