@@ -215,7 +215,7 @@ static BwdBuffers bwd_buffers(const fe_config* cfg, const fe_camera* cam, int64_
 
 static fe_status backward_pre(const Layout& L, const void* state, const BwdBuffers& b, hipStream_t s) {
   StateView v = make_view(L, const_cast<void*>(state));
-  return hip_status(launch_backward_prep(v.tile_maxlast, b.row_base, v.tiles, b.rowidx, v.report, L.cap, s));
+  return hip_status(launch_backward_prep(v.tile_maxlast, b.row_base, v.tiles, L.tiles_x, b.rowidx, v.report, L.cap, s));
 }
 
 static fe_status backward_post(const fe_config* cfg, const fe_camera* cam, const fe_gaussians* g, const Layout& L,

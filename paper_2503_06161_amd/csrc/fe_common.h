@@ -128,7 +128,7 @@ hipError_t launch_zero_u32(uint32_t* p, size_t count, hipStream_t s);
 // row offsets per tile (exclusive scan of the walk lengths) and cleared row
 // indices for the frame's keys; rowidx 16-byte aligned with room for cap
 // rounded up to 4 words
-hipError_t launch_backward_prep(const uint32_t* walk, uint32_t* row_base, int64_t tiles, uint32_t* rowidx,
+hipError_t launch_backward_prep(const uint32_t* walk, uint32_t* row_base, int64_t tiles, int64_t tiles_x, uint32_t* rowidx,
                                 unsigned long long* report, int64_t cap, hipStream_t s);
 hipError_t launch_project_fwd(const CamConst& cc, const fe_config* cfg, const fe_gaussians* g,
                               const StateView& v, hipStream_t s);

@@ -91,11 +91,12 @@ __device__ __forceinline__ void scan_small(const uint32_t* in, uint32_t* out, in
 // Backward preparation in one launch: workgroup 0 clears the backward's
 // status word, scans the per-tile walk lengths into row offsets and orders
 // the tiles for the compositing backward by walk length, longest first (at
-// row_base + tiles + 1; classes of 8 positions, the top class open-ended),
-// so that the longest walks start in the first round; the others
+// row_base + tiles + 1; classes by the two leading bits of the length, so a
+// class spans a factor of at most sqrt 2, and Z order inside a class), so
+// that the longest walks start in the first round; the others
 // clear the row index of every key of the frame (min(report keys, cap) words,
 // 16 bytes per store; nothing reads the words past the key count).
-__global__ __launch_bounds__(kScanWg) void backward_prep_kernel(const uint32_t* walk, uint32_t* row_base, int64_t tiles,
+__global__ __launch_bounds__(kScanWg) void backward_prep_kernel(const uint32_t* walk, uint32_t* row_base, int64_t tiles, int64_t tiles_x,
                                                                 uint4* rowidx, unsigned long long* report,
                                                                 int64_t cap) {
   if (blockIdx.x == 0) {
@@ -103,7 +104,11 @@ __global__ __launch_bounds__(kScanWg) void backward_prep_kernel(const uint32_t* 
     scan_small(walk, row_base, tiles);
     constexpr int kCls = 128;
     __shared__ uint32_t s_cls[kCls];
-    auto wclass = [](uint32_t w) { return w >> 3 < (uint32_t)(kCls - 1) ? (int)(w >> 3) : kCls - 1; };
+    auto wclass = [](uint32_t w) {
+      if (w < 4u) return (int)w;
+      const int lz = 31 - __builtin_clz(w);
+      return 2 * lz + (int)((w >> (lz - 1)) & 1u);
+    };
     if (threadIdx.x < kCls) s_cls[threadIdx.x] = 0u;
     __syncthreads();
     for (int64_t t = threadIdx.x; t < tiles; t += kScanWg) atomicAdd(&s_cls[wclass(walk[t])], 1u);
@@ -118,7 +123,29 @@ __global__ __launch_bounds__(kScanWg) void backward_prep_kernel(const uint32_t* 
     }
     __syncthreads();
     uint32_t* order = row_base + tiles + 1;
-    for (int64_t t = threadIdx.x; t < tiles; t += kScanWg) order[atomicAdd(&s_cls[wclass(walk[t])], 1u)] = (uint32_t)t;
+    // inside a class the tiles are taken in Z order, so that the runs of
+    // consecutive positions one XCD receives are compact blocks of tiles
+    // that share Gaussians in that XCD's L2
+    int lg = 0;
+    const int64_t tiles_y = tiles_x > 0 ? (tiles + tiles_x - 1) / tiles_x : tiles;
+    while (((int64_t)1 << lg) < tiles_x || ((int64_t)1 << lg) < tiles_y) ++lg;
+    const int64_t zn = (int64_t)1 << (2 * lg);
+    if (tiles_x > 0 && lg <= 15 && zn <= 8 * tiles) {
+      auto unz = [](uint32_t v) {
+        v &= 0x55555555u;
+        v = (v | (v >> 1)) & 0x33333333u;
+        v = (v | (v >> 2)) & 0x0f0f0f0fu;
+        v = (v | (v >> 4)) & 0x00ff00ffu;
+        return (int64_t)((v | (v >> 8)) & 0x0000ffffu);
+      };
+      for (int64_t z = threadIdx.x; z < zn; z += kScanWg) {
+        const int64_t x = unz((uint32_t)z), y = unz((uint32_t)z >> 1);
+        const int64_t t = y * tiles_x + x;
+        if (x < tiles_x && t < tiles) order[atomicAdd(&s_cls[wclass(walk[t])], 1u)] = (uint32_t)t;
+      }
+    } else {
+      for (int64_t t = threadIdx.x; t < tiles; t += kScanWg) order[atomicAdd(&s_cls[wclass(walk[t])], 1u)] = (uint32_t)t;
+    }
     return;
   }
   const unsigned long long k = report[kRepKeys];
@@ -739,14 +766,14 @@ __global__ __launch_bounds__(1024) void build_tile_queue_kernel(TileQueueBuild b
 
 }  // namespace
 
-hipError_t launch_backward_prep(const uint32_t* walk, uint32_t* row_base, int64_t tiles, uint32_t* rowidx,
+hipError_t launch_backward_prep(const uint32_t* walk, uint32_t* row_base, int64_t tiles, int64_t tiles_x, uint32_t* rowidx,
                                 unsigned long long* report, int64_t cap, hipStream_t s) {
   // clearing workgroups: one 16-byte group per thread over ceil(cap / 4)
   // groups, at least one whenever there is any key slot
   const size_t groups = ((size_t)(cap > 0 ? cap : 0) + 3) / 4;
   size_t zb = (groups + kScanWg - 1) / kScanWg;
   if (zb > 512) zb = 512;
-  hipLaunchKernelGGL(backward_prep_kernel, dim3((unsigned)(1 + zb)), dim3(kScanWg), 0, s, walk, row_base, tiles,
+  hipLaunchKernelGGL(backward_prep_kernel, dim3((unsigned)(1 + zb)), dim3(kScanWg), 0, s, walk, row_base, tiles, tiles_x,
                      reinterpret_cast<uint4*>(rowidx), report, cap);
   return hipGetLastError();
 }
