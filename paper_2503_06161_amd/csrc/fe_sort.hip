@@ -333,12 +333,17 @@ __global__ __launch_bounds__(kBinOffThreads) void bin_offsets_kernel(BinArgs a) 
     return;
   }
   // tile ranges; the tile counts become the tiles' first free slots.  The
-  // lengths are also counted by floor(log2) class (class 0: empty) for the
-  // launch order of the per-tile sort
-  __shared__ uint32_t s_cls[33];
-  if (threadIdx.x < 33) s_cls[threadIdx.x] = 0u;
+  // lengths are also counted by class (class 0: empty; then the two leading
+  // bits of the length, a factor of at most sqrt 2 per class) for the launch
+  // order of the per-tile sort and the forward compositing
+  __shared__ uint32_t s_cls[65];
+  if (threadIdx.x < 65) s_cls[threadIdx.x] = 0u;
   __syncthreads();
-  auto len_class = [](uint32_t c) { return c ? 32 - __clz((int)c) : 0; };
+  auto len_class = [](uint32_t c) {
+    if (c == 0u) return 0;
+    const int lz = 31 - __builtin_clz(c);
+    return 1 + 2 * lz + (lz > 0 ? (int)((c >> (lz - 1)) & 1u) : 0);
+  };
   constexpr int per = 4;
   uint32_t carry = 0;
   for (int base = 0; base < a.tiles; base += kBinOffThreads * per) {
@@ -366,7 +371,7 @@ __global__ __launch_bounds__(kBinOffThreads) void bin_offsets_kernel(BinArgs a) 
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t acc = 0;
-    for (int b = 32; b >= 0; --b) {
+    for (int b = 64; b >= 0; --b) {
       const uint32_t cb = s_cls[b];
       s_cls[b] = acc;
       acc += cb;
