@@ -133,9 +133,10 @@ def test_tiny_key_capacity_with_dirty_scratch(cap_extra):
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
-@pytest.mark.parametrize("wh", [(5, 3), (16, 16), (21, 9), (70, 33)])
+@pytest.mark.parametrize("wh", [(5, 3), (16, 16), (21, 9), (70, 33), (200, 8)])
 def test_ragged_and_tiny_images(wh, variant):
-    # images smaller than one tile, exactly one tile, and ragged tails
+    # images smaller than one tile, exactly one tile, ragged tails, and a
+    # strip one tile high (the backward's tile order then skips its Z order)
     w, h = wh
     say("image", wh, "variant", variant)
     sc = _small(n=400, seed=11, grads=True)
